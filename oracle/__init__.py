@@ -1,0 +1,130 @@
+"""FSZ oracle: ctypes front end of the plain C reference compressor.
+
+TEST INFRASTRUCTURE ONLY.  Imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg; the product package never imports it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_NONFINITE = 2
+ERR_EB_TOO_SMALL = 3
+ERR_CAPACITY = 4
+ERR_CORRUPT = 5
+ERR_SIZE_MISMATCH = 6
+ERR_EB_TOO_LARGE = 8
+
+ABS = 0
+REL = 1
+
+_lib = None
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"oracle {what} failed with status {status}")
+        self.status = status
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        lib = ctypes.CDLL(LIB)
+        u64 = ctypes.c_uint64
+        p = ctypes.c_void_p
+        lib.fszo_bound.argtypes = [u64]
+        lib.fszo_bound.restype = u64
+        lib.fszo_resolve.argtypes = [p, u64, ctypes.c_int, ctypes.c_double, p, p, p]
+        lib.fszo_resolve.restype = ctypes.c_int
+        lib.fszo_compress.argtypes = [p, u64, ctypes.c_int, ctypes.c_double, p, u64, p]
+        lib.fszo_compress.restype = ctypes.c_int
+        lib.fszo_decompress.argtypes = [p, u64, p, u64]
+        lib.fszo_decompress.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1))
+
+
+def bound(n: int) -> int:
+    return int(_load().fszo_bound(n))
+
+
+def resolve(x, mode: int, value: float):
+    """Return (status, E, inv, flags)."""
+    x = _f32(x)
+    E = ctypes.c_float()
+    inv = ctypes.c_float()
+    flags = ctypes.c_uint32()
+    st = _load().fszo_resolve(x.ctypes.data, x.size, mode, value, ctypes.byref(E),
+                              ctypes.byref(inv), ctypes.byref(flags))
+    return st, E.value, inv.value, flags.value
+
+
+def compress_status(x, mode: int, value: float, capacity=None):
+    """Return (status, stream bytes or None)."""
+    x = _f32(x)
+    cap = bound(x.size) if capacity is None else capacity
+    out = np.zeros(max(cap, 1), dtype=np.uint8)
+    size = ctypes.c_uint64()
+    st = _load().fszo_compress(x.ctypes.data, x.size, mode, value, out.ctypes.data, cap,
+                               ctypes.byref(size))
+    if st != OK:
+        return st, None
+    return st, out[: size.value].tobytes()
+
+
+def compress(x, mode: int, value: float) -> bytes:
+    st, s = compress_status(x, mode, value)
+    if st != OK:
+        raise OracleError(st, "compress")
+    return s
+
+
+def decompress_status(stream, n: int):
+    buf = np.frombuffer(bytes(stream), dtype=np.uint8)
+    if buf.size == 0:
+        buf = np.zeros(1, dtype=np.uint8)
+        size = 0
+    else:
+        size = buf.size
+    out = np.zeros(max(n, 1), dtype=np.float32)
+    st = _load().fszo_decompress(buf.ctypes.data, size, out.ctypes.data, n)
+    return st, (out[:n] if st == OK else None)
+
+
+def decompress(stream, n: int) -> np.ndarray:
+    st, out = decompress_status(stream, n)
+    if st != OK:
+        raise OracleError(st, "decompress")
+    return out
+
+
+def tile_eval(x, inv: float):
+    """Four-way evaluation of one tile: (mu, centre_ok, cost[4], rates[4][8])."""
+    x = _f32(x)
+    lib = _load()
+    if not hasattr(lib, "_tile_eval_ready"):
+        lib.fszo_tile_eval.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+        lib.fszo_tile_eval.restype = ctypes.c_int
+        lib._tile_eval_ready = True
+    mu = ctypes.c_int32()
+    ok = ctypes.c_int()
+    cost = np.zeros(4, dtype=np.uint32)
+    rates = np.zeros((4, 8), dtype=np.uint32)
+    st = lib.fszo_tile_eval(x.ctypes.data, x.size, inv, ctypes.byref(mu), ctypes.byref(ok),
+                            cost.ctypes.data, rates.ctypes.data)
+    if st != OK:
+        raise OracleError(st, "tile_eval")
+    return mu.value, bool(ok.value), cost, rates

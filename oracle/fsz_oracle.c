@@ -1,0 +1,530 @@
+/*
+ * FSZ oracle -- plain, serial, obviously-correct CPU implementation of the
+ * FSZ compressor and decompressor (stream format v1, block B = 32 elements,
+ * tile = T = 8 blocks = 256 elements).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline of the benchmark.  It shares no code with the HIP library.
+ *
+ * Build with -O2 -ffp-contract=off and without fast-math: every floating
+ * point operation below is a single IEEE-754 binary32 (or binary64 where
+ * stated) operation in the written order.
+ *
+ * Paper references (FSZ, "Breaking the Prediction-Throughput Trade-off in
+ * GPU Lossy Compression"):
+ *   Sec. III-A   tile = 8 blocks x 32 elements; compressed format (rate
+ *                header byte per block, block-0 bit 7 = LZ order, bit 6 =
+ *                centering, bits 4-0 = rate; 4-byte sign map + 4*rate bytes
+ *                per block; zero-rate blocks store nothing; inline tile mean)
+ *   Sec. IV-A    cross-block prediction state, Eq. (1)-(2)
+ *   Sec. IV-B    four variants LZ1/LZ2 x centering, quantizer
+ *                q = round(d / (2 eb)), rate r = ceil(log2(max|l| + 1)),
+ *                block cost Eq. (3), cancellation property Eq. (4)
+ *   Sec. IV-C    fixed-length encoding, sign map, bit-shuffle (element i's
+ *                bit at position 31 - i of a 4-byte word)
+ *   Sec. IV-D    exclusive prefix sum of compressed sizes
+ *   Sec. V-A     REL bound: eb = REL * (max - min); pointwise |d - d'| <= eb
+ *
+ * Readings where the paper is silent (each one is listed in the design notes):
+ *   - quantizer: multiply by inv = fl32(1/E) then round-half-even; the step
+ *     E is 2*eb tightened by 4 ulp(max|x|) and rounded toward zero so that the
+ *     pointwise bound holds in binary32 arithmetic;
+ *   - zero predictor state at each tile start: q[-1] = q[-2] = 0;
+ *   - tile mean: index-order pairwise binary32 sum of the 256 slots (missing
+ *     slots of a ragged last tile count as +0), times 2^-8, quantized like
+ *     any element; centering is disabled if that value is not finite;
+ *   - selection ties: strict '<' in the order LZ1, LZ2, LZ1c, LZ2c;
+ *   - centered tile: the mean is stored as a little-endian int32 in the first
+ *     4 bytes of the tile's data;
+ *   - sign bit 1 = negative; sign word first, then planes 0..r-1; each
+ *     32-bit word is written most-significant byte first;
+ *   - a 32-byte stream header precedes the rate bytes, which are zero-padded
+ *     to a multiple of 16 bytes.
+ */
+#include "fsz_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define BLOCK 32
+#define BLOCKS_PER_TILE 8
+#define TILE (BLOCK * BLOCKS_PER_TILE)
+#define HEADER_BYTES 32
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                       */
+/* ------------------------------------------------------------------ */
+
+static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+static uint64_t pad16(uint64_t a) { return (a + 15) / 16 * 16; }
+
+/* rate r = ceil(log2(v + 1)) = number of significant bits of v (Sec. IV-A) */
+static uint32_t rate_of(uint32_t v)
+{
+    uint32_t r = 0;
+    while (v != 0) {
+        r++;
+        v >>= 1;
+    }
+    return r;
+}
+
+/* block cost, Eq. (3): nothing for a zero-rate block, else sign map + planes */
+static uint32_t block_cost(uint32_t r) { return r == 0 ? 0 : 4 + 4 * r; }
+
+static uint32_t magnitude(int32_t v) { return v < 0 ? (uint32_t)0 - (uint32_t)v : (uint32_t)v; }
+
+static void put_u16(uint8_t *p, uint16_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static void put_u32(uint8_t *p, uint32_t v)
+{
+    for (int k = 0; k < 4; k++) p[k] = (uint8_t)(v >> (8 * k));
+}
+static void put_u64(uint8_t *p, uint64_t v)
+{
+    for (int k = 0; k < 8; k++) p[k] = (uint8_t)(v >> (8 * k));
+}
+static uint32_t get_u32(const uint8_t *p)
+{
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+static uint64_t get_u64(const uint8_t *p)
+{
+    uint64_t v = 0;
+    for (int k = 7; k >= 0; k--) v = (v << 8) | p[k];
+    return v;
+}
+/* bit-shuffled words are stored most-significant byte first */
+static void put_word_msb_first(uint8_t *p, uint32_t w)
+{
+    p[0] = (uint8_t)(w >> 24);
+    p[1] = (uint8_t)(w >> 16);
+    p[2] = (uint8_t)(w >> 8);
+    p[3] = (uint8_t)w;
+}
+static uint32_t get_word_msb_first(const uint8_t *p)
+{
+    return ((uint32_t)p[0] << 24) | ((uint32_t)p[1] << 16) | ((uint32_t)p[2] << 8) | (uint32_t)p[3];
+}
+static float bits_to_float(uint32_t u)
+{
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+static uint32_t float_to_bits(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+uint64_t fszo_bound(uint64_t n)
+{
+    uint64_t nblocks = ceil_div(n, BLOCK);
+    uint64_t ntiles = ceil_div(n, TILE);
+    return HEADER_BYTES + pad16(nblocks) + 4 * ntiles + (4 + 4 * 31) * nblocks;
+}
+
+/* ------------------------------------------------------------------ */
+/* error-bound resolution (Sec. V-A and the binary32 reading above)    */
+/* ------------------------------------------------------------------ */
+
+/* spacing of binary32 numbers at magnitude m (m finite, >= 0) */
+static double ulp32(float m)
+{
+    if (m < FLT_MIN) return ldexp(1.0, -149);
+    int e;
+    frexpf(m, &e); /* m = f * 2^e, 0.5 <= f < 1 */
+    return ldexp(1.0, e - 24);
+}
+
+/* binary32 value of d (> 0) rounded toward zero */
+static float to_f32_toward_zero(double d)
+{
+    float f = (float)d;
+    if ((double)f > d) f = nextafterf(f, 0.0f);
+    return f;
+}
+
+int fszo_resolve(const float *x, uint64_t n, int mode, double value,
+                 float *E_out, float *inv_out, uint32_t *flags_out)
+{
+    if (mode != 0 && mode != 1) return FSZO_ERR_INVALID_ARG;
+    if (!isfinite(value) || !(value > 0.0)) return FSZO_ERR_INVALID_ARG;
+
+    float xmin = INFINITY, xmax = -INFINITY, M = 0.0f;
+    for (uint64_t i = 0; i < n; i++) {
+        float v = x[i];
+        if (!isfinite(v)) return FSZO_ERR_NONFINITE;
+        if (v < xmin) xmin = v;
+        if (v > xmax) xmax = v;
+        if (fabsf(v) > M) M = fabsf(v);
+    }
+
+    float E;
+    uint32_t flags = 0;
+    if (n == 0) {
+        E = 1.0f;
+    } else if (mode == 1 && xmax == xmin) {
+        /* zero value range: the field is one constant c, reproduced exactly
+         * with step |c| (q in {-1, 0, 1}) */
+        float c = fabsf(xmin);
+        if (c == 0.0f) E = 1.0f;
+        else if (c < FLT_MIN) return FSZO_ERR_EB_TOO_SMALL;
+        else E = c;
+        flags = 1;
+    } else {
+        double eb = mode == 1 ? value * ((double)xmax - (double)xmin) : value;
+        double u = ulp32(M);
+        if (!(eb >= 8.0 * u)) return FSZO_ERR_EB_TOO_SMALL;
+        double eb_q = eb - 4.0 * u;
+        E = to_f32_toward_zero(2.0 * eb_q);
+        if (E > 0x1p126f) E = 0x1p126f;
+        if (E < FLT_MIN) return FSZO_ERR_EB_TOO_SMALL;
+        if ((double)M + (double)E > (double)FLT_MAX) return FSZO_ERR_EB_TOO_LARGE;
+    }
+    *E_out = E;
+    *inv_out = 1.0f / E;
+    *flags_out = flags;
+    return FSZO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* per-tile analysis: single pass + four-way evaluation (Sec. IV-B)    */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int m;                          /* valid elements in the tile */
+    int nb;                         /* blocks in the tile */
+    int32_t q[TILE];                /* quantized values */
+    int32_t l1[TILE], l2[TILE];     /* LZ1 / LZ2 residuals, zero state at tile start */
+    int32_t mu;                     /* quantized tile mean */
+    int centre_ok;                  /* mean finite -> centered variants allowed */
+    uint32_t cost[4];               /* C of LZ1, LZ2, LZ1c, LZ2c */
+    uint32_t vrate[4][BLOCKS_PER_TILE]; /* per-block rates of each variant */
+    int order2, centred;            /* selected variant */
+    uint32_t rate[BLOCKS_PER_TILE]; /* selected per-block rates */
+    uint32_t bytes;                 /* selected tile cost C */
+} tile_t;
+
+static void analyse_tile(const float *x, int m, float inv, tile_t *t)
+{
+    t->m = m;
+    t->nb = (m + BLOCK - 1) / BLOCK;
+
+    /* Quantize + cross-block LZ1/LZ2 residuals in one loop (Sec. IV-A,
+     * Eq. (2); Sec. IV-B items 1-2).  The predictor state runs across all
+     * blocks of the tile; only the tile start has no predecessor. */
+    int32_t qm1 = 0, qm2 = 0;
+    for (int i = 0; i < TILE; i++) {
+        if (i < m) {
+            float y = x[i] * inv;
+            int32_t q = (int32_t)rintf(y);
+            t->q[i] = q;
+            t->l1[i] = q - qm1;
+            t->l2[i] = q - 2 * qm1 + qm2;
+            qm2 = qm1;
+            qm1 = q;
+        } else {
+            /* missing slots of a ragged last tile carry residual 0 */
+            t->q[i] = 0;
+            t->l1[i] = 0;
+            t->l2[i] = 0;
+        }
+    }
+
+    /* Tile mean (Sec. IV-B item 3): index-order pairwise binary32 sum of
+     * the 256 slots, then divided by 256 and quantized. */
+    float s[TILE];
+    for (int i = 0; i < TILE; i++) s[i] = i < m ? x[i] : 0.0f;
+    for (int w = 1; w < TILE; w *= 2)
+        for (int i = 0; i < TILE; i += 2 * w) s[i] = s[i] + s[i + w];
+    float mean_q = (s[0] * 0.00390625f) * inv;
+    t->centre_ok = isfinite(mean_q) ? 1 : 0;
+    t->mu = t->centre_ok ? (int32_t)rintf(mean_q) : 0;
+
+    /* Per-block rates.  By the cancellation property (Eq. (4)) the centered
+     * residuals equal the plain ones except the first k of the tile, so blocks
+     * 1..7 have one rate per order and block 0 is adjusted after the loop. */
+    uint32_t r1[BLOCKS_PER_TILE] = {0}, r2[BLOCKS_PER_TILE] = {0};
+    uint32_t inner1 = 0, inner2 = 0; /* block 0 without its first 1 / 2 residuals */
+    for (int b = 0; b < t->nb; b++) {
+        uint32_t a1 = 0, a2 = 0;
+        for (int i = b * BLOCK; i < (b + 1) * BLOCK; i++) {
+            uint32_t m1 = magnitude(t->l1[i]), m2 = magnitude(t->l2[i]);
+            if (b > 0 || i >= 1) a1 = m1 > a1 ? m1 : a1;
+            if (b > 0 || i >= 2) a2 = m2 > a2 ? m2 : a2;
+        }
+        if (b == 0) {
+            inner1 = a1;
+            inner2 = a2;
+        } else {
+            r1[b] = rate_of(a1);
+            r2[b] = rate_of(a2);
+        }
+    }
+    /* first residuals of the four variants: l[0] = q0 (or q0 - mu),
+     * LZ2 l[1] = q1 - 2 q0 (or q1 - 2 q0 + mu); absent when m < 2 */
+    int32_t q0 = t->q[0];
+    int32_t d1 = m >= 2 ? t->l2[1] : 0;
+    int32_t c0 = q0 - t->mu;
+    int32_t c1 = m >= 2 ? t->l2[1] + t->mu : 0;
+    uint32_t first[4][2] = {
+        {magnitude(q0), 0},              /* LZ1 */
+        {magnitude(q0), magnitude(d1)},  /* LZ2 */
+        {magnitude(c0), 0},              /* LZ1 + centering */
+        {magnitude(c0), magnitude(c1)},  /* LZ2 + centering */
+    };
+
+    for (int v = 0; v < 4; v++) {
+        int ord2 = v & 1, cen = v >> 1;
+        uint32_t a = ord2 ? inner2 : inner1;
+        if (first[v][0] > a) a = first[v][0];
+        if (first[v][1] > a) a = first[v][1];
+        t->vrate[v][0] = rate_of(a);
+        uint32_t c = block_cost(t->vrate[v][0]) + (cen ? 4 : 0);
+        for (int b = 1; b < BLOCKS_PER_TILE; b++) {
+            t->vrate[v][b] = b < t->nb ? (ord2 ? r2[b] : r1[b]) : 0;
+            c += block_cost(t->vrate[v][b]);
+        }
+        t->cost[v] = c;
+    }
+
+    /* Adaptive select: minimum C; ties keep the earlier of LZ1, LZ2, LZ1c,
+     * LZ2c; centered variants only with a finite mean. */
+    int best = 0;
+    if (t->cost[1] < t->cost[best]) best = 1;
+    if (t->centre_ok) {
+        if (t->cost[2] < t->cost[best]) best = 2;
+        if (t->cost[3] < t->cost[best]) best = 3;
+    }
+    t->order2 = best & 1;
+    t->centred = best >> 1;
+    t->bytes = t->cost[best];
+    for (int b = 0; b < BLOCKS_PER_TILE; b++) t->rate[b] = t->vrate[best][b];
+}
+
+int fszo_tile_eval(const float *x, int m, float inv, int32_t *mu, int *centre_ok,
+                   uint32_t *cost4, uint32_t *rates4x8)
+{
+    if (m < 1 || m > TILE) return FSZO_ERR_INVALID_ARG;
+    tile_t t;
+    analyse_tile(x, m, inv, &t);
+    *mu = t.mu;
+    *centre_ok = t.centre_ok;
+    for (int v = 0; v < 4; v++) {
+        cost4[v] = t.cost[v];
+        for (int b = 0; b < BLOCKS_PER_TILE; b++) rates4x8[v * BLOCKS_PER_TILE + b] = t.vrate[v][b];
+    }
+    return FSZO_OK;
+}
+
+/* residual of the selected variant at tile position i */
+static int32_t selected_residual(const tile_t *t, int i)
+{
+    if (i >= t->m) return 0;
+    int32_t e = t->order2 ? t->l2[i] : t->l1[i];
+    if (t->centred) {
+        if (i == 0) e = t->q[0] - t->mu;
+        else if (i == 1 && t->order2) e = t->l2[1] + t->mu;
+    }
+    return e;
+}
+
+/* Fixed-length encoding + bit-shuffle of one block (Sec. IV-C). */
+static uint8_t *encode_block(const tile_t *t, int b, uint8_t *p)
+{
+    uint32_t r = t->rate[b];
+    if (r == 0) return p;
+    uint32_t mag[BLOCK];
+    uint32_t sign = 0;
+    for (int j = 0; j < BLOCK; j++) {
+        int32_t e = selected_residual(t, b * BLOCK + j);
+        mag[j] = magnitude(e);
+        if (e < 0) sign |= 1u << (31 - j);
+    }
+    put_word_msb_first(p, sign);
+    p += 4;
+    for (uint32_t plane = 0; plane < r; plane++) {
+        uint32_t w = 0;
+        for (int j = 0; j < BLOCK; j++) w |= ((mag[j] >> plane) & 1u) << (31 - j);
+        put_word_msb_first(p, w);
+        p += 4;
+    }
+    return p;
+}
+
+int fszo_compress(const float *x, uint64_t n, int mode, double value,
+                  uint8_t *out, uint64_t cap, uint64_t *out_size)
+{
+    float E, inv;
+    uint32_t flags;
+    int st = fszo_resolve(x, n, mode, value, &E, &inv, &flags);
+    if (st != FSZO_OK) return st;
+
+    uint64_t nblocks = ceil_div(n, BLOCK);
+    uint64_t ntiles = ceil_div(n, TILE);
+    uint64_t data0 = HEADER_BYTES + pad16(nblocks);
+
+    /* Pass 1: per-tile analysis, rate header and tile sizes. */
+    tile_t *tiles = (tile_t *)malloc(sizeof(tile_t) * (ntiles ? ntiles : 1));
+    uint64_t *offset = (uint64_t *)malloc(sizeof(uint64_t) * (ntiles + 1));
+    if (!tiles || !offset) {
+        free(tiles);
+        free(offset);
+        return FSZO_ERR_INVALID_ARG;
+    }
+    for (uint64_t t = 0; t < ntiles; t++) {
+        uint64_t start = t * TILE;
+        int m = (int)(n - start < TILE ? n - start : TILE);
+        analyse_tile(x + start, m, inv, &tiles[t]);
+    }
+
+    /* Pass 2: exclusive prefix sum of tile sizes (Sec. IV-D). */
+    offset[0] = 0;
+    for (uint64_t t = 0; t < ntiles; t++) offset[t + 1] = offset[t] + tiles[t].bytes;
+    uint64_t total = data0 + offset[ntiles];
+    if (total > cap) {
+        free(tiles);
+        free(offset);
+        return FSZO_ERR_CAPACITY;
+    }
+
+    /* Header (32 bytes). */
+    memset(out, 0, data0);
+    out[0] = 'F';
+    out[1] = 'S';
+    out[2] = 'Z';
+    out[3] = '1';
+    put_u16(out + 4, 1);
+    out[6] = (uint8_t)mode;
+    out[7] = (uint8_t)flags;
+    put_u64(out + 8, n);
+    put_u32(out + 16, float_to_bits(E));
+    put_u32(out + 20, float_to_bits((float)value));
+    put_u64(out + 24, total);
+
+    /* Rate header: one byte per block (Sec. III-A). */
+    for (uint64_t t = 0; t < ntiles; t++) {
+        const tile_t *tl = &tiles[t];
+        for (int b = 0; b < tl->nb; b++) {
+            uint8_t byte = (uint8_t)tl->rate[b];
+            if (b == 0) byte |= (uint8_t)((tl->order2 << 7) | (tl->centred << 6));
+            out[HEADER_BYTES + t * BLOCKS_PER_TILE + b] = byte;
+        }
+    }
+
+    /* Pass 3: encode every tile at its offset. */
+    for (uint64_t t = 0; t < ntiles; t++) {
+        const tile_t *tl = &tiles[t];
+        uint8_t *p = out + data0 + offset[t];
+        if (tl->centred) {
+            put_u32(p, (uint32_t)tl->mu);
+            p += 4;
+        }
+        for (int b = 0; b < tl->nb; b++) p = encode_block(tl, b, p);
+    }
+
+    free(tiles);
+    free(offset);
+    *out_size = total;
+    return FSZO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* decompression (Sec. III-A, decompression steps 1-5)                 */
+/* ------------------------------------------------------------------ */
+
+int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t n)
+{
+    if (cmp_size < HEADER_BYTES) return FSZO_ERR_CORRUPT;
+    if (cmp[0] != 'F' || cmp[1] != 'S' || cmp[2] != 'Z' || cmp[3] != '1') return FSZO_ERR_CORRUPT;
+    if ((cmp[4] | (cmp[5] << 8)) != 1) return FSZO_ERR_CORRUPT;
+    if (cmp[6] > 1 || (cmp[7] & ~1u) != 0) return FSZO_ERR_CORRUPT;
+    uint64_t hn = get_u64(cmp + 8);
+    if (hn != n) return FSZO_ERR_SIZE_MISMATCH;
+    float E = bits_to_float(get_u32(cmp + 16));
+    if (!isfinite(E) || !(E > 0.0f)) return FSZO_ERR_CORRUPT;
+    uint64_t total = get_u64(cmp + 24);
+
+    uint64_t nblocks = ceil_div(n, BLOCK);
+    uint64_t ntiles = ceil_div(n, TILE);
+    uint64_t data0 = HEADER_BYTES + pad16(nblocks);
+    if (total > cmp_size || total < data0) return FSZO_ERR_CORRUPT;
+    const uint8_t *rates = cmp + HEADER_BYTES;
+    for (uint64_t k = nblocks; k < pad16(nblocks); k++)
+        if (rates[k] != 0) return FSZO_ERR_CORRUPT;
+
+    /* 1-3: rates and tile metadata -> block sizes -> exclusive prefix sum */
+    uint64_t *offset = (uint64_t *)malloc(sizeof(uint64_t) * (ntiles + 1));
+    if (!offset) return FSZO_ERR_INVALID_ARG;
+    offset[0] = 0;
+    for (uint64_t t = 0; t < ntiles; t++) {
+        uint64_t nb = nblocks - t * BLOCKS_PER_TILE;
+        if (nb > BLOCKS_PER_TILE) nb = BLOCKS_PER_TILE;
+        uint64_t bytes = 0;
+        for (uint64_t b = 0; b < nb; b++) {
+            uint8_t byte = rates[t * BLOCKS_PER_TILE + b];
+            if (b == 0 ? (byte & 0x20) != 0 : (byte & 0xE0) != 0) {
+                free(offset);
+                return FSZO_ERR_CORRUPT;
+            }
+            bytes += block_cost(byte & 0x1F);
+            if (b == 0 && (byte & 0x40)) bytes += 4;
+        }
+        offset[t + 1] = offset[t] + bytes;
+    }
+    if (data0 + offset[ntiles] != total) {
+        free(offset);
+        return FSZO_ERR_CORRUPT;
+    }
+
+    /* 4-5: decode + bit-unshuffle, inverse prediction, dequantize */
+    for (uint64_t t = 0; t < ntiles; t++) {
+        uint64_t start = t * TILE;
+        int m = (int)(n - start < TILE ? n - start : TILE);
+        int nb = (m + BLOCK - 1) / BLOCK;
+        uint8_t head = rates[t * BLOCKS_PER_TILE];
+        int order2 = (head >> 7) & 1, centred = (head >> 6) & 1;
+        const uint8_t *p = cmp + data0 + offset[t];
+        int32_t mu = 0;
+        if (centred) {
+            mu = (int32_t)get_u32(p);
+            p += 4;
+        }
+        uint32_t e[TILE];
+        for (int b = 0; b < nb; b++) {
+            uint32_t r = rates[t * BLOCKS_PER_TILE + b] & 0x1F;
+            for (int j = 0; j < BLOCK; j++) e[b * BLOCK + j] = 0;
+            if (r == 0) continue;
+            uint32_t sign = get_word_msb_first(p);
+            p += 4;
+            for (uint32_t plane = 0; plane < r; plane++) {
+                uint32_t w = get_word_msb_first(p);
+                p += 4;
+                for (int j = 0; j < BLOCK; j++) e[b * BLOCK + j] |= ((w >> (31 - j)) & 1u) << plane;
+            }
+            for (int j = 0; j < BLOCK; j++)
+                if ((sign >> (31 - j)) & 1u) e[b * BLOCK + j] = (uint32_t)0 - e[b * BLOCK + j];
+        }
+        /* inverse Lorenzo: one running sum for LZ1, two for LZ2 (wrapping
+         * 32-bit arithmetic, so corrupt streams cannot overflow) */
+        uint32_t acc1 = 0, acc2 = 0;
+        for (int i = 0; i < m; i++) {
+            acc1 += e[i];
+            uint32_t qhat;
+            if (order2) {
+                acc2 += acc1;
+                qhat = acc2;
+            } else {
+                qhat = acc1;
+            }
+            int32_t q = (int32_t)(qhat + (uint32_t)mu);
+            out[start + i] = (float)q * E;
+        }
+    }
+    free(offset);
+    return FSZO_OK;
+}

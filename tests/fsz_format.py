@@ -1,0 +1,171 @@
+"""Independent pure-Python reading of the FSZ stream format, for tests only.
+
+Written separately from both the oracle and the HIP library: it parses
+streams, recomputes per-tile choices by brute force (four full residual
+passes, no cancellation shortcut) and can encode a stream with arbitrary
+(even non-optimal) per-tile variant choices, which every decoder must accept.
+
+Format (see the design notes): 32-byte header, one rate byte per 32-element
+block (Sec. III-A) zero-padded to 16 bytes, then per 256-element tile its
+optional int32 mean and, per block with rate r > 0, a sign word and r
+bit-plane words, element j of the block at bit 31 - j, words written
+most-significant byte first (Sec. IV-C).
+"""
+import struct
+
+import numpy as np
+
+HEADER = 32
+BLOCK = 32
+TILE = 256
+
+
+def ceil_div(a, b):
+    return -(-a // b)
+
+
+def pad16(a):
+    return (a + 15) // 16 * 16
+
+
+def data_start(n):
+    return HEADER + pad16(ceil_div(n, BLOCK))
+
+
+def parse_header(s: bytes) -> dict:
+    magic, version, mode, flags, n, E, value, total = struct.unpack_from("<4sHBBQffQ", s, 0)
+    return dict(magic=magic, version=version, mode=mode, flags=flags, n=n, E=E, value=value,
+                total=total)
+
+
+def rate_bytes(s: bytes, n: int) -> np.ndarray:
+    return np.frombuffer(s, dtype=np.uint8, count=ceil_div(n, BLOCK), offset=HEADER)
+
+
+def bitlen(v: int) -> int:
+    return int(v).bit_length()
+
+
+def block_cost(r: int) -> int:
+    return 0 if r == 0 else 4 + 4 * r
+
+
+def tile_choices(s: bytes, n: int):
+    """Per tile: (order2, centred, [8 rates]) read from the rate header
+    (blocks past the end of a ragged last tile read as rate 0)."""
+    rb = rate_bytes(s, n)
+    out = []
+    for t in range(ceil_div(n, TILE)):
+        blk = rb[t * 8:(t + 1) * 8]
+        rates = [int(b) & 0x1F for b in blk] + [0] * (8 - blk.size)
+        out.append((int(blk[0] >> 7) & 1, int(blk[0] >> 6) & 1, rates))
+    return out
+
+
+def tile_sizes(s: bytes, n: int):
+    return [sum(block_cost(r) for r in rates) + 4 * c for (_, c, rates) in tile_choices(s, n)]
+
+
+def quantize(x: np.ndarray, inv: float) -> np.ndarray:
+    """q = rint(fl32(x * inv)) in binary32, as int64."""
+    y = (np.asarray(x, dtype=np.float32) * np.float32(inv)).astype(np.float32)
+    return np.rint(y).astype(np.int64)
+
+
+def closed_form(x: np.ndarray, E: float, inv: float) -> np.ndarray:
+    """Reconstruction fl32((float)q * E): independent of variant and mean."""
+    q = quantize(x, inv)
+    return (q.astype(np.float32) * np.float32(E)).astype(np.float32)
+
+
+def pairwise_mean(xt: np.ndarray, inv: float):
+    """(finite, mu): index-order pairwise binary32 sum of 256 slots (+0 padded)."""
+    s = np.zeros(TILE, dtype=np.float32)
+    s[:xt.size] = xt
+    with np.errstate(over="ignore", invalid="ignore"):
+        while s.size > 1:
+            s = (s[0::2] + s[1::2]).astype(np.float32)
+        v = np.float32(np.float32(s[0] * np.float32(0.00390625)) * np.float32(inv))
+    if not np.isfinite(v):
+        return False, 0
+    return True, int(np.rint(v))
+
+
+def residuals(q: np.ndarray, order2: int, mu: int) -> np.ndarray:
+    """Lorenzo residuals of q - mu with zero state before the tile start."""
+    qc = np.asarray(q, dtype=np.int64) - mu
+    p1 = np.concatenate([[0], qc[:-1]])
+    if not order2:
+        return qc - p1
+    p2 = np.concatenate([[0, 0], qc[:-2]])[:qc.size]
+    return qc - 2 * p1 + p2
+
+
+def brute_force_tile(xt: np.ndarray, inv: float):
+    """Four separate full passes; returns (mu, centre_ok, costs[4], rates[4][8], best)."""
+    m = xt.size
+    nb = ceil_div(m, BLOCK)
+    q = quantize(xt, inv)
+    ok, mu = pairwise_mean(xt, inv)
+    costs, rates = [], []
+    for v in range(4):
+        order2, cen = v & 1, v >> 1
+        res = np.zeros(TILE, dtype=np.int64)
+        res[:m] = residuals(q, order2, mu if cen else 0)
+        rv = [bitlen(int(np.abs(res[b * BLOCK:(b + 1) * BLOCK]).max())) if b < nb else 0
+              for b in range(8)]
+        rates.append(rv)
+        costs.append(sum(block_cost(r) for r in rv) + (4 if cen else 0))
+    best = 0
+    for v in (1, 2, 3):
+        if v >= 2 and not ok:
+            continue
+        if costs[v] < costs[best]:
+            best = v
+    return mu, ok, costs, rates, best
+
+
+def _word_bytes(w: int) -> bytes:
+    return struct.pack(">I", w)
+
+
+def encode_stream(x: np.ndarray, E: float, inv: float, mode: int, value: float, flags: int,
+                  choices) -> bytes:
+    """Encode x with the given per-tile (order2, centred, mu) choices."""
+    x = np.asarray(x, dtype=np.float32).reshape(-1)
+    n = x.size
+    q = quantize(x, inv)
+    nblocks = ceil_div(n, BLOCK)
+    rate_hdr = bytearray(pad16(nblocks))
+    body = bytearray()
+    for t in range(ceil_div(n, TILE)):
+        qt = q[t * TILE:(t + 1) * TILE]
+        m = qt.size
+        order2, cen, mu = choices[t]
+        res = np.zeros(TILE, dtype=np.int64)
+        res[:m] = residuals(qt, order2, mu if cen else 0)
+        if cen:
+            body += struct.pack("<i", mu)
+        for b in range(ceil_div(m, BLOCK)):
+            blk = res[b * BLOCK:(b + 1) * BLOCK]
+            r = bitlen(int(np.abs(blk).max()))
+            byte = r
+            if b == 0:
+                byte |= (order2 << 7) | (cen << 6)
+            rate_hdr[t * 8 + b] = byte
+            if r == 0:
+                continue
+            sign = 0
+            for j in range(BLOCK):
+                if blk[j] < 0:
+                    sign |= 1 << (31 - j)
+            body += _word_bytes(sign)
+            mag = np.abs(blk)
+            for p in range(r):
+                w = 0
+                for j in range(BLOCK):
+                    w |= ((int(mag[j]) >> p) & 1) << (31 - j)
+                body += _word_bytes(w)
+    total = HEADER + len(rate_hdr) + len(body)
+    hdr = struct.pack("<4sHBBQffQ", b"FSZ1", 1, mode, flags, n, E, value, total)
+    return bytes(hdr) + bytes(rate_hdr) + bytes(body)
