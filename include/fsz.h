@@ -1,0 +1,112 @@
+/*
+ * fsz.h -- C ABI of the MI355X (gfx950) FSZ compressor library, libfsz.so.
+ *
+ * FSZ is an error-bounded lossy compressor for float32 fields (paper: "FSZ:
+ * Breaking the Prediction-Throughput Trade-off in GPU Lossy Compression").
+ * Every element x is reconstructed as x' with |x - x'| <= eb (Sec. V-A).
+ * The stream is: a 32-byte header, one rate byte per 32-element block
+ * (Sec. III-A, "Compressed format"), zero-padded to 16 bytes, then the
+ * variable-length data of each 256-element tile (optional inline mean,
+ * sign word + bit planes per nonzero-rate block, Sec. IV-C).
+ *
+ * Conventions for every entry point
+ *   - Pointers named d_* are DEVICE pointers (hipMalloc, or a PyTorch CUDA
+ *     tensor's data pointer) on the current HIP device.  The caller owns
+ *     them; the library never frees or retains them after the call.
+ *   - d_in / d_out float arrays need 4-byte alignment; 16-byte alignment
+ *     selects vector loads.  Compressed buffers need 4-byte alignment.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that
+ *     return a size block the host until the stream has executed them.
+ *     Calls on the same stream are ordered; the library keeps one
+ *     workspace per (device, stream), so concurrent calls on different
+ *     streams are safe, and concurrent calls on the SAME stream from
+ *     several host threads are serialized by an internal lock.
+ *   - The library allocates its workspace (chunk flags, tickets, result
+ *     words) on first use per (device, stream) and grows it when a larger
+ *     field arrives; it never allocates on the device otherwise.
+ *   - Errors are returned as fsz_status values; nothing is thrown across
+ *     the ABI.  Device-detected errors (non-finite input, bound too small,
+ *     capacity, corrupt stream) arrive through the final status read.
+ */
+#ifndef FSZ_H
+#define FSZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error-bound modes (Sec. V-A): ABS = absolute bound eb = value; REL = bound
+ * relative to the value range, eb = value * (max(x) - min(x)). */
+typedef enum { FSZ_ABS = 0, FSZ_REL = 1 } fsz_eb_mode;
+
+typedef enum {
+    FSZ_OK = 0,
+    FSZ_ERR_INVALID_ARG = 1,   /* bad pointer / mode / value / alignment */
+    FSZ_ERR_NONFINITE = 2,     /* input holds NaN or Inf */
+    FSZ_ERR_EB_TOO_SMALL = 3,  /* eb below 8 ulp(max|x|): no binary32 grid honours it */
+    FSZ_ERR_CAPACITY = 4,      /* output buffer smaller than the stream */
+    FSZ_ERR_CORRUPT = 5,       /* stream fails validation */
+    FSZ_ERR_SIZE_MISMATCH = 6, /* n differs from the stream's element count */
+    FSZ_ERR_DEVICE = 7,        /* a HIP runtime call failed */
+    FSZ_ERR_EB_TOO_LARGE = 8   /* step so large that max|x| + step overflows binary32 */
+} fsz_status;
+
+/* Field statistics used to resolve the error bound (written by
+ * fsz_field_stats, read by fsz_compress_ex).  flags bit 0 = a non-finite
+ * value was seen (then xmin/xmax/maxabs cover the finite values only). */
+typedef struct {
+    float xmin;
+    float xmax;
+    float maxabs;
+    uint32_t flags;
+} fsz_stats;
+
+/* Worst-case stream size in bytes for n elements (every block at the
+ * format's maximum rate 31, every tile centred):
+ * 32 + pad16(ceil(n/32)) + 4*ceil(n/256) + 128*ceil(n/32).  Pure host
+ * arithmetic; never fails. */
+size_t fsz_compressed_bound(size_t n);
+
+/* Human-readable name of a status value (static string). */
+const char *fsz_status_string(int status);
+
+/* Value-range pass (needed for REL, Sec. V-A, and for the step tightening
+ * in both modes): min, max, max|x| and finiteness of d_in[0..n) into the
+ * device struct *d_stats.  Asynchronous: returns after enqueueing on
+ * stream.  Errors: FSZ_ERR_INVALID_ARG (NULL pointers with n > 0),
+ * FSZ_ERR_DEVICE. */
+fsz_status fsz_field_stats(const float *d_in, size_t n, fsz_stats *d_stats, void *stream);
+
+/* Compress d_in[0..n) with bound (mode, value) into d_out[0..out_capacity).
+ * Runs the value-range pass, then the single compression kernel (Sec. III-A
+ * steps 1-5: quantize + cross-block prediction, four-way evaluation,
+ * adaptive select, in-kernel decoupled-lookback offset scan, bit-shuffle
+ * encode).  On FSZ_OK, *out_size holds the stream length.  Blocks until the
+ * stream finished.  value must be finite and > 0.  out_capacity must be at
+ * least 32 + pad16(ceil(n/32)); fsz_compressed_bound(n) always suffices,
+ * otherwise FSZ_ERR_CAPACITY may be returned with d_out partly written. */
+fsz_status fsz_compress(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                        void *d_out, size_t out_capacity, size_t *out_size, void *stream);
+
+/* As fsz_compress but with field statistics already computed by
+ * fsz_field_stats on the same stream (one HBM read of d_in instead of
+ * two; lets several bounds reuse one range pass). */
+fsz_status fsz_compress_ex(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                           const fsz_stats *d_stats, void *d_out, size_t out_capacity,
+                           size_t *out_size, void *stream);
+
+/* Decompress a stream of cmp_size bytes into d_out[0..n) (Sec. III-A,
+ * decompression steps 1-5, in one kernel).  n must equal the stream's
+ * element count (else FSZ_ERR_SIZE_MISMATCH).  Corrupt streams return
+ * FSZ_ERR_CORRUPT; d_out contents are then unspecified.  Blocks until the
+ * stream finished. */
+fsz_status fsz_decompress(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
+                          void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSZ_H */

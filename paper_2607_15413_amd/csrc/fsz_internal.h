@@ -1,0 +1,98 @@
+// Internal declarations shared by the kernel and host translation units of
+// libfsz.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fsz.h"
+
+namespace fsz {
+
+// Format constants: block of 32 elements, tile of 8 blocks (Sec. III-A).
+constexpr int kBlock = 32;
+constexpr int kBlocksPerTile = 8;
+constexpr int kTile = kBlock * kBlocksPerTile;
+constexpr int kHeaderBytes = 32;
+
+// Launch geometry.  One lane owns one 32-element block, so a wave64 holds 8
+// tiles; a workgroup of kWaves waves owns one chunk of 8*kWaves tiles.
+constexpr int kWaves = 4;
+constexpr int kThreads = kWaves * 64;
+constexpr int kTilesPerWave = 8;
+constexpr int kTilesPerChunk = kTilesPerWave * kWaves;
+constexpr int kStatsThreads = 256;
+constexpr int kStatsMaxBlocks = 1024;
+
+// Per-lane LDS staging row: 32 floats + 4 dwords of padding (bank spread).
+constexpr int kStageRowDwords = 36;
+constexpr int kStageWaveDwords = 64 * kStageRowDwords;
+
+// Chunk flag word for the decoupled lookback (Sec. IV-D): 2-bit state,
+// 18-bit call epoch (stale words from earlier calls read as "not ready"),
+// 44-bit byte count.
+constexpr uint64_t kFlagAggregate = 1;
+constexpr uint64_t kFlagInclusive = 2;
+constexpr int kEpochBits = 18;
+constexpr uint32_t kEpochMask = (1u << kEpochBits) - 1;
+constexpr int kValueBits = 44;
+constexpr uint64_t kValueMask = (1ull << kValueBits) - 1;
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline uint64_t pad16(uint64_t a) { return (a + 15) / 16 * 16; }
+
+// Result record in device memory, read back once per call.  status_word and
+// size_word are tagged with the call's 32-bit epoch, so no per-call reset
+// is needed: a word from an older call is simply "not written this call".
+struct Result {
+    unsigned long long status_word;  // (epoch << 32) | fsz_status, first error wins
+    unsigned long long size;         // total stream bytes (compress)
+    unsigned long long size_epoch;   // epoch of `size`
+    unsigned long long pad;
+};
+
+struct StatsPartial {
+    float xmin, xmax, maxabs;
+    uint32_t flags;
+};
+
+struct StatsArgs {
+    const float *x;
+    uint64_t n;
+    fsz_stats *out;
+    StatsPartial *partials;
+    unsigned int *counter;
+};
+
+struct CompressArgs {
+    const float *x;
+    uint64_t n, ntiles, nblocks, nchunks, data0;
+    uint8_t *out;
+    uint64_t capacity;
+    const fsz_stats *stats;
+    double value;
+    int mode;
+    uint32_t epoch;       // 32-bit call epoch (result words)
+    uint32_t flag_epoch;  // 18-bit nonzero epoch (chunk flags)
+    unsigned long long *flags;
+    unsigned long long *ticket;  // zero between launches (self-resetting)
+    Result *result;
+};
+
+struct DecompressArgs {
+    const uint8_t *cmp;
+    uint64_t cmp_size;
+    float *out;
+    uint64_t n, ntiles, nblocks, nchunks, data0;
+    uint32_t epoch, flag_epoch;
+    unsigned long long *flags;
+    unsigned long long *ticket;  // zero between launches (self-resetting)
+    Result *result;
+};
+
+// Kernel launchers (fsz_kernels.hip).
+hipError_t launch_stats(const StatsArgs &a, hipStream_t s);
+hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, hipStream_t s);
+hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, hipStream_t s);
+
+}  // namespace fsz

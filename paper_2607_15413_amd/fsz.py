@@ -1,0 +1,166 @@
+"""Thin ctypes binding of libfsz.so (the C ABI declared in include/fsz.h).
+
+The functions named fsz_* marshal arguments 1:1 onto the C entry points:
+device pointers are integers (e.g. ``tensor.data_ptr()``), streams are
+hipStream_t handles as integers (``torch.cuda.current_stream().cuda_stream``)
+or None for the default stream.  Every step of compression and
+decompression runs in the library's HIP kernels; if the built library is
+missing this module raises instead of falling back to anything else.
+
+The helpers ``compress`` / ``decompress`` / ``field_stats`` only add PyTorch
+device-memory plumbing around those calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfsz.so")
+
+FSZ_ABS = 0
+FSZ_REL = 1
+
+FSZ_OK = 0
+FSZ_ERR_INVALID_ARG = 1
+FSZ_ERR_NONFINITE = 2
+FSZ_ERR_EB_TOO_SMALL = 3
+FSZ_ERR_CAPACITY = 4
+FSZ_ERR_CORRUPT = 5
+FSZ_ERR_SIZE_MISMATCH = 6
+FSZ_ERR_DEVICE = 7
+FSZ_ERR_EB_TOO_LARGE = 8
+
+# names of every C entry point declared in include/fsz.h
+EXPORTS = (
+    "fsz_compressed_bound",
+    "fsz_status_string",
+    "fsz_field_stats",
+    "fsz_compress",
+    "fsz_compress_ex",
+    "fsz_decompress",
+)
+
+
+class FszError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {fsz_status_string(status)} (status {status})")
+        self.status = status
+
+
+class FszStats(ctypes.Structure):
+    _fields_ = [("xmin", ctypes.c_float), ("xmax", ctypes.c_float), ("maxabs", ctypes.c_float),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libfsz.so (built by ``__graft_entry__.build()``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    sz, vp = ctypes.c_size_t, ctypes.c_void_p
+    lib.fsz_compressed_bound.argtypes = [sz]
+    lib.fsz_compressed_bound.restype = sz
+    lib.fsz_status_string.argtypes = [ctypes.c_int]
+    lib.fsz_status_string.restype = ctypes.c_char_p
+    lib.fsz_field_stats.argtypes = [vp, sz, vp, vp]
+    lib.fsz_field_stats.restype = ctypes.c_int
+    lib.fsz_compress.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, sz,
+                                 ctypes.POINTER(sz), vp]
+    lib.fsz_compress.restype = ctypes.c_int
+    lib.fsz_compress_ex.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, vp, sz,
+                                    ctypes.POINTER(sz), vp]
+    lib.fsz_compress_ex.restype = ctypes.c_int
+    lib.fsz_decompress.argtypes = [vp, sz, vp, sz, vp]
+    lib.fsz_decompress.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+# ----------------------------------------------------------------- C ABI
+
+
+def fsz_compressed_bound(n: int) -> int:
+    return int(load_library().fsz_compressed_bound(n))
+
+
+def fsz_status_string(status: int) -> str:
+    return load_library().fsz_status_string(status).decode()
+
+
+def fsz_field_stats(d_in: int, n: int, d_stats: int, stream=None) -> int:
+    return load_library().fsz_field_stats(d_in, n, d_stats, stream)
+
+
+def fsz_compress(d_in: int, n: int, mode: int, value: float, d_out: int, out_capacity: int,
+                 stream=None):
+    """Returns (status, out_size)."""
+    size = ctypes.c_size_t(0)
+    st = load_library().fsz_compress(d_in, n, mode, value, d_out, out_capacity,
+                                     ctypes.byref(size), stream)
+    return st, size.value
+
+
+def fsz_compress_ex(d_in: int, n: int, mode: int, value: float, d_stats: int, d_out: int,
+                    out_capacity: int, stream=None):
+    """Returns (status, out_size)."""
+    size = ctypes.c_size_t(0)
+    st = load_library().fsz_compress_ex(d_in, n, mode, value, d_stats, d_out, out_capacity,
+                                        ctypes.byref(size), stream)
+    return st, size.value
+
+
+def fsz_decompress(d_cmp: int, cmp_size: int, d_out: int, n: int, stream=None) -> int:
+    return load_library().fsz_decompress(d_cmp, cmp_size, d_out, n, stream)
+
+
+# ----------------------------------------------------------------- torch plumbing
+
+
+def _stream_handle(torch, device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def compress(x, mode: int, value: float, out=None, check: bool = True):
+    """Compress a contiguous float32 CUDA tensor; returns (uint8 tensor view, status)."""
+    import torch
+    assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+    n = x.numel()
+    if out is None:
+        out = torch.empty(fsz_compressed_bound(n), dtype=torch.uint8, device=x.device)
+    st, size = fsz_compress(x.data_ptr(), n, mode, value, out.data_ptr(), out.numel(),
+                            _stream_handle(torch, x.device))
+    if check and st != FSZ_OK:
+        raise FszError(st, "fsz_compress")
+    return (out[:size] if st == FSZ_OK else out), st
+
+
+def decompress(stream_bytes, n: int, out=None, check: bool = True):
+    """Decompress a uint8 CUDA tensor holding one stream; returns (float32 tensor, status)."""
+    import torch
+    assert stream_bytes.dtype == torch.uint8 and stream_bytes.is_cuda
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.float32, device=stream_bytes.device)[:n]
+    st = fsz_decompress(stream_bytes.data_ptr(), stream_bytes.numel(), out.data_ptr(), n,
+                        _stream_handle(torch, stream_bytes.device))
+    if check and st != FSZ_OK:
+        raise FszError(st, "fsz_decompress")
+    return out, st
+
+
+def field_stats(x, out=None):
+    """Enqueue the value-range pass; returns a 16-byte device tensor holding fsz_stats."""
+    import torch
+    if out is None:
+        out = torch.empty(4, dtype=torch.int32, device=x.device)
+    st = fsz_field_stats(x.data_ptr(), x.numel(), out.data_ptr(), _stream_handle(torch, x.device))
+    if st != FSZ_OK:
+        raise FszError(st, "fsz_field_stats")
+    return out

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Compressed streams must be byte-identical and reconstructions bit-identical
+(integer work after one binary32 quantization step, no FMA contraction).
+Every case prints its name before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_15413_amd import fsz, workloads
+from tests import fsz_format as fmt
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def _stream():
+    return torch.cuda.current_stream(_dev()).cuda_stream
+
+
+def announce(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def gpu_compress(x, mode, value, capacity=None, in_offset=0):
+    """Compress numpy float32 x on the GPU; returns (status, bytes or None)."""
+    n = x.size
+    xd = torch.zeros(n + in_offset + 4, dtype=torch.float32, device=_dev())
+    if n:
+        xd[in_offset:in_offset + n] = torch.from_numpy(x).to(_dev())
+    cap = fsz.fsz_compressed_bound(n) if capacity is None else capacity
+    out = torch.zeros(max(cap, 1), dtype=torch.uint8, device=_dev())
+    st, size = fsz.fsz_compress(xd.data_ptr() + 4 * in_offset, n, mode, value, out.data_ptr(), cap,
+                                _stream())
+    if st != fsz.FSZ_OK:
+        return st, None
+    return st, out[:size].cpu().numpy().tobytes()
+
+
+def gpu_decompress(stream_bytes, n, out_offset=0):
+    buf = torch.from_numpy(np.frombuffer(stream_bytes, dtype=np.uint8).copy()).to(_dev())
+    out = torch.full((n + out_offset + 4,), float("nan"), dtype=torch.float32, device=_dev())
+    st = fsz.fsz_decompress(buf.data_ptr(), len(stream_bytes), out.data_ptr() + 4 * out_offset, n,
+                            _stream())
+    if st != fsz.FSZ_OK:
+        return st, None
+    return st, out[out_offset:out_offset + n].cpu().numpy()
+
+
+def first_diff(a: bytes, b: bytes):
+    if len(a) != len(b):
+        return f"lengths {len(a)} vs {len(b)}"
+    for i in range(len(a)):
+        if a[i] != b[i]:
+            return f"byte {i}: {a[i]:#04x} vs {b[i]:#04x}"
+    return "equal"
+
+
+def check_round_trip(name, x, mode, value, in_offset=0, out_offset=0):
+    announce(f"{name} n={x.size} mode={mode} value={value} in_off={in_offset} out_off={out_offset}")
+    st_ref, ref = oracle.compress_status(x, mode, value)
+    st, got = gpu_compress(x, mode, value, in_offset=in_offset)
+    assert st == st_ref, (name, st, st_ref)
+    if st != fsz.FSZ_OK:
+        return None
+    assert got == ref, f"{name}: stream differs from the oracle ({first_diff(got, ref)})"
+    st, y = gpu_decompress(got, x.size, out_offset=out_offset)
+    assert st == fsz.FSZ_OK
+    y_ref = oracle.decompress(ref, x.size)
+    assert np.array_equal(y.view(np.uint32), y_ref.view(np.uint32)), f"{name}: reconstruction differs"
+    return ref
+
+
+# ----------------------------------------------------------------- configs
+
+
+@pytest.mark.parametrize("rel", [1e-2, 1e-3, 1e-4])
+def test_sinusoid_2pow20(rel):
+    x = workloads.sinusoid_field(1 << 20, 0)
+    check_round_trip("sinusoid-2^20", x, fsz.FSZ_REL, rel)
+
+
+def test_piecewise_quadratic_full():
+    x = workloads.piecewise_quadratic((100, 500, 500), 2)
+    for rel in (1e-2, 1e-3, 1e-4):
+        check_round_trip("pwq-100x500x500", x, fsz.FSZ_REL, rel)
+
+
+def test_grf_small():
+    x = workloads.grf_field((64, 64, 64), 1)
+    for rel in (1e-2, 1e-3, 1e-4):
+        check_round_trip("grf-64^3", x, fsz.FSZ_REL, rel)
+
+
+# ----------------------------------------------------------------- ragged / edge sizes
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 31, 32, 33, 255, 256, 257, 2047, 2048, 2049, 8191, 8192,
+                               8193, 65537])
+def test_edge_sizes(n):
+    x = workloads.sinusoid_field(n, n + 7)
+    check_round_trip("edge", x, fsz.FSZ_REL, 1e-3)
+    check_round_trip("edge-abs", x, fsz.FSZ_ABS, 1e-4)
+
+
+def test_unaligned_pointers():
+    x = workloads.sinusoid_field(100_001, 3)
+    for off_in, off_out in ((1, 0), (2, 3), (3, 1)):
+        check_round_trip("unaligned", x, fsz.FSZ_REL, 1e-3, in_offset=off_in, out_offset=off_out)
+
+
+def _fuzz_field(rng, n):
+    kind = int(rng.integers(0, 7))
+    if kind == 0:
+        return "sinusoid", workloads.sinusoid_field(n, int(rng.integers(1 << 30)))
+    if kind == 1:
+        return "uniform", rng.uniform(-1, 1, n).astype(np.float32)
+    if kind == 2:
+        return "offset-noise", (1000.0 + rng.normal(0, 0.01, n)).astype(np.float32)
+    if kind == 3:
+        q = np.cumsum(rng.integers(-3, 4, n))
+        return "random-walk", (q * 0.125).astype(np.float32)
+    if kind == 4:
+        x = np.zeros(n, np.float32)
+        x[rng.integers(0, n, max(1, n // 100))] = rng.uniform(-50, 50, max(1, n // 100))
+        return "sparse-spikes", x
+    if kind == 5:
+        i = np.arange(n, dtype=np.float64)
+        return "quadratic", (3.0 + 0.01 * i - 1e-6 * i * i).astype(np.float32)
+    v = np.repeat(rng.uniform(-5, 5, n // 97 + 1), 97)[:n]
+    return "piecewise-const", v.astype(np.float32)
+
+
+def test_fuzz():
+    rng = np.random.default_rng(1234)
+    for case in range(40):
+        n = int(rng.choice([int(rng.integers(1, 600)), int(rng.integers(1, 40_000)),
+                            int(rng.integers(1, 1 << 20))]))
+        name, x = _fuzz_field(rng, n)
+        mode = int(rng.integers(0, 2))
+        value = float(10.0 ** rng.uniform(-5, -1)) if mode == 1 else float(10.0 ** rng.uniform(-4, 0))
+        check_round_trip(f"fuzz{case}-{name}", x, mode, value)
+
+
+# ----------------------------------------------------------------- special fields and statuses
+
+
+def test_special_fields():
+    n = 256 * 33 + 5
+    check_round_trip("zeros-abs", np.zeros(n, np.float32), fsz.FSZ_ABS, 1e-3)
+    check_round_trip("zeros-rel", np.zeros(n, np.float32), fsz.FSZ_REL, 1e-3)
+    check_round_trip("constant-rel", np.full(n, 1013.25, np.float32), fsz.FSZ_REL, 1e-3)
+    check_round_trip("constant-neg-rel", np.full(n, -7.5, np.float32), fsz.FSZ_REL, 1e-2)
+    check_round_trip("subnormal-constant", np.full(n, 1e-40, np.float32), fsz.FSZ_REL, 1e-3)
+    big = np.full(300, 3.0e38, np.float32)
+    big[::2] = 2.9e38
+    check_round_trip("huge-values", big, fsz.FSZ_ABS, 1e35)
+    too_large = np.full(10, 3.3e38, np.float32)
+    too_large[0] = -1
+    check_round_trip("eb-too-large", too_large, fsz.FSZ_ABS, 1e37)
+    x = workloads.sinusoid_field(5000, 9)
+    check_round_trip("eb-too-small", x, fsz.FSZ_ABS, 1e-9)
+    bad = x.copy()
+    bad[4321] = np.nan
+    check_round_trip("nan", bad, fsz.FSZ_REL, 1e-3)
+    bad[4321] = -np.inf
+    check_round_trip("inf", bad, fsz.FSZ_ABS, 1e-3)
+
+
+def test_capacity_too_small():
+    x = workloads.sinusoid_field(50_000, 5)
+    ref = oracle.compress(x, oracle.REL, 1e-3)
+    announce("capacity")
+    for cap in (fmt.data_start(x.size), len(ref) - 4):
+        st, _ = gpu_compress(x, fsz.FSZ_REL, 1e-3, capacity=cap)
+        assert st == fsz.FSZ_ERR_CAPACITY
+    st, got = gpu_compress(x, fsz.FSZ_REL, 1e-3, capacity=len(ref))
+    assert st == fsz.FSZ_OK and got == ref
+
+
+def test_compress_ex_reuses_stats():
+    x = workloads.grf_field((32, 64, 64), 4)
+    announce("compress_ex")
+    xd = torch.from_numpy(x).to(_dev())
+    stats = torch.zeros(4, dtype=torch.int32, device=_dev())
+    assert fsz.fsz_field_stats(xd.data_ptr(), x.size, stats.data_ptr(), _stream()) == fsz.FSZ_OK
+    st_cpu = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=np.float32)
+    assert st_cpu[0] == x.min() and st_cpu[1] == x.max() and st_cpu[2] == np.abs(x).max()
+    for rel in (1e-2, 1e-3, 1e-4):
+        out = torch.zeros(fsz.fsz_compressed_bound(x.size), dtype=torch.uint8, device=_dev())
+        st, size = fsz.fsz_compress_ex(xd.data_ptr(), x.size, fsz.FSZ_REL, rel, stats.data_ptr(),
+                                       out.data_ptr(), out.numel(), _stream())
+        assert st == fsz.FSZ_OK
+        assert out[:size].cpu().numpy().tobytes() == oracle.compress(x, oracle.REL, rel)
+
+
+# ----------------------------------------------------------------- decoder
+
+
+def test_decoder_any_variant_and_mean():
+    rng = np.random.default_rng(77)
+    for n in (5, 256, 700, 5000, 20_001):
+        announce(f"python-encoded n={n}")
+        x = workloads.sinusoid_field(n, int(rng.integers(1000)))
+        st, E, inv, _ = oracle.resolve(x, oracle.REL, 1e-3)
+        choices = [(int(rng.integers(2)), int(rng.integers(2)), int(rng.integers(-5000, 5000)))
+                   for _ in range(fmt.ceil_div(n, 256))]
+        s = fmt.encode_stream(x, E, inv, oracle.REL, 1e-3, 0, choices)
+        st, y = gpu_decompress(s, n)
+        assert st == fsz.FSZ_OK
+        assert np.array_equal(y, fmt.closed_form(x, E, inv))
+
+
+def test_corrupt_streams_match_oracle_status():
+    from tests.test_oracle import _mutations
+    n = 3000
+    x = workloads.sinusoid_field(n, 2)
+    s = oracle.compress(x, oracle.REL, 1e-4)
+    for name, c, want in _mutations(s, n):
+        announce(f"corrupt-{name}")
+        st, _ = gpu_decompress(c, n)
+        assert st == want == oracle.decompress_status(c, n)[0], name
+    announce("corrupt-truncated")
+    st, _ = gpu_decompress(s[:-4], n)
+    assert st == fsz.FSZ_ERR_CORRUPT
+
+
+def test_repeated_calls_are_deterministic():
+    x = workloads.sinusoid_field(3_000_001, 11)
+    ref = oracle.compress(x, oracle.REL, 1e-4)
+    announce("determinism")
+    xd = torch.from_numpy(x).to(_dev())
+    out = torch.zeros(fsz.fsz_compressed_bound(x.size), dtype=torch.uint8, device=_dev())
+    y = torch.zeros(x.size, dtype=torch.float32, device=_dev())
+    y_ref = oracle.decompress(ref, x.size)
+    for _ in range(20):
+        st, size = fsz.fsz_compress(xd.data_ptr(), x.size, fsz.FSZ_REL, 1e-4, out.data_ptr(),
+                                    out.numel(), _stream())
+        assert st == fsz.FSZ_OK and out[:size].cpu().numpy().tobytes() == ref
+        assert fsz.fsz_decompress(out.data_ptr(), size, y.data_ptr(), x.size, _stream()) == fsz.FSZ_OK
+        assert np.array_equal(y.cpu().numpy(), y_ref)
