@@ -1,0 +1,222 @@
+"""FSZ benchmark on one MI355X.
+
+One step = the whole hot path over the 512^3 float32 k^-3 Gaussian random
+field (512 MiB): the value-range pass once, then for each REL bound in
+{1e-2, 1e-3, 1e-4} one compression and one decompression, all enqueued
+asynchronously on one stream (inputs and outputs resident in HBM).
+
+Printed JSON line (rank 0): value = original bytes compressed + decompressed
+per second over the timed steps (GB/s, 1 GB = 1e9 B), with per-bound
+compress / decompress GB/s (4n / kernel time), compression ratios, the
+roofline of the dominant kernel measured with HIP events on the launch
+stream, and the CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+RELS = (1e-2, 1e-3, 1e-4)
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--shape", type=str, default="512,512,512",
+                    help="GRF shape (default: the 512^3 workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true", help="skip the byte comparison with the oracle")
+    return ap.parse_args()
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in the design notes but not launched.",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2607_15413_amd import fsz, workloads
+
+    shape = tuple(int(s) for s in args.shape.split(","))
+    t0 = time.time()
+    x_np = workloads.grf_field(shape, 1)
+    n = x_np.size
+    print(f"[bench] generated grf {shape} n={n} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    x = torch.from_numpy(x_np).to(dev)
+    cap = fsz.fsz_compressed_bound(n)
+    outs = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in RELS]
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    stats = torch.zeros(4, dtype=torch.int32, device=dev)
+    cres = [torch.zeros(4, dtype=torch.int32, device=dev) for _ in RELS]
+    dres = [torch.zeros(4, dtype=torch.int32, device=dev) for _ in RELS]
+
+    def check(st, what):
+        if st != fsz.FSZ_OK:
+            raise RuntimeError(f"{what}: {fsz.fsz_status_string(st)}")
+
+    def step(events=None):
+        check(fsz.fsz_field_stats(x.data_ptr(), n, stats.data_ptr(), sh), "stats")
+        for k, rel in enumerate(RELS):
+            if events is not None:
+                events[k][0].record(stream)
+            check(fsz.fsz_compress_async(x.data_ptr(), n, fsz.FSZ_REL, rel, stats.data_ptr(),
+                                         outs[k].data_ptr(), cap, cres[k].data_ptr(), sh), "compress")
+            if events is not None:
+                events[k][1].record(stream)
+                events[k][2].record(stream)
+            check(fsz.fsz_decompress_async(outs[k].data_ptr(), cap, y.data_ptr(), n,
+                                           dres[k].data_ptr(), sh), "decompress")
+            if events is not None:
+                events[k][3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ev = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in RELS]
+          for _ in range(args.steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for s in range(args.steps):
+        step(ev[s])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    ms_per_step = total_ms / args.steps
+
+    comp_ms = [np.mean([ev[s][k][0].elapsed_time(ev[s][k][1]) for s in range(args.steps)])
+               for k in range(len(RELS))]
+    dec_ms = [np.mean([ev[s][k][2].elapsed_time(ev[s][k][3]) for s in range(args.steps)])
+              for k in range(len(RELS))]
+    sizes = []
+    for k in range(len(RELS)):
+        size, st, _ = fsz.read_result(cres[k])
+        check(st, f"compress result rel={RELS[k]}")
+        _, st, _ = fsz.read_result(dres[k])
+        check(st, f"decompress result rel={RELS[k]}")
+        sizes.append(int(size))
+
+    per_bound = []
+    comp_bytes = dec_bytes = 0
+    comp_time = dec_time = 0.0
+    for k, rel in enumerate(RELS):
+        alg = 4 * n + sizes[k]  # bytes read + written by either direction
+        per_bound.append({
+            "rel": rel,
+            "cr": round(4 * n / sizes[k], 4),
+            "stream_bytes": sizes[k],
+            "compress_GBps": round(4 * n / comp_ms[k] / 1e6, 1),
+            "decompress_GBps": round(4 * n / dec_ms[k] / 1e6, 1),
+            "compress_ms": round(comp_ms[k], 4),
+            "decompress_ms": round(dec_ms[k], 4),
+            "compress_hbm_frac": round(alg / comp_ms[k] / 1e6 / HBM_PEAK_GBPS, 4),
+            "decompress_hbm_frac": round(alg / dec_ms[k] / 1e6 / HBM_PEAK_GBPS, 4),
+        })
+        comp_bytes += alg
+        dec_bytes += alg
+        comp_time += comp_ms[k]
+        dec_time += dec_ms[k]
+
+    dominant = "compress" if comp_time >= dec_time else "decompress"
+    dom_bytes, dom_time = (comp_bytes, comp_time) if dominant == "compress" else (dec_bytes, dec_time)
+    achieved = dom_bytes / dom_time / 1e6  # GB/s
+    roofline = {
+        "bound": "hbm",
+        "kernel": "compress_kernel" if dominant == "compress" else "decompress_kernel",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(dom_time / len(RELS), 4),
+        "bytes_per_launch": int(dom_bytes / len(RELS)),
+    }
+
+    value = 2 * len(RELS) * 4 * n / (ms_per_step / 1e3) / 1e9
+
+    verified = None
+    cpu = None
+    if not args.no_cpu_baseline or not args.no_verify:
+        import oracle
+
+        t_c = t_d = 0.0
+        identical = True
+        for k, rel in enumerate(RELS):
+            t = time.perf_counter()
+            ref = oracle.compress(x_np, oracle.REL, rel)
+            t_c += time.perf_counter() - t
+            t = time.perf_counter()
+            oracle.decompress(ref, n)
+            t_d += time.perf_counter() - t
+            if not args.no_verify:
+                got = outs[k][:sizes[k]].cpu().numpy().tobytes()
+                identical = identical and got == ref
+        if not args.no_verify:
+            verified = identical
+        if not args.no_cpu_baseline:
+            cpu = {
+                "value": round(2 * len(RELS) * 4 * n / (t_c + t_d) / 1e9, 4),
+                "unit": "GB/s",
+                "cores": 1,
+                "kind": "oracle",
+                "sample": f"full {shape} field, REL 1e-2/1e-3/1e-4, one compress + one decompress "
+                          f"each ({t_c:.1f}s + {t_d:.1f}s, single-threaded)",
+                "compress_GBps": round(len(RELS) * 4 * n / t_c / 1e9, 4),
+                "decompress_GBps": round(len(RELS) * 4 * n / t_d / 1e9, 4),
+            }
+
+    line = {
+        "metric": "compress/decompress GB/s on 1 MI355X (% of HBM peak) + compression ratio",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "grf-k^-3 512x512x512 float32 (512 MiB), seed 1, REL 1e-2/1e-3/1e-4; "
+                        "per step: range pass + 3 x (compress + decompress)",
+            "n": n,
+            "shape": list(shape),
+            "rel_bounds": list(RELS),
+        },
+        "compress_GBps": round(len(RELS) * 4 * n / comp_time / 1e6, 1),
+        "decompress_GBps": round(len(RELS) * 4 * n / dec_time / 1e6, 1),
+        "per_bound": per_bound,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "oracle_identical": verified,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

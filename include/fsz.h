@@ -64,6 +64,15 @@ typedef struct {
     uint32_t flags;
 } fsz_stats;
 
+/* Outcome of an asynchronous call, written to device memory by the call's
+ * kernel when it completes: size = stream bytes written (compress) or read
+ * (decompress), status = an fsz_status, epoch = library-internal call tag. */
+typedef struct {
+    uint64_t size;
+    uint32_t status;
+    uint32_t epoch;
+} fsz_result;
+
 /* Worst-case stream size in bytes for n elements (every block at the
  * format's maximum rate 31, every tile centred):
  * 32 + pad16(ceil(n/32)) + 4*ceil(n/256) + 128*ceil(n/32).  Pure host
@@ -105,6 +114,22 @@ fsz_status fsz_compress_ex(const float *d_in, size_t n, fsz_eb_mode mode, double
  * stream finished. */
 fsz_status fsz_decompress(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
                           void *stream);
+
+/* Asynchronous forms: enqueue the work on `stream` and return at once with
+ * the host-side validation status (FSZ_OK, FSZ_ERR_INVALID_ARG,
+ * FSZ_ERR_CAPACITY for out_capacity below the rate header, FSZ_ERR_CORRUPT
+ * for cmp_size < 32, FSZ_ERR_DEVICE).  The call's outcome appears in the
+ * caller-owned device struct *d_result once the stream reaches it; nothing
+ * is read back to the host, so these calls can be chained on a stream and
+ * issued from a tight loop.  fsz_compress_async runs the value-range pass
+ * first when d_stats is NULL, otherwise it reuses *d_stats.  Each call is
+ * one kernel launch (two with the range pass). */
+fsz_status fsz_compress_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                              const fsz_stats *d_stats, void *d_out, size_t out_capacity,
+                              fsz_result *d_result, void *stream);
+
+fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
+                                fsz_result *d_result, void *stream);
 
 #ifdef __cplusplus
 }

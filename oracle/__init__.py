@@ -8,7 +8,8 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB
+from .build import build as build_library
 
 OK = 0
 ERR_INVALID_ARG = 1
@@ -35,7 +36,7 @@ def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            build()
+            build_library()
         lib = ctypes.CDLL(LIB)
         u64 = ctypes.c_uint64
         p = ctypes.c_void_p

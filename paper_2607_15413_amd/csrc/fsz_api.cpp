@@ -21,11 +21,10 @@ struct Workspace {
     uint64_t flags_cap = 0;
     unsigned long long *d_ticket = nullptr;  // chunk ticket, reset by each launch's last taker
     uint32_t call = 0;                       // per-call epoch
-    Result *d_result = nullptr;
-    Result *h_result = nullptr;              // pinned host copy
-    fsz_stats *d_stats = nullptr;            // range pass output for fsz_compress
+    fsz_result *d_final = nullptr;           // outcome of blocking calls
+    fsz_result *h_final = nullptr;           // pinned host copy
+    fsz_stats *d_stats = nullptr;            // range pass output when the caller has none
     StatsPartial *d_partials = nullptr;
-    unsigned int *d_counter = nullptr;
 };
 
 std::mutex g_mu;
@@ -48,14 +47,13 @@ Workspace *get_workspace(hipStream_t s, fsz_status *st)
     ws->device = dev;
     ws->stream = s;
     bool good = ok(hipMalloc(&ws->d_ticket, sizeof(unsigned long long))) &&
-                ok(hipMalloc(&ws->d_result, sizeof(Result))) &&
-                ok(hipHostMalloc(&ws->h_result, sizeof(Result), hipHostMallocDefault)) &&
+                ok(hipMalloc(&ws->d_final, sizeof(fsz_result))) &&
+                ok(hipHostMalloc(&ws->h_final, sizeof(fsz_result), hipHostMallocDefault)) &&
                 ok(hipMalloc(&ws->d_stats, sizeof(fsz_stats))) &&
                 ok(hipMalloc(&ws->d_partials, sizeof(StatsPartial) * kStatsMaxBlocks)) &&
-                ok(hipMalloc(&ws->d_counter, sizeof(unsigned int))) &&
                 ok(hipMemset(ws->d_ticket, 0, sizeof(unsigned long long))) &&
-                ok(hipMemset(ws->d_result, 0, sizeof(Result))) &&
-                ok(hipMemset(ws->d_counter, 0, sizeof(unsigned int))) && ok(hipDeviceSynchronize());
+                ok(hipMemset(ws->d_final, 0, sizeof(fsz_result))) &&
+                ok(hipDeviceSynchronize());
     if (!good) {
         *st = FSZ_ERR_DEVICE;
         return nullptr;
@@ -95,26 +93,51 @@ bool next_epoch(Workspace *ws, uint32_t *epoch, uint32_t *flag_epoch)
     return true;
 }
 
-// Copy the result record back and wait for the stream.
-fsz_status finish(Workspace *ws, uint32_t epoch, uint64_t *size_out)
+// Blocking calls: copy the outcome back and wait for the stream.
+fsz_status finish(Workspace *ws, uint32_t epoch, size_t *size_out)
 {
-    if (!ok(hipMemcpyAsync(ws->h_result, ws->d_result, sizeof(Result), hipMemcpyDeviceToHost, ws->stream)))
+    if (!ok(hipMemcpyAsync(ws->h_final, ws->d_final, sizeof(fsz_result), hipMemcpyDeviceToHost, ws->stream)))
         return FSZ_ERR_DEVICE;
     if (!ok(hipStreamSynchronize(ws->stream))) return FSZ_ERR_DEVICE;
-    const Result r = *ws->h_result;
-    if ((uint32_t)(r.status_word >> 32) == epoch) return (fsz_status)(uint32_t)r.status_word;
-    if (size_out) {
-        if (r.size_epoch != epoch) return FSZ_ERR_DEVICE;
-        *size_out = r.size;
-    }
-    return FSZ_OK;
+    const fsz_result r = *ws->h_final;
+    if (r.epoch != epoch) return FSZ_ERR_DEVICE;
+    if (r.status == FSZ_OK && size_out) *size_out = (size_t)r.size;
+    return (fsz_status)r.status;
 }
 
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
-fsz_status compress_common(Workspace *ws, const float *d_in, uint64_t n, int mode, double value,
-                           const fsz_stats *d_stats, void *d_out, uint64_t cap, size_t *out_size)
+bool valid_bound(int mode, double value)
 {
+    return (mode == FSZ_ABS || mode == FSZ_REL) && std::isfinite(value) && value > 0.0;
+}
+
+fsz_status check_compress_args(const float *d_in, size_t n, int mode, double value, const void *d_out,
+                               size_t cap)
+{
+    if (!valid_bound(mode, value) || !d_out || (n > 0 && !d_in) || !aligned(d_in, 4) || !aligned(d_out, 4))
+        return FSZ_ERR_INVALID_ARG;
+    if (cap < kHeaderBytes + pad16(ceil_div(n, kBlock))) return FSZ_ERR_CAPACITY;
+    return FSZ_OK;
+}
+
+fsz_status check_decompress_args(const void *d_cmp, size_t cmp_size, const float *d_out, size_t n)
+{
+    if (!d_cmp || (n > 0 && !d_out) || !aligned(d_cmp, 4) || !aligned(d_out, 4)) return FSZ_ERR_INVALID_ARG;
+    if (cmp_size < (size_t)kHeaderBytes) return FSZ_ERR_CORRUPT;
+    return FSZ_OK;
+}
+
+// Enqueue (range pass if d_stats is NULL) + compression kernel.
+fsz_status enqueue_compress(Workspace *ws, const float *d_in, uint64_t n, int mode, double value,
+                            const fsz_stats *d_stats, void *d_out, uint64_t cap, fsz_result *d_final,
+                            uint32_t *epoch_out)
+{
+    if (!d_stats) {
+        StatsArgs sa{d_in, n, ws->d_stats, ws->d_partials};
+        if (!ok(launch_stats(sa, ws->stream))) return FSZ_ERR_DEVICE;
+        d_stats = ws->d_stats;
+    }
     CompressArgs a{};
     a.x = d_in;
     a.n = n;
@@ -131,17 +154,32 @@ fsz_status compress_common(Workspace *ws, const float *d_in, uint64_t n, int mod
     if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
     a.flags = ws->d_flags;
     a.ticket = ws->d_ticket;
-    a.result = ws->d_result;
+    a.final = d_final;
     if (!ok(launch_compress(a, aligned(d_in, 16), ws->stream))) return FSZ_ERR_DEVICE;
-    uint64_t size = 0;
-    fsz_status st = finish(ws, a.epoch, &size);
-    if (st == FSZ_OK) *out_size = (size_t)size;
-    return st;
+    *epoch_out = a.epoch;
+    return FSZ_OK;
 }
 
-bool valid_bound(int mode, double value)
+fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_size, float *d_out, uint64_t n,
+                              fsz_result *d_final, uint32_t *epoch_out)
 {
-    return (mode == FSZ_ABS || mode == FSZ_REL) && std::isfinite(value) && value > 0.0;
+    DecompressArgs a{};
+    a.cmp = static_cast<const uint8_t *>(d_cmp);
+    a.cmp_size = cmp_size;
+    a.out = d_out;
+    a.n = n;
+    a.ntiles = ceil_div(n, kTile);
+    a.nblocks = ceil_div(n, kBlock);
+    a.nchunks = a.ntiles ? ceil_div(a.ntiles, kTilesPerChunk) : 1;
+    a.data0 = kHeaderBytes + pad16(a.nblocks);
+    if (!ensure_flags(ws, a.nchunks)) return FSZ_ERR_DEVICE;
+    if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
+    a.flags = ws->d_flags;
+    a.ticket = ws->d_ticket;
+    a.final = d_final;
+    if (!ok(launch_decompress(a, aligned(d_out, 16), ws->stream))) return FSZ_ERR_DEVICE;
+    *epoch_out = a.epoch;
+    return FSZ_OK;
 }
 
 }  // namespace
@@ -178,65 +216,70 @@ fsz_status fsz_field_stats(const float *d_in, size_t n, fsz_stats *d_stats, void
     Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);
-    StatsArgs a{d_in, n, d_stats, ws->d_partials, ws->d_counter};
+    StatsArgs a{d_in, n, d_stats, ws->d_partials};
     return ok(launch_stats(a, ws->stream)) ? FSZ_OK : FSZ_ERR_DEVICE;
 }
 
 fsz_status fsz_compress(const float *d_in, size_t n, fsz_eb_mode mode, double value, void *d_out,
                         size_t out_capacity, size_t *out_size, void *stream)
 {
-    if (!valid_bound(mode, value) || !out_size || !d_out || (n > 0 && !d_in) || !aligned(d_in, 4) ||
-        !aligned(d_out, 4))
-        return FSZ_ERR_INVALID_ARG;
-    if (out_capacity < kHeaderBytes + pad16(ceil_div(n, kBlock))) return FSZ_ERR_CAPACITY;
-    fsz_status st = FSZ_OK;
-    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
-    if (!ws) return st;
-    std::lock_guard<std::mutex> g(ws->mu);
-    StatsArgs sa{d_in, n, ws->d_stats, ws->d_partials, ws->d_counter};
-    if (!ok(launch_stats(sa, ws->stream))) return FSZ_ERR_DEVICE;
-    return compress_common(ws, d_in, n, mode, value, ws->d_stats, d_out, out_capacity, out_size);
+    return fsz_compress_ex(d_in, n, mode, value, nullptr, d_out, out_capacity, out_size, stream);
 }
 
 fsz_status fsz_compress_ex(const float *d_in, size_t n, fsz_eb_mode mode, double value,
                            const fsz_stats *d_stats, void *d_out, size_t out_capacity, size_t *out_size,
                            void *stream)
 {
-    if (!valid_bound(mode, value) || !out_size || !d_out || !d_stats || (n > 0 && !d_in) ||
-        !aligned(d_in, 4) || !aligned(d_out, 4))
-        return FSZ_ERR_INVALID_ARG;
-    if (out_capacity < kHeaderBytes + pad16(ceil_div(n, kBlock))) return FSZ_ERR_CAPACITY;
-    fsz_status st = FSZ_OK;
+    if (!out_size) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_compress_args(d_in, n, mode, value, d_out, out_capacity);
+    if (st != FSZ_OK) return st;
     Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);
-    return compress_common(ws, d_in, n, mode, value, d_stats, d_out, out_capacity, out_size);
+    uint32_t epoch = 0;
+    st = enqueue_compress(ws, d_in, n, mode, value, d_stats, d_out, out_capacity, ws->d_final, &epoch);
+    if (st != FSZ_OK) return st;
+    return finish(ws, epoch, out_size);
 }
 
 fsz_status fsz_decompress(const void *d_cmp, size_t cmp_size, float *d_out, size_t n, void *stream)
 {
-    if (!d_cmp || (n > 0 && !d_out) || !aligned(d_cmp, 4) || !aligned(d_out, 4)) return FSZ_ERR_INVALID_ARG;
-    if (cmp_size < (size_t)kHeaderBytes) return FSZ_ERR_CORRUPT;
-    fsz_status st = FSZ_OK;
+    fsz_status st = check_decompress_args(d_cmp, cmp_size, d_out, n);
+    if (st != FSZ_OK) return st;
     Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);
-    DecompressArgs a{};
-    a.cmp = static_cast<const uint8_t *>(d_cmp);
-    a.cmp_size = cmp_size;
-    a.out = d_out;
-    a.n = n;
-    a.ntiles = ceil_div(n, kTile);
-    a.nblocks = ceil_div(n, kBlock);
-    a.nchunks = a.ntiles ? ceil_div(a.ntiles, kTilesPerChunk) : 1;
-    a.data0 = kHeaderBytes + pad16(a.nblocks);
-    if (!ensure_flags(ws, a.nchunks)) return FSZ_ERR_DEVICE;
-    if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
-    a.flags = ws->d_flags;
-    a.ticket = ws->d_ticket;
-    a.result = ws->d_result;
-    if (!ok(launch_decompress(a, aligned(d_out, 16), ws->stream))) return FSZ_ERR_DEVICE;
-    return finish(ws, a.epoch, nullptr);
+    uint32_t epoch = 0;
+    st = enqueue_decompress(ws, d_cmp, cmp_size, d_out, n, ws->d_final, &epoch);
+    if (st != FSZ_OK) return st;
+    return finish(ws, epoch, nullptr);
+}
+
+fsz_status fsz_compress_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                              const fsz_stats *d_stats, void *d_out, size_t out_capacity,
+                              fsz_result *d_result, void *stream)
+{
+    if (!d_result) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_compress_args(d_in, n, mode, value, d_out, out_capacity);
+    if (st != FSZ_OK) return st;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    uint32_t epoch = 0;
+    return enqueue_compress(ws, d_in, n, mode, value, d_stats, d_out, out_capacity, d_result, &epoch);
+}
+
+fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
+                                fsz_result *d_result, void *stream)
+{
+    if (!d_result) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_decompress_args(d_cmp, cmp_size, d_out, n);
+    if (st != FSZ_OK) return st;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    uint32_t epoch = 0;
+    return enqueue_decompress(ws, d_cmp, cmp_size, d_out, n, d_result, &epoch);
 }
 
 }  // extern "C"

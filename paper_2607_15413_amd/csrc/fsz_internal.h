@@ -30,26 +30,17 @@ constexpr int kStageWaveDwords = 64 * kStageRowDwords;
 
 // Chunk flag word for the decoupled lookback (Sec. IV-D): 2-bit state,
 // 18-bit call epoch (stale words from earlier calls read as "not ready"),
-// 44-bit byte count.
+// 1 error bit (OR-ed along the prefix), 43-bit byte count.
 constexpr uint64_t kFlagAggregate = 1;
 constexpr uint64_t kFlagInclusive = 2;
 constexpr int kEpochBits = 18;
 constexpr uint32_t kEpochMask = (1u << kEpochBits) - 1;
-constexpr int kValueBits = 44;
-constexpr uint64_t kValueMask = (1ull << kValueBits) - 1;
+constexpr int kEpochShift = 44;
+constexpr int kErrorBit = 43;
+constexpr uint64_t kValueMask = (1ull << kErrorBit) - 1;
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t pad16(uint64_t a) { return (a + 15) / 16 * 16; }
-
-// Result record in device memory, read back once per call.  status_word and
-// size_word are tagged with the call's 32-bit epoch, so no per-call reset
-// is needed: a word from an older call is simply "not written this call".
-struct Result {
-    unsigned long long status_word;  // (epoch << 32) | fsz_status, first error wins
-    unsigned long long size;         // total stream bytes (compress)
-    unsigned long long size_epoch;   // epoch of `size`
-    unsigned long long pad;
-};
 
 struct StatsPartial {
     float xmin, xmax, maxabs;
@@ -61,7 +52,6 @@ struct StatsArgs {
     uint64_t n;
     fsz_stats *out;
     StatsPartial *partials;
-    unsigned int *counter;
 };
 
 struct CompressArgs {
@@ -76,7 +66,7 @@ struct CompressArgs {
     uint32_t flag_epoch;  // 18-bit nonzero epoch (chunk flags)
     unsigned long long *flags;
     unsigned long long *ticket;  // zero between launches (self-resetting)
-    Result *result;
+    fsz_result *final;           // written by the workgroup owning the last chunk
 };
 
 struct DecompressArgs {
@@ -87,7 +77,7 @@ struct DecompressArgs {
     uint32_t epoch, flag_epoch;
     unsigned long long *flags;
     unsigned long long *ticket;  // zero between launches (self-resetting)
-    Result *result;
+    fsz_result *final;           // written by the workgroup owning the last chunk
 };
 
 // Kernel launchers (fsz_kernels.hip).

@@ -105,16 +105,13 @@ __device__ __forceinline__ uint32_t bswap32(uint32_t v) { return __builtin_bswap
 
 // ------------------------------------------------------------------ results
 
-__device__ void record_status(Result *res, uint32_t epoch, int code)
+// The call's outcome, written once per launch by the workgroup that owns the
+// last chunk (it sees the inclusive prefix, hence every chunk's error bit).
+__device__ __forceinline__ void write_final(fsz_result *final, uint64_t size, uint32_t status, uint32_t epoch)
 {
-    unsigned long long want = ((unsigned long long)epoch << 32) | (unsigned)code;
-    unsigned long long cur = __hip_atomic_load(&res->status_word, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-    while ((uint32_t)(cur >> 32) != epoch) {
-        unsigned long long prev = atomicCAS(&res->status_word, cur, want);
-        if (prev == cur) return;
-        cur = prev;
-    }
+    final->size = status == FSZ_OK ? size : 0;
+    final->status = status;
+    final->epoch = epoch;
 }
 
 // ------------------------------------------------------------------ bound
@@ -202,36 +199,43 @@ __device__ __forceinline__ unsigned long long take_ticket(unsigned long long *ti
     return t;
 }
 
-__device__ __forceinline__ unsigned long long pack_flag(uint64_t state, uint32_t ep, uint64_t v)
+__device__ __forceinline__ unsigned long long pack_flag(uint64_t state, uint32_t ep, bool err, uint64_t v)
 {
-    return (state << 62) | ((uint64_t)ep << kValueBits) | (v & kValueMask);
+    return (state << 62) | ((uint64_t)ep << kEpochShift) | ((uint64_t)err << kErrorBit) | (v & kValueMask);
 }
 
 // Decoupled lookback (Sec. IV-D, three-state flags) run by one whole wave:
 // publishes this chunk's aggregate, sums predecessors' aggregates 64 at a
 // time until an inclusive prefix is found, publishes the inclusive prefix
-// and returns the exclusive one.  Flags are read and written with
-// agent-scope atomics so that they are coherent across the 8 XCDs' L2s.
-// The spin is bounded so that every wave exits even if the flag protocol
-// were broken (then *timed_out is set and the caller reports an error).
-__device__ uint64_t lookback(unsigned long long *flags, uint64_t chunk, uint32_t ep, uint64_t total,
-                         bool *timed_out)
+// and returns the exclusive one.  Each flag word also carries an error bit
+// that is OR-ed along the prefix, so the last chunk learns whether any chunk
+// failed.  Flags are plain relaxed agent-scope atomics (coherent across the
+// 8 XCDs' L2s, no cache-flushing fences): the value travels inside the flag
+// word, so no other memory needs ordering.  The spin is bounded so that every
+// wave exits even if the protocol were broken (*err is then set).
+struct Prefix {
+    uint64_t excl;
+    bool err;
+};
+
+__device__ Prefix lookback(unsigned long long *flags, uint64_t chunk, uint32_t ep, uint64_t total, bool err)
 {
     const int lane = __lane_id();
     if (chunk == 0) {
         if (lane == 0)
-            __hip_atomic_store(&flags[0], pack_flag(kFlagInclusive, ep, total), __ATOMIC_RELAXED,
+            __hip_atomic_store(&flags[0], pack_flag(kFlagInclusive, ep, err, total), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        return 0;
+        return Prefix{0, err};
     }
     if (lane == 0)
-        __hip_atomic_store(&flags[chunk], pack_flag(kFlagAggregate, ep, total), __ATOMIC_RELAXED,
+        __hip_atomic_store(&flags[chunk], pack_flag(kFlagAggregate, ep, err, total), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     uint64_t excl = 0;
+    bool perr = false;
     long long pos = (long long)chunk - 1;
     for (uint32_t spins = 0;; spins++) {
         if (spins >= kLookbackSpinLimit) {  // a predecessor never published: give up
-            *timed_out = true;
+            perr = true;
             break;
         }
         const long long idx = pos - lane;
@@ -239,30 +243,34 @@ __device__ uint64_t lookback(unsigned long long *flags, uint64_t chunk, uint32_t
         if (idx >= 0)
             f = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         else
-            f = pack_flag(kFlagInclusive, ep, 0);
-        const bool current = (uint32_t)((f >> kValueBits) & kEpochMask) == ep;
+            f = pack_flag(kFlagInclusive, ep, false, 0);
+        const bool current = (uint32_t)((f >> kEpochShift) & kEpochMask) == ep;
         const uint32_t state = current ? (uint32_t)(f >> 62) : 0u;
         const unsigned long long not_ready = __ballot(state == 0);
         const unsigned long long incl = __ballot(state == kFlagInclusive);
         const uint64_t v = f & kValueMask;
+        const bool e = (f >> kErrorBit) & 1ull;
         if (incl != 0) {
             const int first = __builtin_ctzll(incl);
             const unsigned long long need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
             if ((not_ready & need) == 0) {
                 excl += wave_sum_u64(lane <= first ? v : 0);
+                perr = perr || (__ballot(lane <= first && e) != 0);
                 break;
             }
         } else if (not_ready == 0) {
             excl += wave_sum_u64(v);
+            perr = perr || (__ballot(e) != 0);
             pos -= 64;
             continue;
         }
         __builtin_amdgcn_s_sleep(1);
     }
+    err = err || perr;
     if (lane == 0)
-        __hip_atomic_store(&flags[chunk], pack_flag(kFlagInclusive, ep, excl + total), __ATOMIC_RELAXED,
+        __hip_atomic_store(&flags[chunk], pack_flag(kFlagInclusive, ep, err, excl + total), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-    return excl;
+    return Prefix{excl, err};
 }
 
 // ------------------------------------------------------------------ staging
@@ -314,8 +322,35 @@ __device__ __forceinline__ void load_blocks(const float *__restrict__ x, uint64_
 
 // ------------------------------------------------------------------ stats
 
+__device__ __forceinline__ void stats_combine(float &mn, float &mx, float &ma, uint32_t &nf, const StatsPartial &p)
+{
+    mn = fminf(mn, p.xmin);
+    mx = fmaxf(mx, p.xmax);
+    ma = fmaxf(ma, p.maxabs);
+    nf |= p.flags;
+}
+
+// block-wide reduction of (min, max, max|x|, non-finite); result in thread 0
+__device__ StatsPartial stats_block_reduce(float mn, float mx, float ma, uint32_t nf)
+{
+    for (int m = 32; m >= 1; m >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, m));
+        mx = fmaxf(mx, __shfl_xor(mx, m));
+        ma = fmaxf(ma, __shfl_xor(ma, m));
+        nf |= __shfl_xor(nf, m);
+    }
+    __shared__ StatsPartial wsum[kStatsThreads / 64];
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = StatsPartial{mn, mx, ma, nf};
+    __syncthreads();
+    StatsPartial p = wsum[0];
+    for (int k = 1; k < kStatsThreads / 64; k++) stats_combine(p.xmin, p.xmax, p.maxabs, p.flags, wsum[k]);
+    return p;
+}
+
+// Value-range pass, part 1: one partial (min, max, max|x|, non-finite) per
+// workgroup over a grid-stride slice of x.
 template <bool ALIGNED>
-__global__ __launch_bounds__(kStatsThreads) void stats_kernel(StatsArgs a)
+__global__ __launch_bounds__(kStatsThreads) void stats_partial_kernel(StatsArgs a)
 {
     float mn = INFINITY, mx = -INFINITY, ma = 0.0f;
     uint32_t nonfinite = 0;
@@ -344,70 +379,18 @@ __global__ __launch_bounds__(kStatsThreads) void stats_kernel(StatsArgs a)
     } else {
         for (uint64_t i = tid; i < a.n; i += nthreads) take(a.x[i]);
     }
-    for (int m = 32; m >= 1; m >>= 1) {
-        mn = fminf(mn, __shfl_xor(mn, m));
-        mx = fmaxf(mx, __shfl_xor(mx, m));
-        ma = fmaxf(ma, __shfl_xor(ma, m));
-        nonfinite |= __shfl_xor(nonfinite, m);
-    }
-    __shared__ StatsPartial wsum[kStatsThreads / 64];
-    __shared__ int is_last;
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) wsum[w] = StatsPartial{mn, mx, ma, nonfinite};
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        StatsPartial p = wsum[0];
-        for (int k = 1; k < kStatsThreads / 64; k++) {
-            p.xmin = fminf(p.xmin, wsum[k].xmin);
-            p.xmax = fmaxf(p.xmax, wsum[k].xmax);
-            p.maxabs = fmaxf(p.maxabs, wsum[k].maxabs);
-            p.flags |= wsum[k].flags;
-        }
-        uint32_t *dst = reinterpret_cast<uint32_t *>(&a.partials[blockIdx.x]);
-        __hip_atomic_store(dst + 0, __float_as_uint(p.xmin), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(dst + 1, __float_as_uint(p.xmax), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(dst + 2, __float_as_uint(p.maxabs), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(dst + 3, p.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    // last workgroup: combine every partial
-    mn = INFINITY;
-    mx = -INFINITY;
-    ma = 0.0f;
-    nonfinite = 0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(&a.partials[i]);
-        mn = fminf(mn, __uint_as_float(__hip_atomic_load(src + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-        mx = fmaxf(mx, __uint_as_float(__hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-        ma = fmaxf(ma, __uint_as_float(__hip_atomic_load(src + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-        nonfinite |= __hip_atomic_load(src + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    for (int m = 32; m >= 1; m >>= 1) {
-        mn = fminf(mn, __shfl_xor(mn, m));
-        mx = fmaxf(mx, __shfl_xor(mx, m));
-        ma = fmaxf(ma, __shfl_xor(ma, m));
-        nonfinite |= __shfl_xor(nonfinite, m);
-    }
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) wsum[w] = StatsPartial{mn, mx, ma, nonfinite};
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        StatsPartial p = wsum[0];
-        for (int k = 1; k < kStatsThreads / 64; k++) {
-            p.xmin = fminf(p.xmin, wsum[k].xmin);
-            p.xmax = fmaxf(p.xmax, wsum[k].xmax);
-            p.maxabs = fmaxf(p.maxabs, wsum[k].maxabs);
-            p.flags |= wsum[k].flags;
-        }
-        a.out->xmin = p.xmin;
-        a.out->xmax = p.xmax;
-        a.out->maxabs = p.maxabs;
-        a.out->flags = p.flags;
-        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const StatsPartial p = stats_block_reduce(mn, mx, ma, nonfinite);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = p;
+}
+
+// Value-range pass, part 2: one workgroup folds the partials into *out.
+__global__ __launch_bounds__(kStatsThreads) void stats_final_kernel(StatsArgs a, unsigned nparts)
+{
+    float mn = INFINITY, mx = -INFINITY, ma = 0.0f;
+    uint32_t nf = 0;
+    for (unsigned i = threadIdx.x; i < nparts; i += blockDim.x) stats_combine(mn, mx, ma, nf, a.partials[i]);
+    const StatsPartial p = stats_block_reduce(mn, mx, ma, nf);
+    if (threadIdx.x == 0) *a.out = fsz_stats{p.xmin, p.xmax, p.maxabs, p.flags};
 }
 
 // ------------------------------------------------------------------ compress
@@ -436,14 +419,11 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
     if (tid == 0) s_chunk = take_ticket(a.ticket, a.nchunks);
     __syncthreads();
     const uint64_t chunk = s_chunk;
-    if (chunk >= a.nchunks) {  // inconsistent ticket counter: never index past the flags
-        if (tid == 0) record_status(a.result, a.epoch, FSZ_ERR_DEVICE);
-        return;
-    }
+    if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
 
     const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
     if (R.status != FSZ_OK) {
-        if (chunk == 0 && tid == 0) record_status(a.result, a.epoch, R.status);
+        if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
         return;
     }
 
@@ -586,14 +566,14 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
 
     // ---- step 4: device-wide exclusive prefix by decoupled lookback
     if (w == 0) {
-        bool timed_out = false;
-        const uint64_t base = lookback(a.flags, chunk, a.flag_epoch, chunk_total, &timed_out);
+        const Prefix pre = lookback(a.flags, chunk, a.flag_epoch, chunk_total, false);
         if (lane == 0) {
-            s_base = base;
-            if (timed_out) record_status(a.result, a.epoch, FSZ_ERR_DEVICE);
+            s_base = pre.excl;
             if (chunk == a.nchunks - 1) {
-                const uint64_t total = a.data0 + base + chunk_total;
-                if (total <= a.capacity) {
+                const uint64_t total = a.data0 + pre.excl + chunk_total;
+                uint32_t st = pre.err ? (uint32_t)FSZ_ERR_DEVICE : (uint32_t)FSZ_OK;
+                if (st == FSZ_OK && total > a.capacity) st = FSZ_ERR_CAPACITY;
+                if (st == FSZ_OK) {
                     uint32_t *h = reinterpret_cast<uint32_t *>(a.out);
                     h[0] = 0x315A5346u;  // "FSZ1"
                     h[1] = 1u | ((uint32_t)a.mode << 16) | (R.flags << 24);
@@ -604,19 +584,14 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
                     h[6] = (uint32_t)total;
                     h[7] = (uint32_t)(total >> 32);
                     for (uint64_t k = kHeaderBytes + a.nblocks; k < a.data0; k++) a.out[k] = 0;
-                    a.result->size = total;
-                    a.result->size_epoch = a.epoch;
                 }
+                write_final(a.final, total, st, a.epoch);
             }
         }
     }
     __syncthreads();
     const uint64_t base = s_base;
-    if (a.data0 + base + chunk_total > a.capacity) {
-        if (tid == 0) record_status(a.result, a.epoch, FSZ_ERR_CAPACITY);
-        return;
-    }
-    if (tile0 >= a.ntiles) return;
+    if (a.data0 + base + chunk_total > a.capacity || tile0 >= a.ntiles) return;
 
     // ---- step 5: encode the selected variant into the wave's LDS region
     if (cnt > 0 && j == 0 && cent) st[tile_excl >> 2] = (uint32_t)mu;
@@ -673,10 +648,7 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
     }
     __syncthreads();
     const uint64_t chunk = s_chunk;
-    if (chunk >= a.nchunks) {  // inconsistent ticket counter: never index past the flags
-        if (tid == 0) record_status(a.result, a.epoch, FSZ_ERR_DEVICE);
-        return;
-    }
+    if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
 
     // ---- header validation (same for every workgroup)
     const uint32_t *h = reinterpret_cast<const uint32_t *>(a.cmp);
@@ -698,7 +670,7 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
         }
     }
     if (hst != FSZ_OK) {
-        if (chunk == 0 && tid == 0) record_status(a.result, a.epoch, hst);
+        if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, hst, a.epoch);
         return;
     }
 
@@ -707,7 +679,6 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
     const bool tile_ok = tile < a.ntiles;
     const uint64_t gblock = tile * kBlocksPerTile + j;
     const bool blk_ok = gblock < a.nblocks;
-    const uint64_t eblk = gblock * kBlock;
 
     // ---- steps 1-2: rates, tile metadata, block and tile sizes
     const uint32_t rb = blk_ok ? a.cmp[kHeaderBytes + gblock] : 0u;
@@ -734,25 +705,19 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
 
     // ---- step 3: offsets by decoupled lookback
     if (w == 0) {
-        bool timed_out = false;
-        const uint64_t base = lookback(a.flags, chunk, a.flag_epoch, chunk_total, &timed_out);
+        const Prefix pre = lookback(a.flags, chunk, a.flag_epoch, chunk_total, s_bad != 0);
         if (lane == 0) {
-            s_base = base;
-            if (timed_out) record_status(a.result, a.epoch, FSZ_ERR_DEVICE);
+            s_base = pre.excl;
             if (chunk == a.nchunks - 1) {
-                bool ok = a.data0 + base + chunk_total == total;
-                for (uint64_t k = kHeaderBytes + a.nblocks; k < a.data0; k++) ok = ok && a.cmp[k] == 0;
-                if (!ok) s_bad = 1;
+                bool ok = !pre.err && a.data0 + pre.excl + chunk_total == total;
+                for (uint64_t k = kHeaderBytes + a.nblocks; ok && k < a.data0; k++) ok = a.cmp[k] == 0;
+                write_final(a.final, total, ok ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT, a.epoch);
             }
         }
     }
     __syncthreads();
     const uint64_t base = s_base;
-    if (s_bad || a.data0 + base + chunk_total > total) {
-        if (tid == 0) record_status(a.result, a.epoch, FSZ_ERR_CORRUPT);
-        return;
-    }
-    if (tile0 >= a.ntiles) return;
+    if (s_bad || a.data0 + base + chunk_total > total || tile0 >= a.ntiles) return;
 
     // ---- step 4: decode + bit-unshuffle
     const uint8_t *tile_data = a.cmp + a.data0 + base + wave_base;
@@ -838,12 +803,13 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
 
 hipError_t launch_stats(const StatsArgs &a, hipStream_t s)
 {
-    uint64_t want = ceil_div(a.n, (uint64_t)kStatsThreads * 16);
-    unsigned grid = (unsigned)(want < 1 ? 1 : (want > kStatsMaxBlocks ? kStatsMaxBlocks : want));
+    const uint64_t want = ceil_div(a.n, (uint64_t)kStatsThreads * 16);
+    const unsigned grid = (unsigned)(want < 1 ? 1 : (want > kStatsMaxBlocks ? kStatsMaxBlocks : want));
     if ((reinterpret_cast<uintptr_t>(a.x) & 15u) == 0)
-        hipLaunchKernelGGL(stats_kernel<true>, dim3(grid), dim3(kStatsThreads), 0, s, a);
+        hipLaunchKernelGGL(stats_partial_kernel<true>, dim3(grid), dim3(kStatsThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(stats_kernel<false>, dim3(grid), dim3(kStatsThreads), 0, s, a);
+        hipLaunchKernelGGL(stats_partial_kernel<false>, dim3(grid), dim3(kStatsThreads), 0, s, a);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kStatsThreads), 0, s, a, grid);
     return hipGetLastError();
 }
 

@@ -39,6 +39,8 @@ EXPORTS = (
     "fsz_compress",
     "fsz_compress_ex",
     "fsz_decompress",
+    "fsz_compress_async",
+    "fsz_decompress_async",
 )
 
 
@@ -51,6 +53,10 @@ class FszError(RuntimeError):
 class FszStats(ctypes.Structure):
     _fields_ = [("xmin", ctypes.c_float), ("xmax", ctypes.c_float), ("maxabs", ctypes.c_float),
                 ("flags", ctypes.c_uint32)]
+
+
+class FszResult(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint64), ("status", ctypes.c_uint32), ("epoch", ctypes.c_uint32)]
 
 
 _lib = None
@@ -80,6 +86,10 @@ def load_library():
     lib.fsz_compress_ex.restype = ctypes.c_int
     lib.fsz_decompress.argtypes = [vp, sz, vp, sz, vp]
     lib.fsz_decompress.restype = ctypes.c_int
+    lib.fsz_compress_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, vp, sz, vp, vp]
+    lib.fsz_compress_async.restype = ctypes.c_int
+    lib.fsz_decompress_async.argtypes = [vp, sz, vp, sz, vp, vp]
+    lib.fsz_decompress_async.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -119,6 +129,25 @@ def fsz_compress_ex(d_in: int, n: int, mode: int, value: float, d_stats: int, d_
 
 def fsz_decompress(d_cmp: int, cmp_size: int, d_out: int, n: int, stream=None) -> int:
     return load_library().fsz_decompress(d_cmp, cmp_size, d_out, n, stream)
+
+
+def fsz_compress_async(d_in: int, n: int, mode: int, value: float, d_stats, d_out: int,
+                       out_capacity: int, d_result: int, stream=None) -> int:
+    """Enqueue only; the outcome lands in the device fsz_result at d_result."""
+    return load_library().fsz_compress_async(d_in, n, mode, value, d_stats, d_out, out_capacity,
+                                             d_result, stream)
+
+
+def fsz_decompress_async(d_cmp: int, cmp_size: int, d_out: int, n: int, d_result: int,
+                         stream=None) -> int:
+    return load_library().fsz_decompress_async(d_cmp, cmp_size, d_out, n, d_result, stream)
+
+
+def read_result(result_tensor):
+    """(size, status, epoch) from a 16-byte device tensor holding an fsz_result."""
+    raw = result_tensor.cpu().numpy().tobytes()[:16]
+    r = FszResult.from_buffer_copy(raw)
+    return r.size, r.status, r.epoch
 
 
 # ----------------------------------------------------------------- torch plumbing

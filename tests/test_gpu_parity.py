@@ -245,3 +245,35 @@ def test_repeated_calls_are_deterministic():
         assert st == fsz.FSZ_OK and out[:size].cpu().numpy().tobytes() == ref
         assert fsz.fsz_decompress(out.data_ptr(), size, y.data_ptr(), x.size, _stream()) == fsz.FSZ_OK
         assert np.array_equal(y.cpu().numpy(), y_ref)
+
+
+def test_async_calls_chain_on_stream():
+    """Async forms: no host read between calls; outcomes land in device fsz_result structs."""
+    x = workloads.sinusoid_field(500_001, 8)
+    announce("async chain")
+    xd = torch.from_numpy(x).to(_dev())
+    cap = fsz.fsz_compressed_bound(x.size)
+    out = torch.zeros(cap, dtype=torch.uint8, device=_dev())
+    y = torch.zeros(x.size, dtype=torch.float32, device=_dev())
+    stats = torch.zeros(4, dtype=torch.int32, device=_dev())
+    r1 = torch.zeros(4, dtype=torch.int32, device=_dev())
+    r2 = torch.zeros(4, dtype=torch.int32, device=_dev())
+    assert fsz.fsz_field_stats(xd.data_ptr(), x.size, stats.data_ptr(), _stream()) == fsz.FSZ_OK
+    assert fsz.fsz_compress_async(xd.data_ptr(), x.size, fsz.FSZ_REL, 1e-3, stats.data_ptr(),
+                                  out.data_ptr(), cap, r1.data_ptr(), _stream()) == fsz.FSZ_OK
+    # decompress straight from the capacity-sized buffer: the header carries the length
+    assert fsz.fsz_decompress_async(out.data_ptr(), cap, y.data_ptr(), x.size, r2.data_ptr(),
+                                    _stream()) == fsz.FSZ_OK
+    ref = oracle.compress(x, oracle.REL, 1e-3)
+    size, st, _ = fsz.read_result(r1)
+    assert st == fsz.FSZ_OK and size == len(ref)
+    assert out[:size].cpu().numpy().tobytes() == ref
+    size2, st2, _ = fsz.read_result(r2)
+    assert st2 == fsz.FSZ_OK and size2 == len(ref)
+    assert np.array_equal(y.cpu().numpy(), oracle.decompress(ref, x.size))
+    # the range pass runs inside the call when no stats are given; errors arrive on device
+    bad = xd.clone()
+    bad[1234] = float("nan")
+    assert fsz.fsz_compress_async(bad.data_ptr(), x.size, fsz.FSZ_REL, 1e-3, None, out.data_ptr(),
+                                  cap, r1.data_ptr(), _stream()) == fsz.FSZ_OK
+    assert fsz.read_result(r1)[1] == fsz.FSZ_ERR_NONFINITE
