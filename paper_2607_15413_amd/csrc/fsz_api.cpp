@@ -1,6 +1,7 @@
 // C ABI of libfsz.so: argument validation, per-(device, stream) workspace,
 // kernel launches and the single device->host status read per call.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -10,6 +11,26 @@
 #include "fsz_internal.h"
 
 using namespace fsz;
+
+namespace fsz {
+const Tuning &tuning()
+{
+    static const Tuning t = [] {
+        Tuning v;
+        if (const char *e = std::getenv("FSZ_STAGED")) {  // letters: c = compress, d = decompress
+            v.staged_compress = std::strchr(e, 'c') != nullptr;
+            v.staged_decompress = std::strchr(e, 'd') != nullptr;
+            v.staged_compress_loads = std::strchr(e, 'l') != nullptr;
+        }
+        if (const char *e = std::getenv("FSZ_GRID_FACTOR")) {
+            const int f = std::atoi(e);
+            if (f >= 1 && f <= 64) v.grid_factor = f;
+        }
+        return v;
+    }();
+    return t;
+}
+}  // namespace fsz
 
 namespace {
 
@@ -31,6 +52,7 @@ std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
 
 bool ok(hipError_t e) { return e == hipSuccess; }
+
 
 Workspace *get_workspace(hipStream_t s, fsz_status *st)
 {
@@ -155,7 +177,7 @@ fsz_status enqueue_compress(Workspace *ws, const float *d_in, uint64_t n, int mo
     a.flags = ws->d_flags;
     a.ticket = ws->d_ticket;
     a.final = d_final;
-    if (!ok(launch_compress(a, aligned(d_in, 16), ws->stream))) return FSZ_ERR_DEVICE;
+    if (!ok(launch_compress(a, aligned(d_in, 16), tuning().staged_compress, ws->stream))) return FSZ_ERR_DEVICE;
     *epoch_out = a.epoch;
     return FSZ_OK;
 }
@@ -177,7 +199,7 @@ fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_siz
     a.flags = ws->d_flags;
     a.ticket = ws->d_ticket;
     a.final = d_final;
-    if (!ok(launch_decompress(a, aligned(d_out, 16), ws->stream))) return FSZ_ERR_DEVICE;
+    if (!ok(launch_decompress(a, aligned(d_out, 16), tuning().staged_decompress, ws->stream))) return FSZ_ERR_DEVICE;
     *epoch_out = a.epoch;
     return FSZ_OK;
 }

@@ -82,7 +82,21 @@ struct DecompressArgs {
 
 // Kernel launchers (fsz_kernels.hip).
 hipError_t launch_stats(const StatsArgs &a, hipStream_t s);
-hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, hipStream_t s);
-hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, hipStream_t s);
+// staged = write outputs through an LDS staging buffer with coalesced stores
+// instead of lane-per-block stores.
+hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s);
+hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s);
+
+// Launch tuning knobs, process-wide, read once from the environment:
+// FSZ_STAGED (letters c / d / l: stage compress output / decompress output /
+// compress input through LDS) and FSZ_GRID_FACTOR (persistent workgroups per
+// CU slot, default 1).
+struct Tuning {
+    bool staged_compress = true;
+    bool staged_decompress = true;
+    bool staged_compress_loads = true;
+    int grid_factor = 1;
+};
+const Tuning &tuning();
 
 }  // namespace fsz

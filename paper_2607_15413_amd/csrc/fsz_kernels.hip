@@ -103,6 +103,57 @@ __device__ __forceinline__ uint32_t block_bytes(uint32_t r) { return r ? 4u + 4u
 
 __device__ __forceinline__ uint32_t bswap32(uint32_t v) { return __builtin_bswap32(v); }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ bit planes
+//
+// Bit-shuffle (Sec. IV-C) as an in-register transpose.  A block's residual
+// codes c[i] = (|l_i| << 1) | sign_i hold the sign in bit 0 and magnitude bit
+// p in bit p + 1, so the block's stored words are exactly the bit planes of
+// the codes: word b = bit b of every code (word 0 = sign map, word b = plane
+// b - 1).  Stored words are written most-significant byte first, so in the
+// little-endian dword element i sits at bit i ^ 7.
+//
+// Eight planes at a time (byte g of the codes): registers R[rho] take byte g
+// of codes 8k + 7 - rho in their byte k; three delta-swap stages exchange the
+// register index with the bit-in-byte index, after which R[p] is the stored
+// dword of plane word 8g + p.  The same stages invert the mapping on decode.
+
+// byte g of a0..a3 packed into bytes 0..3
+__device__ __forceinline__ uint32_t pack_byte_g(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t g)
+{
+    const uint32_t sel = g | ((4u + g) << 8) | 0x0C0C0000u;
+    const uint32_t t01 = __builtin_amdgcn_perm(a1, a0, sel);
+    const uint32_t t23 = __builtin_amdgcn_perm(a3, a2, sel);
+    return __builtin_amdgcn_perm(t23, t01, 0x05040100u);
+}
+
+template <int D, uint32_t M>
+__device__ __forceinline__ void delta_swap(uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t nlo = (M & (hi << D)) | (~M & lo);
+    const uint32_t nhi = (M & hi) | (~M & (lo >> D));
+    lo = nlo;
+    hi = nhi;
+}
+
+// swaps the register index (0..7) with the bit-in-byte index of every byte
+__device__ __forceinline__ void transpose8(uint32_t (&R)[8])
+{
+    delta_swap<1, 0xAAAAAAAAu>(R[0], R[1]);
+    delta_swap<1, 0xAAAAAAAAu>(R[2], R[3]);
+    delta_swap<1, 0xAAAAAAAAu>(R[4], R[5]);
+    delta_swap<1, 0xAAAAAAAAu>(R[6], R[7]);
+    delta_swap<2, 0xCCCCCCCCu>(R[0], R[2]);
+    delta_swap<2, 0xCCCCCCCCu>(R[1], R[3]);
+    delta_swap<2, 0xCCCCCCCCu>(R[4], R[6]);
+    delta_swap<2, 0xCCCCCCCCu>(R[5], R[7]);
+    delta_swap<4, 0xF0F0F0F0u>(R[0], R[4]);
+    delta_swap<4, 0xF0F0F0F0u>(R[1], R[5]);
+    delta_swap<4, 0xF0F0F0F0u>(R[2], R[6]);
+    delta_swap<4, 0xF0F0F0F0u>(R[3], R[7]);
+}
+
 // ------------------------------------------------------------------ results
 
 // The call's outcome, written once per launch by the workgroup that owns the
@@ -189,13 +240,16 @@ __device__ Resolved resolve_bound(const fsz_stats *stp, int mode, double value, 
 
 constexpr uint32_t kLookbackSpinLimit = 1u << 22;
 
-// Chunk id from the launch's ticket counter; the workgroup that takes the
-// last ticket resets the counter for the next launch on the stream.
-__device__ __forceinline__ unsigned long long take_ticket(unsigned long long *ticket, uint64_t nchunks)
+// Chunk ids come from the launch's ticket counter, so a chunk is only ever
+// owned by a running workgroup and the lookback always makes progress.
+// A grid of G workgroups takes `takes` tickets in total (G for one chunk per
+// workgroup; nchunks + G for a persistent grid, whose workgroups take tickets
+// until one is out of range); the last take resets the counter for the next
+// launch on the stream.
+__device__ __forceinline__ unsigned long long take_ticket(unsigned long long *ticket, uint64_t takes)
 {
     const unsigned long long t = atomicAdd(ticket, 1ull);
-    if (t == nchunks - 1)
-        __hip_atomic_store(ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == takes - 1) __hip_atomic_store(ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return t;
 }
 
@@ -218,53 +272,67 @@ struct Prefix {
     bool err;
 };
 
-__device__ Prefix lookback(unsigned long long *flags, uint64_t chunk, uint32_t ep, uint64_t total, bool err)
+// Publishes this chunk's aggregate (chunk 0 publishes its inclusive prefix).
+__device__ __forceinline__ void publish_aggregate(unsigned long long *flags, uint64_t chunk, uint32_t ep,
+                                                  uint64_t total, bool err)
+{
+    __hip_atomic_store(&flags[chunk], pack_flag(chunk == 0 ? kFlagInclusive : kFlagAggregate, ep, err, total),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits for the exclusive prefix of `chunk` (whose aggregate is published)
+// and publishes its inclusive prefix.  Run by one whole wave.  A probe reads
+// the 64 nearest unresolved predecessors; while one of them is not ready the
+// wave re-reads only that single flag word (with a short sleep), so waiting
+// chunks add little memory traffic, and then probes the window again.
+__device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint32_t ep, uint64_t total, bool err)
 {
     const int lane = __lane_id();
-    if (chunk == 0) {
-        if (lane == 0)
-            __hip_atomic_store(&flags[0], pack_flag(kFlagInclusive, ep, err, total), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        return Prefix{0, err};
-    }
-    if (lane == 0)
-        __hip_atomic_store(&flags[chunk], pack_flag(kFlagAggregate, ep, err, total), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    if (chunk == 0) return Prefix{0, err};
     uint64_t excl = 0;
     bool perr = false;
     long long pos = (long long)chunk - 1;
-    for (uint32_t spins = 0;; spins++) {
-        if (spins >= kLookbackSpinLimit) {  // a predecessor never published: give up
-            perr = true;
-            break;
-        }
+    uint32_t spins = 0;
+    auto state_of = [&](unsigned long long f) -> uint32_t {
+        return (uint32_t)((f >> kEpochShift) & kEpochMask) == ep ? (uint32_t)(f >> 62) : 0u;
+    };
+    for (;;) {
         const long long idx = pos - lane;
-        unsigned long long f;
-        if (idx >= 0)
-            f = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            f = pack_flag(kFlagInclusive, ep, false, 0);
-        const bool current = (uint32_t)((f >> kEpochShift) & kEpochMask) == ep;
-        const uint32_t state = current ? (uint32_t)(f >> 62) : 0u;
+        const unsigned long long f =
+            idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : pack_flag(kFlagInclusive, ep, false, 0);
+        const uint32_t state = state_of(f);
         const unsigned long long not_ready = __ballot(state == 0);
         const unsigned long long incl = __ballot(state == kFlagInclusive);
         const uint64_t v = f & kValueMask;
         const bool e = (f >> kErrorBit) & 1ull;
-        if (incl != 0) {
-            const int first = __builtin_ctzll(incl);
-            const unsigned long long need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
-            if ((not_ready & need) == 0) {
+        const unsigned long long need =
+            incl ? (__builtin_ctzll(incl) >= 63 ? ~0ull : ((2ull << __builtin_ctzll(incl)) - 1ull)) : ~0ull;
+        if ((not_ready & need) == 0) {
+            if (incl != 0) {
+                const int first = __builtin_ctzll(incl);
                 excl += wave_sum_u64(lane <= first ? v : 0);
                 perr = perr || (__ballot(lane <= first && e) != 0);
                 break;
             }
-        } else if (not_ready == 0) {
             excl += wave_sum_u64(v);
             perr = perr || (__ballot(e) != 0);
             pos -= 64;
             continue;
         }
-        __builtin_amdgcn_s_sleep(1);
+        // wait on the nearest predecessor that is not ready yet
+        const long long widx = pos - __builtin_ctzll(not_ready & need);
+        for (;;) {
+            if (++spins >= kLookbackSpinLimit) break;
+            __builtin_amdgcn_s_sleep(2);
+            const unsigned long long g =
+                __hip_atomic_load(&flags[widx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (state_of(g) != 0) break;
+        }
+        if (spins >= kLookbackSpinLimit) {  // a predecessor never published: give up
+            perr = true;
+            break;
+        }
     }
     err = err || perr;
     if (lane == 0)
@@ -275,12 +343,35 @@ __device__ Prefix lookback(unsigned long long *flags, uint64_t chunk, uint32_t e
 
 // ------------------------------------------------------------------ staging
 
-// Loads the wave's 8 tiles (2048 floats starting at element e0) with
-// coalesced loads and hands lane L the 32 floats of block L via LDS.
+// Lane-per-block loads straight from HBM: lane L reads its block's 128
+// contiguous bytes (8 x 16 B); the wave's 8 loads cover 64 whole blocks.
 // Elements at or beyond n read as +0.
 template <bool ALIGNED>
-__device__ __forceinline__ void load_blocks(const float *__restrict__ x, uint64_t n, uint64_t e0,
-                                            uint32_t *st, int lane, float (&v)[32])
+__device__ __forceinline__ void load_block(const float *__restrict__ x, uint64_t eblk, int cnt, float (&v)[32])
+{
+    if (ALIGNED && cnt == 32) {
+        const f4 *p = reinterpret_cast<const f4 *>(x + eblk);
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const f4 f = __builtin_nontemporal_load(p + k);
+            v[4 * k + 0] = f.x;
+            v[4 * k + 1] = f.y;
+            v[4 * k + 2] = f.z;
+            v[4 * k + 3] = f.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 32; i++) v[i] = i < cnt ? x[eblk + i] : 0.0f;
+    }
+}
+
+// Coalesced loads of the wave's 8 tiles (2048 floats from element e0, 16 B
+// per lane per instruction), handed to the lane-per-block layout through LDS
+// (rows padded to 36 dwords so that neither side has bank conflicts).
+// Elements at or beyond n read as +0.
+template <bool ALIGNED>
+__device__ __forceinline__ void load_blocks_staged(const float *__restrict__ x, uint64_t n, uint64_t e0, uint32_t *st,
+                                                   int lane, float (&v)[32])
 {
     const bool full = e0 + 2048 <= n;
     if (ALIGNED) {
@@ -288,16 +379,16 @@ __device__ __forceinline__ void load_blocks(const float *__restrict__ x, uint64_
         for (int k = 0; k < 8; k++) {
             const int p = k * 64 + lane;  // 16-byte piece of the wave's 8 KiB
             const uint64_t e = e0 + 4ull * p;
-            float4 f;
+            f4 f;
             if (full || e + 4 <= n) {
-                f = *reinterpret_cast<const float4 *>(x + e);
+                f = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(x + e));
             } else {
                 f.x = e + 0 < n ? x[e + 0] : 0.0f;
                 f.y = e + 1 < n ? x[e + 1] : 0.0f;
                 f.z = e + 2 < n ? x[e + 2] : 0.0f;
                 f.w = e + 3 < n ? x[e + 3] : 0.0f;
             }
-            *reinterpret_cast<float4 *>(st + (p >> 3) * kStageRowDwords + (p & 7) * 4) = f;
+            *reinterpret_cast<f4 *>(st + (p >> 3) * kStageRowDwords + (p & 7) * 4) = f;
         }
     } else {
 #pragma unroll 8
@@ -312,12 +403,14 @@ __device__ __forceinline__ void load_blocks(const float *__restrict__ x, uint64_
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
     for (int k = 0; k < 8; k++) {
-        const float4 f = *reinterpret_cast<const float4 *>(st + lane * kStageRowDwords + k * 4);
+        const f4 f = *reinterpret_cast<const f4 *>(st + lane * kStageRowDwords + k * 4);
         v[4 * k + 0] = f.x;
         v[4 * k + 1] = f.y;
         v[4 * k + 2] = f.z;
         v[4 * k + 3] = f.w;
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
 // ------------------------------------------------------------------ stats
@@ -395,57 +488,132 @@ __global__ __launch_bounds__(kStatsThreads) void stats_final_kernel(StatsArgs a,
 
 // ------------------------------------------------------------------ compress
 
-// Compression kernel: Sec. III-A steps 1-5 in one launch.
-//   1 quantize + cross-block LZ1/LZ2 residuals (Sec. IV-A, Eq. (2))
-//   2 four-way evaluation (Sec. IV-B, Eq. (3)-(4)): blocks 1..7 have one rate
-//     per order; block 0 is re-rated per variant from q0, q1 - 2 q0 and mu
-//   3 adaptive select (strict minimum in the order LZ1, LZ2, LZ1c, LZ2c)
-//     and the rate header
-//   4 chunk offsets by decoupled lookback (Sec. IV-D)
-//   5 fixed-length sign / bit-plane encoding (Sec. IV-C), staged in LDS and
-//     written with coalesced stores
-template <bool ALIGNED>
-__global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
-{
-    __shared__ __attribute__((aligned(16))) uint32_t stage[kWaves * kStageWaveDwords];
-    __shared__ uint32_t s_wave_total[kWaves];
-    __shared__ unsigned long long s_chunk, s_base;
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(a, max(b, c)); }
+__device__ __forceinline__ int min3i(int a, int b, int c) { return min(a, min(b, c)); }
 
+// Quantization (Sec. IV-B, q = round(x / (2 eb)) read as rint(fl(x * inv))):
+// for |t| < 2^22 the binary32 sum t + 1.5 * 2^23 rounds t to the nearest
+// integer with ties to even and holds it in the low mantissa bits, so
+// bits(fl(fl(x * inv) + 1.5 * 2^23)) = kQBias + rint(fl(x * inv)) exactly.
+// The bias cancels in every Lorenzo difference; |q| <= 2^21 + 1 follows from
+// the step tightening of the error-bound resolution.
+constexpr float kQMagic = 12582912.0f;  // 1.5 * 2^23
+constexpr int kQBias = 0x4B400000;       // bits of kQMagic
+
+// Extrema of the LZ1 / LZ2 residual magnitudes of one block (Sec. IV-A,
+// Eq. (2); Sec. IV-B) from biased quantized values B.  The predictor state
+// (carry_b = biased q of the previous block's last element, carry_l1 = its
+// LZ1 residual) crosses the block boundary; at a tile start q[-1] = q[-2] = 0.
+// Block 0 of a tile (j == 0) leaves its first one (LZ1) or two (LZ2)
+// residuals out: they are re-rated per variant.  Slots whose bit in vm is
+// clear lie past the end of the field and carry residual 0.
+template <bool FULL>
+__device__ __forceinline__ void block_extrema(const int (&B)[32], int carry_b, int carry_l1, int j, uint32_t vm,
+                                              uint32_t &a1, uint32_t &a2, int &l2_1)
+{
+    auto live = [&](int i, int v) { return FULL ? v : (v & ((int)(vm << (31 - i)) >> 31)); };
+    const int d0 = B[0] - carry_b, d1 = B[1] - B[0], d2 = B[2] - B[1];
+    const int l1_0 = live(0, d0), l2_0 = live(0, d0 - carry_l1);
+    const int l1_1 = live(1, d1), l2_1v = live(1, d1 - d0);
+    const int l1_2 = live(2, d2), l2_2 = live(2, d2 - d1);
+    l2_1 = l2_1v;
+    // neutral substitutes for the excluded leading residuals of block 0
+    const int e10 = j ? l1_0 : l1_1;
+    const int e20 = j ? l2_0 : l2_2;
+    const int e21 = j ? l2_1v : l2_2;
+    int mx1 = max3i(e10, l1_1, l1_2), mn1 = min3i(e10, l1_1, l1_2);
+    int mx2 = max3i(e20, e21, l2_2), mn2 = min3i(e20, e21, l2_2);
+    int pl = d2;
+#pragma unroll
+    for (int i = 3; i < 31; i += 2) {
+        const int da = B[i] - B[i - 1];
+        const int db = B[i + 1] - B[i];
+        const int l1a = live(i, da), l2a = live(i, da - pl);
+        const int l1b = live(i + 1, db), l2b = live(i + 1, db - da);
+        pl = db;
+        mx1 = max3i(mx1, l1a, l1b);
+        mn1 = min3i(mn1, l1a, l1b);
+        mx2 = max3i(mx2, l2a, l2b);
+        mn2 = min3i(mn2, l2a, l2b);
+        __builtin_amdgcn_sched_barrier(0);  // stream: keep few residuals live at a time
+    }
+    const int d31 = B[31] - B[30];
+    const int l1z = live(31, d31), l2z = live(31, d31 - pl);
+    mx1 = max(mx1, l1z);
+    mn1 = min(mn1, l1z);
+    mx2 = max(mx2, l2z);
+    mn2 = min(mn2, l2z);
+    a1 = max(uabs(mx1), uabs(mn1));
+    a2 = max(uabs(mx2), uabs(mn2));
+}
+
+// Residual codes of the selected variant, in place: code = (|e| << 1) | sign.
+// ORDER: 1 or 2 when the whole wave uses that order, 0 = per-tile order2.
+// Codes of slots past the end of the field are garbage; the encoder clears
+// them in the transposed plane words.
+template <int ORDER>
+__device__ __forceinline__ void block_codes(int (&B)[32], int carry_b, int carry_l1, int j, int order2, int cent,
+                                            int mu)
+{
+    const int om = -order2;  // all ones for LZ2
+    int pl = carry_l1;
+    int pb = carry_b;
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        const int bi = B[i];
+        const int l1 = bi - pb;
+        int e = ORDER == 1 ? l1 : (ORDER == 2 ? l1 - pl : l1 - (pl & om));
+        pb = bi;
+        pl = l1;
+        if (i == 0 && j == 0 && cent) e = bi - kQBias - mu;
+        if (i == 1 && j == 0 && cent) e = e + (ORDER == 1 ? 0 : (ORDER == 2 ? mu : (mu & om)));
+        const uint32_t m = (uint32_t)max(e, -e);
+        B[i] = (int)__builtin_amdgcn_alignbit(m, (uint32_t)e, 31);  // (|e| << 1) | (e >> 31)
+    }
+}
+
+// Per-lane result of the rate pass of one chunk, kept until its encode.
+struct ChunkState {
+    uint64_t chunk;
+    int carry_b, carry_l1, mu;
+    uint32_t vm, r, blk_off, tile_excl, wave_total;
+    int order2, cent;
+};
+
+struct CompressShared {
+    uint32_t wave_total[2][kWaves];
+    unsigned long long base;
+    unsigned long long ticket[2];  // alternating broadcast slots
+};
+
+// Rate pass of one chunk (8 tiles per wave), Sec. III-A steps 1-3:
+//   1 quantize + cross-block LZ1/LZ2 residuals
+//   2 four-way evaluation (Eq. (3)-(4)): blocks 1..7 have one rate per order;
+//     block 0 is re-rated per variant from q0, q1 - 2 q0 and mu
+//   3 adaptive select (strict minimum in the order LZ1, LZ2, LZ1c, LZ2c),
+//     rate header; the chunk's byte count is published for the lookback.
+// On return x holds the biased quantized values.
+__device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, const Resolved &R, uint64_t chunk,
+                                                     int (&x)[32], int slot, CompressShared &sh)
+{
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
-    const int j = lane & 7;  // block within the tile
-
-    if (tid == 0) s_chunk = take_ticket(a.ticket, a.nchunks);
-    __syncthreads();
-    const uint64_t chunk = s_chunk;
-    if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
-
-    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
-    if (R.status != FSZ_OK) {
-        if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
-        return;
-    }
-
+    const int j = lane & 7;
     const uint64_t tile0 = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
     const uint64_t tile = tile0 + (lane >> 3);
     const bool tile_ok = tile < a.ntiles;
     const uint64_t eblk = tile * kTile + (uint64_t)j * kBlock;
     const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
-    uint32_t *st = stage + w * kStageWaveDwords;
-
-    float x[32];
-    if (tile0 < a.ntiles) {
-        load_blocks<ALIGNED>(a.x, a.n, tile0 * kTile, st, lane, x);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 32; i++) x[i] = 0.0f;
-    }
+    const bool full = (tile0 + kTilesPerWave) * kTile <= a.n;  // wave-uniform
+    ChunkState cs;
+    cs.chunk = chunk;
+    cs.vm = cnt >= 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u);  // valid slots of the block
 
     // ---- tile mean: index-order pairwise binary32 tree over the 256 slots
     float s16[16];
 #pragma unroll
-    for (int i = 0; i < 16; i++) s16[i] = x[2 * i] + x[2 * i + 1];
+    for (int i = 0; i < 16; i++) s16[i] = __int_as_float(x[2 * i]) + __int_as_float(x[2 * i + 1]);
 #pragma unroll
     for (int i = 0; i < 8; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
 #pragma unroll
@@ -453,62 +621,38 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
 #pragma unroll
     for (int i = 0; i < 2; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
     float ts = s16[0] + s16[1];
-    ts = ts + dppf<kQuadXor1>(ts);      // blocks (0,1) (2,3) ...
-    ts = ts + dppf<kQuadXor2>(ts);      // (0-1, 2-3) ...
-    ts = ts + dppf<kRowHalfMirror>(ts); // (0-3, 4-7)
+    ts = ts + dppf<kQuadXor1>(ts);       // blocks (0,1) (2,3) ...
+    ts = ts + dppf<kQuadXor2>(ts);       // (0-1, 2-3) ...
+    ts = ts + dppf<kRowHalfMirror>(ts);  // (0-3, 4-7)
     const float mean_q = (ts * 0x1p-8f) * R.inv;
     const bool centre_ok = __builtin_isfinite(mean_q);
     const int mu = centre_ok ? (int)__builtin_rintf(mean_q) : 0;
+    cs.mu = mu;
 
-    // ---- quantize (Sec. IV-B): q = rint(x * inv)
-    int q[32];
+    // ---- quantize, biased: x[i] = kQBias + rint(x * inv)
 #pragma unroll
-    for (int i = 0; i < 32; i++) q[i] = (int)__builtin_rintf(x[i] * R.inv);
+    for (int i = 0; i < 32; i++) x[i] = __float_as_int(__int_as_float(x[i]) * R.inv + kQMagic);
 
-    // ---- cross-block state: last q and last LZ1 residual of block j-1
-    int t0 = dpp<kRowShr1>(q[31]);
-    int t1 = dpp<kRowShr1>(q[31] - q[30]);
-    const int carry_q = j ? t0 : 0;
-    const int carry_l1 = j ? t1 : 0;
+    // ---- cross-block state from block j-1 of the same tile
+    const int t0 = dpp<kRowShr1>(x[31]);
+    const int t1 = dpp<kRowShr1>(x[31] - x[30]);
+    cs.carry_b = j ? t0 : kQBias;
+    cs.carry_l1 = j ? t1 : 0;
 
-    // ---- residuals and their extrema (block 0 keeps its first residuals aside)
-    int mx1 = INT_MIN, mn1 = INT_MAX, mx2 = INT_MIN, mn2 = INT_MAX;
-    int l2_1 = 0;
-    {
-        int pq = carry_q, pl = carry_l1;
-#pragma unroll
-        for (int i = 0; i < 32; i++) {
-            int l1 = q[i] - pq;
-            int l2 = l1 - pl;
-            pq = q[i];
-            pl = l1;
-            if (i >= cnt) {
-                l1 = 0;
-                l2 = 0;
-            }
-            if (i == 1) l2_1 = l2;
-            const bool in1 = i >= 1 || j != 0;
-            const bool in2 = i >= 2 || j != 0;
-            if (in1) {
-                mx1 = max(mx1, l1);
-                mn1 = min(mn1, l1);
-            }
-            if (in2) {
-                mx2 = max(mx2, l2);
-                mn2 = min(mn2, l2);
-            }
-        }
-    }
-    const uint32_t a1 = max(uabs(mx1), uabs(mn1));
-    const uint32_t a2 = max(uabs(mx2), uabs(mn2));
+    uint32_t a1, a2;
+    int l2_1;
+    if (full)
+        block_extrema<true>(x, cs.carry_b, cs.carry_l1, j, cs.vm, a1, a2, l2_1);
+    else
+        block_extrema<false>(x, cs.carry_b, cs.carry_l1, j, cs.vm, a1, a2, l2_1);
     const uint32_t r1 = bitlen(a1), r2 = bitlen(a2);
     const int T1 = group_sum(j ? (int)block_bytes(r1) : 0);
     const int T2 = group_sum(j ? (int)block_bytes(r2) : 0);
 
-    // ---- four-way evaluation of block 0 and the selection (lane j == 0)
+    // ---- four-way evaluation of block 0 and the selection (valid in lane j == 0)
     int dec;
     {
-        const int q0 = q[0];
+        const int q0 = x[0] - kQBias;
         const int d1 = cnt >= 2 ? l2_1 : 0;  // q1 - 2 q0
         const int c0 = q0 - mu;
         const int c1 = cnt >= 2 ? l2_1 + mu : 0;
@@ -542,38 +686,55 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
         if (!tile_ok) dec = 0;
     }
     dec = group_head(dec);
-    const int order2 = (dec >> 7) & 1;
-    const int cent = (dec >> 6) & 1;
+    cs.order2 = (dec >> 7) & 1;
+    cs.cent = (dec >> 6) & 1;
     const uint32_t Z = (uint32_t)dec >> 8;
-    const uint32_t r = j == 0 ? (uint32_t)(dec & 31) : (order2 ? r2 : r1);
-    if (cnt > 0) a.out[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)(j == 0 ? (dec & 0xFF) : r);
-    const uint32_t S = block_bytes(r);
+    cs.r = j == 0 ? (uint32_t)(dec & 31) : (cs.order2 ? r2 : r1);
+    if (cnt > 0) a.out[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)(j == 0 ? (dec & 0xFF) : cs.r);
+    const uint32_t S = block_bytes(cs.r);
 
-    // ---- offsets inside the wave / chunk
-    const int zt = j == 0 ? (int)Z : 0;
-    const int incl = wave_incl_scan(zt);
-    const uint32_t tile_excl = (uint32_t)incl - Z;
-    const uint32_t wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
-    const uint32_t blk_off = tile_excl + group_excl_scan(S, j) + 4u * cent;
-    if (lane == 0) s_wave_total[w] = wave_total;
+    // ---- offsets inside the wave / chunk, aggregate for the lookback
+    const int incl = wave_incl_scan(j == 0 ? (int)Z : 0);
+    cs.tile_excl = (uint32_t)incl - Z;
+    cs.wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
+    cs.blk_off = cs.tile_excl + group_excl_scan(S, j) + 4u * cs.cent;
+    if (lane == 0) sh.wave_total[slot][w] = cs.wave_total;
     __syncthreads();
+    if (tid == 0) {
+        uint32_t chunk_total = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; k++) chunk_total += sh.wave_total[slot][k];
+        publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, false);
+    }
+    return cs;
+}
+
+// Steps 4-5 of one chunk whose rate pass is done: wait for the chunk's output
+// offset (decoupled lookback, Sec. IV-D), then the sign / bit-plane encoding
+// (Sec. IV-C) straight to the output.  B holds the biased quantized values.
+template <bool STAGED>
+__device__ __forceinline__ void compress_encode(const CompressArgs &a, const Resolved &R, const ChunkState &cs,
+                                                int (&B)[32], int slot, CompressShared &sh, uint32_t *st)
+{
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int j = lane & 7;
     uint32_t chunk_total = 0, wave_base = 0;
 #pragma unroll
     for (int k = 0; k < kWaves; k++) {
-        if (k < w) wave_base += s_wave_total[k];
-        chunk_total += s_wave_total[k];
+        if (k < w) wave_base += sh.wave_total[slot][k];
+        chunk_total += sh.wave_total[slot][k];
     }
-
-    // ---- step 4: device-wide exclusive prefix by decoupled lookback
     if (w == 0) {
-        const Prefix pre = lookback(a.flags, chunk, a.flag_epoch, chunk_total, false);
+        const Prefix pre = lookback_wait(a.flags, cs.chunk, a.flag_epoch, chunk_total, false);
         if (lane == 0) {
-            s_base = pre.excl;
-            if (chunk == a.nchunks - 1) {
+            sh.base = pre.excl;
+            if (cs.chunk == a.nchunks - 1) {
                 const uint64_t total = a.data0 + pre.excl + chunk_total;
-                uint32_t st = pre.err ? (uint32_t)FSZ_ERR_DEVICE : (uint32_t)FSZ_OK;
-                if (st == FSZ_OK && total > a.capacity) st = FSZ_ERR_CAPACITY;
-                if (st == FSZ_OK) {
+                uint32_t status = pre.err ? (uint32_t)FSZ_ERR_DEVICE : (uint32_t)FSZ_OK;
+                if (status == FSZ_OK && total > a.capacity) status = FSZ_ERR_CAPACITY;
+                if (status == FSZ_OK) {
                     uint32_t *h = reinterpret_cast<uint32_t *>(a.out);
                     h[0] = 0x315A5346u;  // "FSZ1"
                     h[1] = 1u | ((uint32_t)a.mode << 16) | (R.flags << 24);
@@ -585,72 +746,324 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
                     h[7] = (uint32_t)(total >> 32);
                     for (uint64_t k = kHeaderBytes + a.nblocks; k < a.data0; k++) a.out[k] = 0;
                 }
-                write_final(a.final, total, st, a.epoch);
+                write_final(a.final, total, status, a.epoch);
             }
         }
     }
     __syncthreads();
-    const uint64_t base = s_base;
+    const uint64_t base = sh.base;
+    const uint64_t tile0 = cs.chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
     if (a.data0 + base + chunk_total > a.capacity || tile0 >= a.ntiles) return;
 
-    // ---- step 5: encode the selected variant into the wave's LDS region
-    if (cnt > 0 && j == 0 && cent) st[tile_excl >> 2] = (uint32_t)mu;
-    uint32_t code[32];
+    uint8_t *wave_out = a.out + a.data0 + base + wave_base;
+    if (cs.vm != 0 && j == 0 && cs.cent) {
+        if (STAGED)
+            st[cs.tile_excl >> 2] = (uint32_t)cs.mu;
+        else
+            *reinterpret_cast<uint32_t *>(wave_out + cs.tile_excl) = (uint32_t)cs.mu;
+    }
+    const unsigned long long o2 = __ballot(cs.order2 != 0);
+    const unsigned long long o1 = __ballot(cs.order2 == 0);
+    if (o2 == 0)
+        block_codes<1>(B, cs.carry_b, cs.carry_l1, j, 0, cs.cent, cs.mu);
+    else if (o1 == 0)
+        block_codes<2>(B, cs.carry_b, cs.carry_l1, j, 1, cs.cent, cs.mu);
+    else
+        block_codes<0>(B, cs.carry_b, cs.carry_l1, j, cs.order2, cs.cent, cs.mu);
+    // valid slots in stored bit order (element i at bit i ^ 7)
+    const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(cs.vm));
+    const uint32_t nwords = cs.r ? cs.r + 1 : 0;  // sign word + r planes
+    uint32_t *words = STAGED ? st + (cs.blk_off >> 2) : reinterpret_cast<uint32_t *>(wave_out + cs.blk_off);
+    for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
+        uint32_t Rg[8];
+#pragma unroll
+        for (int rho = 0; rho < 8; rho++)
+            Rg[rho] = pack_byte_g((uint32_t)B[7 - rho], (uint32_t)B[15 - rho], (uint32_t)B[23 - rho],
+                                  (uint32_t)B[31 - rho], g);
+        transpose8(Rg);
+#pragma unroll
+        for (int p = 0; p < 8; p++)
+            if (8 * g + p < nwords) words[8 * g + p] = Rg[p] & keep;
+    }
+    if (STAGED) {  // coalesced copy of the wave's contiguous output
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        uint32_t *dst = reinterpret_cast<uint32_t *>(wave_out);
+        for (uint32_t k = lane; k < (cs.wave_total >> 2); k += 64) dst[k] = st[k];
+    }
+}
+
+// Thread 0 takes the next ticket and broadcasts it.  Consecutive calls use
+// alternating slots, so a slot is rewritten only after a barrier that every
+// reader of its previous value has passed.
+template <typename Shared>
+__device__ __forceinline__ uint64_t next_ticket(unsigned long long *ticket, uint64_t takes, Shared &sh, int &slot)
+{
+    if (threadIdx.x == 0) sh.ticket[slot] = take_ticket(ticket, takes);
+    __syncthreads();
+    const uint64_t t = sh.ticket[slot];
+    slot ^= 1;
+    return t;
+}
+
+// Compression kernel: one chunk per workgroup, chunk ids from the ticket
+// counter, so the lookback only waits on chunks that are already running.
+// The kernel is kept small in registers so that many chunks are in flight per
+// CU: chunks waiting in the lookback leave the CU to the others.
+template <bool ALIGNED, bool LOAD_STAGED, bool STORE_STAGED>
+__global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
+{
+    __shared__ CompressShared sh;
+    __shared__ __attribute__((aligned(16))) uint32_t
+        stage[(LOAD_STAGED || STORE_STAGED) ? kWaves * kStageWaveDwords : 4];
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    uint32_t *st = stage + ((LOAD_STAGED || STORE_STAGED) ? w * kStageWaveDwords : 0);
+
+    int tslot = 0;
+    const uint64_t chunk = next_ticket(a.ticket, a.nchunks, sh, tslot);
+    if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
+
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status != FSZ_OK) {
+        if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
+        return;
+    }
+    const uint64_t tile = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave + (lane >> 3);
+    const uint64_t eblk = tile * kTile + (uint64_t)(lane & 7) * kBlock;
+    const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
+    int x[32];
     {
-        int pq = carry_q, pl = carry_l1;
+        float f[32];
+        if (LOAD_STAGED) {
+            const uint64_t tile0 = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+            if (tile0 < a.ntiles) {
+                load_blocks_staged<ALIGNED>(a.x, a.n, tile0 * kTile, st, lane, f);
+            } else {
 #pragma unroll
-        for (int i = 0; i < 32; i++) {
-            const int l1 = q[i] - pq;
-            int e = order2 ? l1 - pl : l1;
-            pq = q[i];
-            pl = l1;
-            if (i == 0 && j == 0 && cent) e = q[0] - mu;
-            if (i == 1 && j == 0 && cent && order2) e = e + mu;
-            if (i >= cnt) e = 0;
-            code[i] = (uabs(e) << 1) | ((uint32_t)e >> 31);
+                for (int i = 0; i < 32; i++) f[i] = 0.0f;
+            }
+        } else {
+            load_block<ALIGNED>(a.x, eblk, cnt, f);
         }
-    }
-    const uint32_t nwords = r ? r + 1 : 0;  // sign word + r planes
-    for (uint32_t b = 0; __ballot(b < nwords) != 0; b++) {
-        uint32_t word = 0;
 #pragma unroll
-        for (int i = 0; i < 32; i++) word |= ((code[i] >> b) & 1u) << (31 - i);
-        if (b < nwords) st[(blk_off >> 2) + b] = bswap32(word);
+        for (int i = 0; i < 32; i++) x[i] = __float_as_int(f[i]);
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    uint32_t *dst = reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base);
-    for (uint32_t k = lane; k < (wave_total >> 2); k += 64) dst[k] = st[k];
+    const ChunkState cs = compress_rates(a, R, chunk, x, 0, sh);
+    compress_encode<STORE_STAGED>(a, R, cs, x, 0, sh, st);
 }
 
 // ------------------------------------------------------------------ decompress
 
-// Decompression kernel: Sec. III-A decompression steps 1-5 in one launch:
-// rate bytes -> block and tile sizes -> lookback offsets -> bit-unshuffle
-// -> inverse cross-block prediction (one inclusive scan for LZ1, two for
-// LZ2, plus the tile mean) -> x' = (float)q * E.
-template <bool ALIGNED>
-__global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
-{
-    __shared__ __attribute__((aligned(16))) uint32_t stage[kWaves * kStageWaveDwords];
-    __shared__ uint32_t s_wave_total[kWaves];
-    __shared__ unsigned long long s_chunk, s_base;
-    __shared__ int s_bad;
+// Per-lane state of one chunk between the size pass and the decode pass.
+struct DecChunk {
+    uint64_t chunk;
+    uint32_t r, blk_off, tile_excl, wave_total;
+    int order2, cent;
+};
 
+struct DecompressShared {
+    uint32_t wave_total[2][kWaves];
+    int bad[2];
+    unsigned long long base;
+    unsigned long long ticket[2];  // alternating broadcast slots
+};
+
+// Decompression steps 1-2 (Sec. III-A): rate bytes and tile metadata ->
+// block and tile sizes -> this chunk's aggregate, published at once so that
+// successors' lookbacks rarely wait.
+__device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t chunk, int slot, DecompressShared &sh)
+{
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
     const int j = lane & 7;
-
-    if (tid == 0) {
-        s_chunk = take_ticket(a.ticket, a.nchunks);
-        s_bad = 0;
+    const uint64_t tile = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave + (lane >> 3);
+    const bool tile_ok = tile < a.ntiles;
+    const uint64_t gblock = tile * kBlocksPerTile + j;
+    const bool blk_ok = gblock < a.nblocks;
+    const uint32_t rb = blk_ok ? a.cmp[kHeaderBytes + gblock] : 0u;
+    const bool bad = blk_ok && (j == 0 ? (rb & 0x20u) : (rb & 0xE0u)) != 0;
+    const uint32_t head = (uint32_t)group_head((int)rb);
+    DecChunk d;
+    d.chunk = chunk;
+    d.order2 = tile_ok ? (int)((head >> 7) & 1u) : 0;
+    d.cent = tile_ok ? (int)((head >> 6) & 1u) : 0;
+    d.r = rb & 31u;
+    const uint32_t S = block_bytes(d.r);
+    const uint32_t Z = (uint32_t)group_sum((int)S) + 4u * d.cent;
+    const int incl = wave_incl_scan(j == 0 ? (int)Z : 0);
+    d.tile_excl = (uint32_t)incl - Z;
+    d.wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
+    d.blk_off = d.tile_excl + group_excl_scan(S, j) + 4u * d.cent;
+    const bool wave_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+        sh.wave_total[slot][w] = d.wave_total;
+        if (w == 0) sh.bad[slot] = 0;
     }
     __syncthreads();
-    const uint64_t chunk = s_chunk;
-    if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
+    if (lane == 0 && wave_bad) sh.bad[slot] = 1;
+    __syncthreads();
+    uint32_t chunk_total = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; k++) chunk_total += sh.wave_total[slot][k];
+    if (tid == 0) publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, sh.bad[slot] != 0);
+    return d;
+}
 
-    // ---- header validation (same for every workgroup)
+// Decompression steps 3-5: lookback offset, bit-unshuffle, inverse
+// cross-block prediction (one inclusive scan for LZ1, two for LZ2, plus the
+// tile mean), x' = (float)q * E.
+template <bool ALIGNED, bool STAGED>
+__device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChunk &d, int slot, float E,
+                                           uint64_t total, uint32_t *st, DecompressShared &sh)
+{
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int j = lane & 7;
+    uint32_t chunk_total = 0, wave_base = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; k++) {
+        if (k < w) wave_base += sh.wave_total[slot][k];
+        chunk_total += sh.wave_total[slot][k];
+    }
+    const bool bad = sh.bad[slot] != 0;
+    if (w == 0) {
+        const Prefix pre = lookback_wait(a.flags, d.chunk, a.flag_epoch, chunk_total, bad);
+        if (lane == 0) {
+            sh.base = pre.excl;
+            if (d.chunk == a.nchunks - 1) {
+                bool ok = !pre.err && a.data0 + pre.excl + chunk_total == total;
+                for (uint64_t k = kHeaderBytes + a.nblocks; ok && k < a.data0; k++) ok = a.cmp[k] == 0;
+                write_final(a.final, total, ok ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT, a.epoch);
+            }
+        }
+    }
+    __syncthreads();
+    const uint64_t base = sh.base;
+    const uint64_t tile0 = d.chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    if (bad || a.data0 + base + chunk_total > total || tile0 >= a.ntiles) return;
+
+    const uint64_t gblock = (tile0 + (lane >> 3)) * kBlocksPerTile + j;
+    const bool blk_ok = gblock < a.nblocks;
+    const uint8_t *wave_data = a.cmp + a.data0 + base + wave_base;
+    int mu = 0;
+    if (d.cent) mu = (int)*reinterpret_cast<const uint32_t *>(wave_data + d.tile_excl);
+
+    // ---- bit-unshuffle: stored words -> residual codes
+    uint32_t code[32];
+#pragma unroll
+    for (int i = 0; i < 32; i++) code[i] = 0;
+    const uint32_t nwords = (blk_ok && d.r) ? d.r + 1 : 0;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(wave_data + d.blk_off);
+    for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
+        uint32_t Rg[8];
+#pragma unroll
+        for (int p = 0; p < 8; p++) Rg[p] = 8 * g + p < nwords ? words[8 * g + p] : 0u;
+        transpose8(Rg);
+        // Rg[rho] byte k = byte g of code 8k + 7 - rho
+#pragma unroll
+        for (int rho = 0; rho < 8; rho++) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t sel = (0x03020100u & ~(0xFFu << (8 * g))) | ((4u + k) << (8 * g));
+                code[8 * k + 7 - rho] = __builtin_amdgcn_perm(Rg[rho], code[8 * k + 7 - rho], sel);
+            }
+        }
+    }
+
+    // ---- inverse cross-block prediction + dequantization
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        const uint32_t ns = (uint32_t)-(int)(code[i] & 1u);  // 0 or all ones
+        acc += ((code[i] >> 1) ^ ns) - ns;
+        code[i] = acc;  // first running sum (LZ1 reconstruction / LZ2 first differences)
+    }
+    const uint32_t start1 = group_excl_scan(acc, j);
+    uint32_t acc2 = 0;
+    if (__ballot(d.order2) != 0) {
+#pragma unroll
+        for (int i = 0; i < 32; i++) {
+            acc2 += code[i] + start1;
+        }
+    }
+    const uint32_t start2 = group_excl_scan(acc2, j);
+    float xo[32];
+    {
+        const uint32_t om = (uint32_t)-d.order2;
+        uint32_t run = start2;
+#pragma unroll
+        for (int i = 0; i < 32; i++) {
+            const uint32_t d1 = code[i] + start1;  // first running sum with the carry
+            run += d1;                             // second running sum
+            const uint32_t qh = (run & om) | (d1 & ~om);
+            xo[i] = (float)(int)(qh + (uint32_t)mu) * E;
+        }
+    }
+
+    const uint64_t eblk = gblock * kBlock;
+    const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
+    if (!STAGED) {  // lane-per-block stores, 8 x 16 B per lane
+        if (ALIGNED && cnt == 32) {
+            f4 *p = reinterpret_cast<f4 *>(a.out + eblk);
+#pragma unroll
+            for (int k = 0; k < 8; k++) p[k] = f4{xo[4 * k], xo[4 * k + 1], xo[4 * k + 2], xo[4 * k + 3]};
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; i++)
+                if (i < cnt) a.out[eblk + i] = xo[i];
+        }
+        return;
+    }
+    // ---- write back through LDS with coalesced stores
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        *reinterpret_cast<float4 *>(st + lane * kStageRowDwords + 4 * k) =
+            make_float4(xo[4 * k], xo[4 * k + 1], xo[4 * k + 2], xo[4 * k + 3]);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const uint64_t e0 = tile0 * kTile;
+    const bool fullw = e0 + 2048 <= a.n;
+    if (ALIGNED) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int p = k * 64 + lane;
+            const uint64_t e = e0 + 4ull * p;
+            const f4 f = *reinterpret_cast<const f4 *>(st + (p >> 3) * kStageRowDwords + (p & 7) * 4);
+            if (fullw || e + 4 <= a.n) {
+                __builtin_nontemporal_store(f, reinterpret_cast<f4 *>(a.out + e));
+            } else {
+                if (e + 0 < a.n) a.out[e + 0] = f.x;
+                if (e + 1 < a.n) a.out[e + 1] = f.y;
+                if (e + 2 < a.n) a.out[e + 2] = f.z;
+            }
+        }
+    } else {
+#pragma unroll 8
+        for (int k = 0; k < 32; k++) {
+            const int p = k * 64 + lane;
+            const uint64_t e = e0 + p;
+            if (fullw || e < a.n) a.out[e] = __uint_as_float(st[(p >> 5) * kStageRowDwords + (p & 31)]);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// Persistent decompression kernel: the size pass of the next chunk (which
+// publishes its aggregate) runs before the decode of the current one.
+template <bool ALIGNED, bool STAGED>
+__global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t stage[STAGED ? kWaves * kStageWaveDwords : 4];
+    __shared__ DecompressShared sh;
+    const int tid = threadIdx.x;
+    uint32_t *st = stage + (STAGED ? (tid >> 6) * kStageWaveDwords : 0);
+
+    // ---- header validation (identical in every workgroup)
     const uint32_t *h = reinterpret_cast<const uint32_t *>(a.cmp);
     int hst = FSZ_OK;
     float E = 1.0f;
@@ -670,132 +1083,24 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
         }
     }
     if (hst != FSZ_OK) {
-        if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, hst, a.epoch);
+        if (tid == 0 && blockIdx.x == 0) write_final(a.final, 0, hst, a.epoch);
         return;
     }
 
-    const uint64_t tile0 = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
-    const uint64_t tile = tile0 + (lane >> 3);
-    const bool tile_ok = tile < a.ntiles;
-    const uint64_t gblock = tile * kBlocksPerTile + j;
-    const bool blk_ok = gblock < a.nblocks;
-
-    // ---- steps 1-2: rates, tile metadata, block and tile sizes
-    const uint32_t rb = blk_ok ? a.cmp[kHeaderBytes + gblock] : 0u;
-    const bool bad = blk_ok && (j == 0 ? (rb & 0x20u) : (rb & 0xE0u)) != 0;
-    const uint32_t head = (uint32_t)group_head((int)rb);
-    const int order2 = tile_ok ? (int)((head >> 7) & 1u) : 0;
-    const int cent = tile_ok ? (int)((head >> 6) & 1u) : 0;
-    const uint32_t r = rb & 31u;
-    const uint32_t S = block_bytes(r);
-    const uint32_t Z = (uint32_t)group_sum((int)S) + 4u * cent;
-    const int incl = wave_incl_scan(j == 0 ? (int)Z : 0);
-    const uint32_t tile_excl = (uint32_t)incl - Z;
-    const uint32_t wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
-    const uint32_t blk_off = tile_excl + group_excl_scan(S, j) + 4u * cent;
-    if (__ballot(bad) != 0 && lane == 0) s_bad = 1;
-    if (lane == 0) s_wave_total[w] = wave_total;
-    __syncthreads();
-    uint32_t chunk_total = 0, wave_base = 0;
-#pragma unroll
-    for (int k = 0; k < kWaves; k++) {
-        if (k < w) wave_base += s_wave_total[k];
-        chunk_total += s_wave_total[k];
-    }
-
-    // ---- step 3: offsets by decoupled lookback
-    if (w == 0) {
-        const Prefix pre = lookback(a.flags, chunk, a.flag_epoch, chunk_total, s_bad != 0);
-        if (lane == 0) {
-            s_base = pre.excl;
-            if (chunk == a.nchunks - 1) {
-                bool ok = !pre.err && a.data0 + pre.excl + chunk_total == total;
-                for (uint64_t k = kHeaderBytes + a.nblocks; ok && k < a.data0; k++) ok = a.cmp[k] == 0;
-                write_final(a.final, total, ok ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT, a.epoch);
-            }
-        }
-    }
-    __syncthreads();
-    const uint64_t base = s_base;
-    if (s_bad || a.data0 + base + chunk_total > total || tile0 >= a.ntiles) return;
-
-    // ---- step 4: decode + bit-unshuffle
-    const uint8_t *tile_data = a.cmp + a.data0 + base + wave_base;
-    int mu = 0;
-    if (cent) mu = (int)*reinterpret_cast<const uint32_t *>(tile_data + tile_excl);
-    uint32_t code[32];
-#pragma unroll
-    for (int i = 0; i < 32; i++) code[i] = 0;
-    const uint32_t nwords = (blk_ok && r) ? r + 1 : 0;
-    const uint32_t *words = reinterpret_cast<const uint32_t *>(tile_data + blk_off);
-    for (uint32_t b = 0; __ballot(b < nwords) != 0; b++) {
-        if (b < nwords) {
-            const uint32_t word = bswap32(words[b]);
-#pragma unroll
-            for (int i = 0; i < 32; i++) code[i] |= ((word >> (31 - i)) & 1u) << b;
-        }
-    }
-
-    // ---- step 5: inverse cross-block prediction + dequantization
-    uint32_t d[32];
-    uint32_t acc = 0;
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        const uint32_t m = code[i] >> 1;
-        const uint32_t e = (code[i] & 1u) ? 0u - m : m;
-        acc += e;
-        d[i] = acc;
-    }
-    const uint32_t start1 = group_excl_scan(acc, j);
-#pragma unroll
-    for (int i = 0; i < 32; i++) d[i] += start1;
-    uint32_t acc2 = 0;
-    uint32_t q2[32];
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        acc2 += d[i];
-        q2[i] = acc2;
-    }
-    const uint32_t start2 = group_excl_scan(acc2, j);
-    float xo[32];
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        const uint32_t qh = order2 ? q2[i] + start2 : d[i];
-        const int qi = (int)(qh + (uint32_t)mu);
-        xo[i] = (float)qi * E;
-    }
-
-    // ---- write back through LDS with coalesced stores
-    uint32_t *st = stage + w * kStageWaveDwords;
-#pragma unroll
-    for (int k = 0; k < 8; k++)
-        *reinterpret_cast<float4 *>(st + lane * kStageRowDwords + 4 * k) =
-            make_float4(xo[4 * k], xo[4 * k + 1], xo[4 * k + 2], xo[4 * k + 3]);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    const uint64_t e0 = tile0 * kTile;
-    const bool full = e0 + 2048 <= a.n;
-    if (ALIGNED) {
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-            const int p = k * 64 + lane;
-            const uint64_t e = e0 + 4ull * p;
-            const float4 f = *reinterpret_cast<const float4 *>(st + (p >> 3) * kStageRowDwords + (p & 7) * 4);
-            if (full || e + 4 <= a.n) {
-                *reinterpret_cast<float4 *>(a.out + e) = f;
-            } else {
-                if (e + 0 < a.n) a.out[e + 0] = f.x;
-                if (e + 1 < a.n) a.out[e + 1] = f.y;
-                if (e + 2 < a.n) a.out[e + 2] = f.z;
-            }
-        }
-    } else {
-#pragma unroll 8
-        for (int k = 0; k < 32; k++) {
-            const int p = k * 64 + lane;
-            const uint64_t e = e0 + p;
-            if (full || e < a.n) a.out[e] = __uint_as_float(st[(p >> 5) * kStageRowDwords + (p & 31)]);
-        }
+    int tslot = 0;
+    const uint64_t takes = a.nchunks + gridDim.x;
+    uint64_t cur = next_ticket(a.ticket, takes, sh, tslot);
+    if (cur >= a.nchunks) return;
+    int slot = 0;
+    DecChunk dc = dec_sizes(a, cur, slot, sh);
+    for (;;) {
+        const uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
+        DecChunk dn;
+        if (nxt < a.nchunks) dn = dec_sizes(a, nxt, slot ^ 1, sh);
+        dec_decode<ALIGNED, STAGED>(a, dc, slot, E, total, st, sh);
+        if (nxt >= a.nchunks) break;
+        dc = dn;
+        slot ^= 1;
     }
 }
 
@@ -813,22 +1118,55 @@ hipError_t launch_stats(const StatsArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, hipStream_t s)
+// Workgroups of a persistent grid: enough to fill every CU at the kernel's
+// occupancy, never more than there are chunks.
+template <typename K>
+static unsigned persistent_grid(K kernel, uint64_t nchunks)
 {
-    if (in_aligned16)
-        hipLaunchKernelGGL(compress_kernel<true>, dim3((unsigned)a.nchunks), dim3(kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(compress_kernel<false>, dim3((unsigned)a.nchunks), dim3(kThreads), 0, s, a);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || cus <= 0 ||
+        per_cu <= 0) {
+        cus = 256;
+        per_cu = 2;
+    }
+    const uint64_t g = (uint64_t)cus * (uint64_t)per_cu * (uint64_t)tuning().grid_factor;
+    return (unsigned)(nchunks < g ? nchunks : g);
+}
+
+template <bool ALIGNED, bool LS, bool SS>
+static hipError_t launch_compress_t(const CompressArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((compress_kernel<ALIGNED, LS, SS>), dim3((unsigned)a.nchunks), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, hipStream_t s)
+template <bool ALIGNED, bool STAGED>
+static hipError_t launch_decompress_t(const DecompressArgs &a, hipStream_t s)
+{
+    static const unsigned cap = persistent_grid(decompress_kernel<ALIGNED, STAGED>, ~0ull);
+    const unsigned grid = (unsigned)(a.nchunks < cap ? a.nchunks : cap);
+    hipLaunchKernelGGL((decompress_kernel<ALIGNED, STAGED>), dim3(grid), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s)
+{
+    const bool ls = tuning().staged_compress_loads;
+    if (in_aligned16) {
+        if (ls) return staged ? launch_compress_t<true, true, true>(a, s) : launch_compress_t<true, true, false>(a, s);
+        return staged ? launch_compress_t<true, false, true>(a, s) : launch_compress_t<true, false, false>(a, s);
+    }
+    if (ls) return staged ? launch_compress_t<false, true, true>(a, s) : launch_compress_t<false, true, false>(a, s);
+    return staged ? launch_compress_t<false, false, true>(a, s) : launch_compress_t<false, false, false>(a, s);
+}
+
+hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s)
 {
     if (out_aligned16)
-        hipLaunchKernelGGL(decompress_kernel<true>, dim3((unsigned)a.nchunks), dim3(kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(decompress_kernel<false>, dim3((unsigned)a.nchunks), dim3(kThreads), 0, s, a);
-    return hipGetLastError();
+        return staged ? launch_decompress_t<true, true>(a, s) : launch_decompress_t<true, false>(a, s);
+    return staged ? launch_decompress_t<false, true>(a, s) : launch_decompress_t<false, false>(a, s);
 }
 
 }  // namespace fsz
