@@ -27,6 +27,30 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 RELS = (1e-2, 1e-3, 1e-4)
+PROFILE = os.path.join(ROOT, "profiles", "compress_decompress_grf512.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2607_15413_amd", "csrc", "fsz_kernels.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("kernel_source_sha256:"):
+            fields["sha"] = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch:"):
+            for kv in line.split(":", 1)[1].split():
+                k, v = kv.split("=")
+                fields[k] = int(v)
+    if fields.get("sha") != sha:
+        return None
+    return fields.get(kernel)
 
 
 def parse_args():
@@ -38,6 +62,9 @@ def parse_args():
                     help="GRF shape (default: the 512^3 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true", help="skip the byte comparison with the oracle")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, run one plain device copy of the input (n floats) so that "
+                         "profiler counters can be calibrated against a kernel of known traffic")
     return ap.parse_args()
 
 
@@ -75,8 +102,12 @@ def main():
         if st != fsz.FSZ_OK:
             raise RuntimeError(f"{what}: {fsz.fsz_status_string(st)}")
 
-    def step(events=None):
+    def step(events=None, stats_events=None):
+        if stats_events is not None:
+            stats_events[0].record(stream)
         check(fsz.fsz_field_stats(x.data_ptr(), n, stats.data_ptr(), sh), "stats")
+        if stats_events is not None:
+            stats_events[1].record(stream)
         for k, rel in enumerate(RELS):
             if events is not None:
                 events[k][0].record(stream)
@@ -96,16 +127,21 @@ def main():
 
     ev = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in RELS]
           for _ in range(args.steps)]
+    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
     for s in range(args.steps):
-        step(ev[s])
+        step(ev[s], sev[s])
     stop.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
     ms_per_step = total_ms / args.steps
+    stats_ms = float(np.mean([sev[s][0].elapsed_time(sev[s][1]) for s in range(args.steps)]))
+    if args.copy_probe:
+        y.copy_(x)  # n floats read + n floats written: the counter calibration kernel
+        torch.cuda.synchronize()
 
     comp_ms = [np.mean([ev[s][k][0].elapsed_time(ev[s][k][1]) for s in range(args.steps)])
                for k in range(len(RELS))]
@@ -150,7 +186,7 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBPS, 4),
-        "traffic": None,
+        "traffic": measured_traffic("compress_kernel" if dominant == "compress" else "decompress_kernel"),
         "avg_launch_ms": round(dom_time / len(RELS), 4),
         "bytes_per_launch": int(dom_bytes / len(RELS)),
     }
@@ -210,6 +246,8 @@ def main():
         },
         "compress_GBps": round(len(RELS) * 4 * n / comp_time / 1e6, 1),
         "decompress_GBps": round(len(RELS) * 4 * n / dec_time / 1e6, 1),
+        "range_pass_ms": round(stats_ms, 4),
+        "compress_end_to_end_GBps": round(len(RELS) * 4 * n / (comp_time + len(RELS) * stats_ms) / 1e6, 1),
         "per_bound": per_bound,
         "roofline": roofline,
         "cpu_baseline": cpu,
