@@ -53,6 +53,124 @@ def measured_traffic(kernel: str):
     return fields.get(kernel)
 
 
+def batched_comparison(torch, fsz, workloads, reps: int, verify_oracle: bool):
+    """64 uneven fields (seed 3, 16K-16M elements, REL from {1e-2, 1e-3, 1e-4}):
+    64 plain asynchronous calls (each with its own range pass) against one
+    batched launch, one autotuned batched launch and one graph replay of a plan,
+    for compression and for decompression.  GB/s = original bytes / time."""
+    t0 = time.time()
+    fields = workloads.batch_fields(64, 3)
+    print(f"[bench] generated 64 batch fields in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    xs = [torch.from_numpy(f.data).to(dev) for f in fields]
+    ns = [f.data.size for f in fields]
+    caps = [fsz.fsz_compressed_bound(n) for n in ns]
+    total_bytes = 4 * sum(ns)
+    outs_p = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    outs_b = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    ys_p = [torch.empty(n, dtype=torch.float32, device=dev) for n in ns]
+    ys_b = [torch.empty(n, dtype=torch.float32, device=dev) for n in ns]
+    res = torch.zeros((4 * 64, 4), dtype=torch.int32, device=dev)
+
+    def rptr(k):
+        return res[k].data_ptr()
+
+    def check(st, what):
+        if st != fsz.FSZ_OK:
+            raise RuntimeError(f"{what}: {fsz.fsz_status_string(st)}")
+
+    def plain_compress():
+        for k in range(64):
+            check(fsz.fsz_compress_async(xs[k].data_ptr(), ns[k], fsz.FSZ_REL, fields[k].rel, None,
+                                         outs_p[k].data_ptr(), caps[k], rptr(k), sh), "plain compress")
+
+    cjobs = [fsz.compress_job(xs[k].data_ptr(), ns[k], fsz.FSZ_REL, fields[k].rel, outs_b[k].data_ptr(),
+                              caps[k], rptr(64 + k)) for k in range(64)]
+
+    def timed(fn, n_reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(n_reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n_reps
+
+    ms_pc = timed(plain_compress, reps)
+    ms_bc_default = timed(lambda: check(fsz.fsz_batch_async(cjobs, (4, 0), sh), "batch"), reps)
+    st, tuned = fsz.fsz_autotune(cjobs, 3, sh)
+    check(st, "autotune")
+    ms_bc = timed(lambda: check(fsz.fsz_batch_async(cjobs, tuned, sh), "batch"), reps)
+    st, plan = fsz.fsz_plan_create(cjobs, tuned)
+    check(st, "plan")
+    ms_gc = timed(lambda: check(fsz.fsz_plan_launch(plan, sh), "plan launch"), reps)
+    fsz.fsz_plan_destroy(plan)
+    torch.cuda.synchronize()
+    r = res.cpu().numpy().astype(np.uint32)
+    sizes_p = [int(r[k, 0]) | (int(r[k, 1]) << 32) for k in range(64)]
+    sizes_b = [int(r[64 + k, 0]) | (int(r[64 + k, 1]) << 32) for k in range(64)]
+    if any(int(r[k, 2]) != 0 for k in range(128)):
+        raise RuntimeError("a batched or plain compression failed")
+    identical = sizes_p == sizes_b and all(
+        torch.equal(outs_p[k][:sizes_p[k]], outs_b[k][:sizes_b[k]]) for k in range(64))
+
+    def plain_decompress():
+        for k in range(64):
+            check(fsz.fsz_decompress_async(outs_p[k].data_ptr(), sizes_p[k], ys_p[k].data_ptr(), ns[k],
+                                           rptr(128 + k), sh), "plain decompress")
+
+    djobs = [fsz.decompress_job(outs_p[k].data_ptr(), sizes_p[k], ys_b[k].data_ptr(), ns[k], rptr(192 + k))
+             for k in range(64)]
+    ms_pd = timed(plain_decompress, reps)
+    st, dtuned = fsz.fsz_autotune(djobs, 3, sh)
+    check(st, "autotune")
+    ms_bd = timed(lambda: check(fsz.fsz_batch_async(djobs, dtuned, sh), "batch"), reps)
+    st, dplan = fsz.fsz_plan_create(djobs, dtuned)
+    check(st, "plan")
+    ms_gd = timed(lambda: check(fsz.fsz_plan_launch(dplan, sh), "plan launch"), reps)
+    fsz.fsz_plan_destroy(dplan)
+    torch.cuda.synchronize()
+    r = res.cpu().numpy().astype(np.uint32)
+    if any(int(r[k, 2]) != 0 for k in range(128, 256)):
+        raise RuntimeError("a batched or plain decompression failed")
+    identical = identical and all(torch.equal(ys_p[k].view(torch.int32), ys_b[k].view(torch.int32))
+                                  for k in range(64))
+    oracle_ok = None
+    if verify_oracle:
+        import oracle
+        oracle_ok = all(outs_b[k][:sizes_b[k]].cpu().numpy().tobytes()
+                        == oracle.compress(fields[k].data, oracle.REL, fields[k].rel) for k in range(64))
+    stream_bytes = sum(sizes_p)
+
+    def gbps(ms):
+        return round(total_bytes / ms / 1e6, 1)
+
+    return {
+        "workload": "64 fields, seed 3, 16K-16M elements (log-uniform, ragged), sinusoid or k^-3 GRF slice, "
+                    "REL from {1e-2,1e-3,1e-4}",
+        "elements": int(sum(ns)),
+        "stream_bytes": int(stream_bytes),
+        "per_field_compress_GBps": gbps(ms_pc),
+        "batch_compress_GBps_default_shape": gbps(ms_bc_default),
+        "batch_compress_GBps": gbps(ms_bc),
+        "plan_compress_GBps": gbps(ms_gc),
+        "per_field_decompress_GBps": gbps(ms_pd),
+        "batch_decompress_GBps": gbps(ms_bd),
+        "plan_decompress_GBps": gbps(ms_gd),
+        "compress_ms": {"per_field": round(ms_pc, 4), "batch": round(ms_bc, 4), "plan": round(ms_gc, 4)},
+        "decompress_ms": {"per_field": round(ms_pd, 4), "batch": round(ms_bd, 4), "plan": round(ms_gd, 4)},
+        "tuning_compress": list(tuned),
+        "tuning_decompress": list(dtuned),
+        "identical_to_per_field": bool(identical),
+        "oracle_identical": oracle_ok,
+    }
+
+
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +180,9 @@ def parse_args():
                     help="GRF shape (default: the 512^3 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true", help="skip the byte comparison with the oracle")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-form comparison on the 64-field workload")
+    ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain device copy of the input (n floats) so that "
                          "profiler counters can be calibrated against a kernel of known traffic")
@@ -224,6 +345,12 @@ def main():
                 "decompress_GBps": round(len(RELS) * 4 * n / t_d / 1e9, 4),
             }
 
+    batched = None
+    if not args.no_batched:
+        del outs, y  # room for the 64-field workload
+        torch.cuda.empty_cache()
+        batched = batched_comparison(torch, fsz, workloads, args.batched_reps, not args.no_verify)
+
     line = {
         "metric": "compress/decompress GB/s on 1 MI355X (% of HBM peak) + compression ratio",
         "value": round(value, 1),
@@ -252,6 +379,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "oracle_identical": verified,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

@@ -22,8 +22,9 @@
  *     streams are safe, and concurrent calls on the SAME stream from
  *     several host threads are serialized by an internal lock.
  *   - The library allocates its workspace (chunk flags, tickets, result
- *     words) on first use per (device, stream) and grows it when a larger
- *     field arrives; it never allocates on the device otherwise.
+ *     words, batch job tables) on first use per (device, stream) and grows
+ *     it when a larger field or batch arrives; plans own their buffers; it
+ *     never allocates on the device otherwise.
  *   - Errors are returned as fsz_status values; nothing is thrown across
  *     the ABI.  Device-detected errors (non-finite input, bound too small,
  *     capacity, corrupt stream) arrive through the final status read.
@@ -130,6 +131,76 @@ fsz_status fsz_compress_async(const float *d_in, size_t n, fsz_eb_mode mode, dou
 
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
                                 fsz_result *d_result, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many fields of uneven sizes in one launch.
+ *
+ * Every job produces exactly the bytes (compress) or floats (decompress)
+ * that the plain call with the same arguments produces; only the launch
+ * differs.  A batch runs as three kernels on the stream: a segmented
+ * value-range pass over all compress jobs, a per-job fold of that pass, and
+ * one kernel whose workgroups take (job, chunk) work items from a single
+ * ticket counter in job order, each chunk following Sec. III-A steps 1-5
+ * (compress) or decompression steps 1-5, with one decoupled-lookback chain
+ * (Sec. IV-D) per job.
+ *
+ * Jobs of one batch must not write memory that another job of the same batch
+ * reads or writes.  Per-job errors (non-finite input, bound too small,
+ * capacity, corrupt stream) arrive in that job's *d_result and do not affect
+ * the other jobs.
+ * ------------------------------------------------------------------------ */
+typedef enum { FSZ_OP_COMPRESS = 0, FSZ_OP_DECOMPRESS = 1 } fsz_op;
+
+typedef struct {
+    int op;               /* fsz_op */
+    const void *d_src;    /* compress: const float[n]; decompress: the stream */
+    size_t src_size;      /* decompress: stream bytes (>= 32); compress: ignored */
+    void *d_dst;          /* compress: stream buffer; decompress: float[n] */
+    size_t dst_capacity;  /* compress: stream buffer bytes (as out_capacity of
+                             fsz_compress); decompress: ignored */
+    size_t n;             /* element count of the float field */
+    int mode;             /* compress: fsz_eb_mode */
+    double value;         /* compress: bound value (finite, > 0) */
+    fsz_result *d_result; /* outcome of the job (device memory, caller-owned) */
+} fsz_job;
+
+/* Launch shape of the batched kernel.  waves_per_group in {2, 4, 8} (a
+ * workgroup owns 8 tiles per wave); groups_per_cu caps resident workgroups
+ * per CU through extra LDS (0 = no cap, else 1..8; a cap that the kernel's
+ * own LDS or the device's per-workgroup LDS limit makes void or impossible
+ * is rejected as FSZ_ERR_INVALID_ARG).  Neither changes any output byte. */
+typedef struct {
+    int waves_per_group;
+    int groups_per_cu;
+} fsz_tuning;
+
+/* Enqueue one batch on `stream` and return.  tuning NULL = the shape the
+ * autotuner cached for this batch's size class, else the default {4, 0}.
+ * Host-side errors: FSZ_ERR_INVALID_ARG (NULL jobs with njobs > 0, an
+ * invalid job or tuning), FSZ_ERR_CAPACITY (a compress job whose capacity is
+ * below its rate header), FSZ_ERR_CORRUPT (a decompress job with src_size <
+ * 32), FSZ_ERR_DEVICE; then nothing is enqueued.  The job table is copied,
+ * so `jobs` may be reused when the call returns. */
+fsz_status fsz_batch_async(const fsz_job *jobs, size_t njobs, const fsz_tuning *tuning, void *stream);
+
+/* Autotuner: runs the batch under every supported shape (`reps` timed runs
+ * each, HIP events on `stream`), stores the fastest in the process-wide
+ * cache for the batch's size class (and in the file named by the
+ * FSZ_TUNE_CACHE environment variable, if set), and returns it in *best.
+ * The jobs' outputs are written (identically) by every run.  Blocks. */
+fsz_status fsz_autotune(const fsz_job *jobs, size_t njobs, int reps, void *stream, fsz_tuning *best);
+
+/* A plan is a fixed batch captured once in a HIP graph: its job table,
+ * flags and range-pass scratch live in plan-owned device memory, and
+ * fsz_plan_launch replays the graph (three kernel nodes, no host work per
+ * replay).  Buffers named by the jobs must stay valid for the plan's life.
+ * Launches of one plan are ordered only if they share a stream; a plan must
+ * not run concurrently with itself.  tuning NULL = as fsz_batch_async. */
+typedef struct fsz_plan fsz_plan;
+fsz_status fsz_plan_create(const fsz_job *jobs, size_t njobs, const fsz_tuning *tuning, fsz_plan **plan);
+fsz_status fsz_plan_launch(fsz_plan *plan, void *stream);
+fsz_status fsz_plan_get_tuning(const fsz_plan *plan, fsz_tuning *out);
+void fsz_plan_destroy(fsz_plan *plan);
 
 #ifdef __cplusplus
 }

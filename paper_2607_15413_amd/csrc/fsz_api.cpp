@@ -1,12 +1,17 @@
 // C ABI of libfsz.so: argument validation, per-(device, stream) workspace,
 // kernel launches and the single device->host status read per call.
+#include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <utility>
+#include <vector>
 
 #include "fsz_internal.h"
 
@@ -34,6 +39,16 @@ const Tuning &tuning()
 
 namespace {
 
+// Pinned staging + device copy of one batch's job table.  A slot is reused
+// only after the event recorded behind the batch that last used it.
+struct DescSlot {
+    void *h = nullptr;
+    void *d = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+
 struct Workspace {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -46,6 +61,16 @@ struct Workspace {
     fsz_result *h_final = nullptr;           // pinned host copy
     fsz_stats *d_stats = nullptr;            // range pass output when the caller has none
     StatsPartial *d_partials = nullptr;
+    // batched form
+    std::array<DescSlot, 4> ring;
+    unsigned ring_next = 0;
+    unsigned long long *b_flags = nullptr;
+    uint64_t b_flags_cap = 0;
+    StatsPartial *b_partials = nullptr;
+    uint64_t b_partials_cap = 0;
+    fsz_stats *b_stats = nullptr;
+    uint64_t b_stats_cap = 0;
+    unsigned long long *b_ticket = nullptr;
 };
 
 std::mutex g_mu;
@@ -73,9 +98,12 @@ Workspace *get_workspace(hipStream_t s, fsz_status *st)
                 ok(hipHostMalloc(&ws->h_final, sizeof(fsz_result), hipHostMallocDefault)) &&
                 ok(hipMalloc(&ws->d_stats, sizeof(fsz_stats))) &&
                 ok(hipMalloc(&ws->d_partials, sizeof(StatsPartial) * kStatsMaxBlocks)) &&
+                ok(hipMalloc(&ws->b_ticket, sizeof(unsigned long long))) &&
                 ok(hipMemset(ws->d_ticket, 0, sizeof(unsigned long long))) &&
+                ok(hipMemset(ws->b_ticket, 0, sizeof(unsigned long long))) &&
                 ok(hipMemset(ws->d_final, 0, sizeof(fsz_result))) &&
                 ok(hipDeviceSynchronize());
+    for (auto &slot : ws->ring) good = good && ok(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
     if (!good) {
         *st = FSZ_ERR_DEVICE;
         return nullptr;
@@ -204,6 +232,288 @@ fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_siz
     return FSZ_OK;
 }
 
+
+// ------------------------------------------------------------------ batched form
+
+// Device-side layout of a batch for one launch shape.
+struct BatchLayout {
+    std::vector<BatchJob> jobs;
+    std::vector<uint64_t> chunk_end, seg_end;
+    uint64_t total_chunks = 0, total_segs = 0, total_elems = 0;
+    bool aligned16 = true, any_compress = false, any_decompress = false;
+    size_t desc_bytes() const { return jobs.size() * (sizeof(BatchJob) + 2 * sizeof(uint64_t)); }
+    void pack(void *dst) const
+    {
+        char *p = static_cast<char *>(dst);
+        std::memcpy(p, jobs.data(), jobs.size() * sizeof(BatchJob));
+        p += jobs.size() * sizeof(BatchJob);
+        std::memcpy(p, chunk_end.data(), jobs.size() * sizeof(uint64_t));
+        p += jobs.size() * sizeof(uint64_t);
+        std::memcpy(p, seg_end.data(), jobs.size() * sizeof(uint64_t));
+    }
+};
+
+// Validates every job (nothing is enqueued unless all pass) and lays out
+// global chunk and range-pass segment ranges in job order.
+fsz_status layout_batch(const fsz_job *jobs, size_t njobs, int waves, BatchLayout *L)
+{
+    if (njobs > 0 && !jobs) return FSZ_ERR_INVALID_ARG;
+    if (njobs >= (1u << 31)) return FSZ_ERR_INVALID_ARG;
+    const uint64_t tiles_per_chunk = (uint64_t)kTilesPerWave * (uint64_t)waves;
+    L->jobs.resize(njobs);
+    L->chunk_end.resize(njobs);
+    L->seg_end.resize(njobs);
+    for (size_t k = 0; k < njobs; k++) {
+        const fsz_job &j = jobs[k];
+        if (!j.d_result) return FSZ_ERR_INVALID_ARG;
+        fsz_status st;
+        if (j.op == FSZ_OP_COMPRESS)
+            st = check_compress_args(static_cast<const float *>(j.d_src), j.n, j.mode, j.value, j.d_dst,
+                                     j.dst_capacity);
+        else if (j.op == FSZ_OP_DECOMPRESS)
+            st = check_decompress_args(j.d_src, j.src_size, static_cast<const float *>(j.d_dst), j.n);
+        else
+            st = FSZ_ERR_INVALID_ARG;
+        if (st != FSZ_OK) return st;
+        BatchJob J{};
+        J.op = (uint32_t)j.op;
+        J.mode = j.mode;
+        J.n = j.n;
+        J.ntiles = ceil_div(j.n, kTile);
+        J.nblocks = ceil_div(j.n, kBlock);
+        J.nchunks = J.ntiles ? ceil_div(J.ntiles, tiles_per_chunk) : 1;
+        J.data0 = kHeaderBytes + pad16(J.nblocks);
+        J.src = j.d_src;
+        J.src_size = j.op == FSZ_OP_DECOMPRESS ? j.src_size : 0;
+        J.dst = j.d_dst;
+        J.dst_capacity = j.op == FSZ_OP_COMPRESS ? j.dst_capacity : 0;
+        J.value = j.value;
+        J.final = j.d_result;
+        J.chunk_base = L->total_chunks;
+        L->total_chunks += J.nchunks;
+        J.seg_base = L->total_segs;
+        J.nsegs = j.op == FSZ_OP_COMPRESS ? ceil_div(j.n, kSegElems) : 0;
+        L->total_segs += J.nsegs;
+        L->total_elems += j.n;
+        L->chunk_end[k] = L->total_chunks;
+        L->seg_end[k] = L->total_segs;
+        if (j.op == FSZ_OP_COMPRESS) {
+            L->any_compress = true;
+            L->aligned16 = L->aligned16 && aligned(j.d_src, 16);
+        } else {
+            L->any_decompress = true;
+            L->aligned16 = L->aligned16 && aligned(j.d_dst, 16);
+        }
+        L->jobs[k] = J;
+    }
+    // one work item per workgroup: grid x times workgroup size must fit 32 bits
+    if (L->total_chunks * (uint64_t)(waves * 64) >= (1ull << 32) || L->total_segs * kStatsThreads >= (1ull << 32))
+        return FSZ_ERR_INVALID_ARG;
+    return FSZ_OK;
+}
+
+template <typename T>
+bool grow(T **p, uint64_t *cap, uint64_t want, hipStream_t s)
+{
+    if (want <= *cap) return true;
+    uint64_t c = *cap ? *cap : 256;
+    while (c < want) c *= 2;
+    if (*p) {
+        if (!ok(hipStreamSynchronize(s)) || !ok(hipFree(*p))) return false;
+        *p = nullptr;
+        *cap = 0;
+    }
+    if (!ok(hipMalloc(p, c * sizeof(T)))) return false;
+    *cap = c;
+    return true;
+}
+
+BatchShape to_shape(const fsz_tuning &t)
+{
+    BatchShape s;
+    s.waves = t.waves_per_group;
+    s.groups_per_cu = t.groups_per_cu;
+    return s;
+}
+
+// ---- autotune cache: best shape per (architecture, batch size class)
+
+std::mutex g_tune_mu;
+std::map<std::string, fsz_tuning> g_tune;
+bool g_tune_loaded = false;
+
+std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (!ok(hipGetDevice(&dev)) || !ok(hipGetDeviceProperties(&prop, dev))) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+int ilog2(uint64_t v)
+{
+    int l = 0;
+    while (v > 1) {
+        v >>= 1;
+        l++;
+    }
+    return l;
+}
+
+// Size class: log2 of the total element count, log2 of the job count and
+// which operations occur.
+std::string size_class(const fsz_job *jobs, size_t njobs)
+{
+    uint64_t elems = 0;
+    bool c = false, d = false;
+    for (size_t k = 0; k < njobs; k++) {
+        elems += jobs[k].n;
+        (jobs[k].op == FSZ_OP_COMPRESS ? c : d) = true;
+    }
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "%s/e%d/j%d/%s%s", arch_name().c_str(), ilog2(elems + 1), ilog2(njobs + 1),
+                  c ? "c" : "", d ? "d" : "");
+    return buf;
+}
+
+void load_tune_file_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("FSZ_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char key[128];
+    int w = 0, g = 0;
+    while (std::fscanf(f, "%127s %d %d", key, &w, &g) == 3) g_tune[key] = fsz_tuning{w, g};
+    std::fclose(f);
+}
+
+bool cached_tuning(const fsz_job *jobs, size_t njobs, fsz_tuning *out)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    load_tune_file_locked();
+    auto it = g_tune.find(size_class(jobs, njobs));
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void store_tuning(const fsz_job *jobs, size_t njobs, const fsz_tuning &t)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    load_tune_file_locked();
+    const std::string key = size_class(jobs, njobs);
+    g_tune[key] = t;
+    if (const char *path = std::getenv("FSZ_TUNE_CACHE")) {
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fprintf(f, "%s %d %d\n", key.c_str(), t.waves_per_group, t.groups_per_cu);
+            std::fclose(f);
+        }
+    }
+}
+
+fsz_status resolve_tuning(const fsz_job *jobs, size_t njobs, const fsz_tuning *tuning, fsz_tuning *out)
+{
+    if (tuning) {
+        if (!batch_shape_supported(to_shape(*tuning))) return FSZ_ERR_INVALID_ARG;
+        *out = *tuning;
+        return FSZ_OK;
+    }
+    if (!cached_tuning(jobs, njobs, out)) *out = fsz_tuning{4, 0};
+    return FSZ_OK;
+}
+
+BatchArgs batch_args(const BatchLayout &L, void *d_desc, uint32_t epoch, unsigned long long *flags,
+                     unsigned long long *ticket, fsz_stats *stats, StatsPartial *partials)
+{
+    BatchArgs b{};
+    const size_t nj = L.jobs.size();
+    char *p = static_cast<char *>(d_desc);
+    b.jobs = reinterpret_cast<const BatchJob *>(p);
+    b.chunk_end = reinterpret_cast<const uint64_t *>(p + nj * sizeof(BatchJob));
+    b.seg_end = reinterpret_cast<const uint64_t *>(p + nj * (sizeof(BatchJob) + sizeof(uint64_t)));
+    b.njobs = (uint32_t)nj;
+    b.epoch = epoch;
+    b.total_chunks = L.total_chunks;
+    b.total_segs = L.total_segs;
+    b.nflags = L.total_chunks;
+    b.flags = flags;
+    b.ticket = ticket;
+    b.stats = stats;
+    b.partials = partials;
+    return b;
+}
+
+// Enqueue one batch on the workspace's stream (caller holds ws->mu).
+fsz_status enqueue_batch(Workspace *ws, const fsz_job *jobs, size_t njobs, const BatchShape &shape)
+{
+    BatchLayout L;
+    fsz_status st = layout_batch(jobs, njobs, shape.waves, &L);
+    if (st != FSZ_OK || njobs == 0) return st;
+    if (!grow(&ws->b_flags, &ws->b_flags_cap, L.total_chunks, ws->stream) ||
+        !grow(&ws->b_partials, &ws->b_partials_cap, std::max<uint64_t>(L.total_segs, 1), ws->stream) ||
+        !grow(&ws->b_stats, &ws->b_stats_cap, njobs, ws->stream))
+        return FSZ_ERR_DEVICE;
+    DescSlot &slot = ws->ring[ws->ring_next++ % ws->ring.size()];
+    if (slot.used && !ok(hipEventSynchronize(slot.ev))) return FSZ_ERR_DEVICE;
+    const size_t bytes = L.desc_bytes();
+    if (bytes > slot.cap) {
+        if (slot.h && !ok(hipHostFree(slot.h))) return FSZ_ERR_DEVICE;
+        if (slot.d && !ok(hipFree(slot.d))) return FSZ_ERR_DEVICE;
+        slot.h = slot.d = nullptr;
+        slot.cap = 0;
+        size_t c = 4096;
+        while (c < bytes) c *= 2;
+        if (!ok(hipHostMalloc(&slot.h, c, hipHostMallocDefault)) || !ok(hipMalloc(&slot.d, c)))
+            return FSZ_ERR_DEVICE;
+        slot.cap = c;
+    }
+    L.pack(slot.h);
+    if (!ok(hipMemcpyAsync(slot.d, slot.h, bytes, hipMemcpyHostToDevice, ws->stream))) return FSZ_ERR_DEVICE;
+    if (++ws->call == 0) ++ws->call;
+    const BatchArgs b = batch_args(L, slot.d, ws->call, ws->b_flags, ws->b_ticket, ws->b_stats, ws->b_partials);
+    if (!ok(launch_batch(b, L.aligned16, L.any_compress, shape, ws->stream))) return FSZ_ERR_DEVICE;
+    if (!ok(hipEventRecord(slot.ev, ws->stream))) return FSZ_ERR_DEVICE;
+    slot.used = true;
+    return FSZ_OK;
+}
+
+}  // namespace
+
+// A captured batch (see fsz_plan_create).
+struct fsz_plan {
+    int device = 0;
+    fsz_tuning tuning{4, 0};
+    size_t njobs = 0;
+    void *d_desc = nullptr;
+    unsigned long long *d_flags = nullptr;
+    unsigned long long *d_ticket = nullptr;
+    StatsPartial *d_partials = nullptr;
+    fsz_stats *d_stats = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_plan(fsz_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    (void)hipFree(p->d_desc);
+    (void)hipFree(p->d_flags);
+    (void)hipFree(p->d_ticket);
+    (void)hipFree(p->d_partials);
+    (void)hipFree(p->d_stats);
+    delete p;
+}
+
+uint32_t g_plan_ids = 0x80000000u;
 }  // namespace
 
 extern "C" {
@@ -303,5 +613,131 @@ fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out
     uint32_t epoch = 0;
     return enqueue_decompress(ws, d_cmp, cmp_size, d_out, n, d_result, &epoch);
 }
+
+fsz_status fsz_batch_async(const fsz_job *jobs, size_t njobs, const fsz_tuning *tuning, void *stream)
+{
+    if (njobs > 0 && !jobs) return FSZ_ERR_INVALID_ARG;
+    fsz_tuning t{};
+    fsz_status st = resolve_tuning(jobs, njobs, tuning, &t);
+    if (st != FSZ_OK) return st;
+    {
+        BatchLayout L;  // host-side validation before any device work
+        st = layout_batch(jobs, njobs, t.waves_per_group, &L);
+        if (st != FSZ_OK || njobs == 0) return st;
+    }
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    return enqueue_batch(ws, jobs, njobs, to_shape(t));
+}
+
+fsz_status fsz_autotune(const fsz_job *jobs, size_t njobs, int reps, void *stream, fsz_tuning *best)
+{
+    if (!best || reps < 1 || njobs == 0 || !jobs) return FSZ_ERR_INVALID_ARG;
+    BatchLayout L;
+    fsz_status st = layout_batch(jobs, njobs, 4, &L);
+    if (st != FSZ_OK) return st;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!ok(hipEventCreate(&e0)) || !ok(hipEventCreate(&e1))) return FSZ_ERR_DEVICE;
+    float best_ms = 0.0f;
+    bool found = false;
+    st = FSZ_OK;
+    const int waves[] = {2, 4, 8};
+    const int groups[] = {0, 1, 2, 3, 4, 6};
+    for (int w : waves) {
+        for (int gcu : groups) {
+            const fsz_tuning cand{w, gcu};
+            if (!batch_shape_supported(to_shape(cand))) continue;
+            std::lock_guard<std::mutex> g(ws->mu);
+            st = enqueue_batch(ws, jobs, njobs, to_shape(cand));  // warm-up
+            if (st != FSZ_OK) break;
+            if (!ok(hipEventRecord(e0, ws->stream))) { st = FSZ_ERR_DEVICE; break; }
+            for (int r = 0; r < reps && st == FSZ_OK; r++) st = enqueue_batch(ws, jobs, njobs, to_shape(cand));
+            if (st != FSZ_OK) break;
+            float ms = 0.0f;
+            if (!ok(hipEventRecord(e1, ws->stream)) || !ok(hipEventSynchronize(e1)) ||
+                !ok(hipEventElapsedTime(&ms, e0, e1))) {
+                st = FSZ_ERR_DEVICE;
+                break;
+            }
+            if (!found || ms < best_ms) {
+                best_ms = ms;
+                *best = cand;
+                found = true;
+            }
+        }
+        if (st != FSZ_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FSZ_OK) return st;
+    if (!found) return FSZ_ERR_DEVICE;
+    store_tuning(jobs, njobs, *best);
+    return FSZ_OK;
+}
+
+fsz_status fsz_plan_create(const fsz_job *jobs, size_t njobs, const fsz_tuning *tuning, fsz_plan **plan)
+{
+    if (!plan || (njobs > 0 && !jobs)) return FSZ_ERR_INVALID_ARG;
+    *plan = nullptr;
+    fsz_tuning t{};
+    fsz_status st = resolve_tuning(jobs, njobs, tuning, &t);
+    if (st != FSZ_OK) return st;
+    BatchLayout L;
+    st = layout_batch(jobs, njobs, t.waves_per_group, &L);
+    if (st != FSZ_OK) return st;
+    auto *p = new fsz_plan();
+    p->tuning = t;
+    p->njobs = njobs;
+    bool good = ok(hipGetDevice(&p->device));
+    if (good && njobs > 0) {
+        std::vector<char> host(L.desc_bytes());
+        L.pack(host.data());
+        hipStream_t cs = nullptr;
+        good = ok(hipMalloc(&p->d_desc, host.size())) &&
+               ok(hipMalloc(&p->d_flags, std::max<uint64_t>(L.total_chunks, 1) * sizeof(unsigned long long))) &&
+               ok(hipMalloc(&p->d_ticket, sizeof(unsigned long long))) &&
+               ok(hipMalloc(&p->d_partials, std::max<uint64_t>(L.total_segs, 1) * sizeof(StatsPartial))) &&
+               ok(hipMalloc(&p->d_stats, njobs * sizeof(fsz_stats))) &&
+               ok(hipMemcpy(p->d_desc, host.data(), host.size(), hipMemcpyHostToDevice)) &&
+               ok(hipMemset(p->d_ticket, 0, sizeof(unsigned long long))) && ok(hipDeviceSynchronize()) &&
+               ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        if (good) {
+            const BatchArgs b = batch_args(L, p->d_desc, g_plan_ids++, p->d_flags, p->d_ticket, p->d_stats,
+                                           p->d_partials);
+            good = ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            if (good) {
+                const bool launched = ok(launch_batch(b, L.aligned16, L.any_compress, to_shape(t), cs));
+                const bool ended = ok(hipStreamEndCapture(cs, &p->graph));
+                good = launched && ended && ok(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+            }
+        }
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    if (!good) {
+        free_plan(p);
+        return FSZ_ERR_DEVICE;
+    }
+    *plan = p;
+    return FSZ_OK;
+}
+
+fsz_status fsz_plan_launch(fsz_plan *plan, void *stream)
+{
+    if (!plan) return FSZ_ERR_INVALID_ARG;
+    if (plan->njobs == 0) return FSZ_OK;
+    return ok(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream))) ? FSZ_OK : FSZ_ERR_DEVICE;
+}
+
+fsz_status fsz_plan_get_tuning(const fsz_plan *plan, fsz_tuning *out)
+{
+    if (!plan || !out) return FSZ_ERR_INVALID_ARG;
+    *out = plan->tuning;
+    return FSZ_OK;
+}
+
+void fsz_plan_destroy(fsz_plan *plan) { free_plan(plan); }
 
 }  // extern "C"

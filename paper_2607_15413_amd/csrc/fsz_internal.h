@@ -80,12 +80,59 @@ struct DecompressArgs {
     fsz_result *final;           // written by the workgroup owning the last chunk
 };
 
+// ---- batched form: one launch over many jobs (compress or decompress)
+
+constexpr int kSegElems = 32768;  // elements per workgroup of the batched range pass
+
+// One job of a batch, as the kernels read it (built by the host, uploaded to
+// device memory once per batch).  Chunks of job j are global chunks
+// [chunk_base, chunk_base + nchunks); its range-pass segments are
+// [seg_base, seg_base + nsegs) (compress only).
+struct BatchJob {
+    uint32_t op;  // FSZ_OP_COMPRESS or FSZ_OP_DECOMPRESS
+    int32_t mode;
+    uint64_t n, ntiles, nblocks, nchunks, data0;
+    const void *src;
+    uint64_t src_size;
+    void *dst;
+    uint64_t dst_capacity;
+    double value;
+    fsz_result *final;
+    uint64_t chunk_base, seg_base, nsegs;
+    uint64_t pad;
+};
+static_assert(sizeof(BatchJob) == 128, "BatchJob layout");
+
+struct BatchArgs {
+    const BatchJob *jobs;
+    const uint64_t *chunk_end;  // chunk_end[j] = chunk_base[j] + nchunks[j]
+    const uint64_t *seg_end;    // seg_end[j] = seg_base[j] + nsegs[j]
+    uint32_t njobs;
+    uint32_t epoch;             // result tag
+    uint64_t total_chunks, total_segs, nflags;
+    unsigned long long *flags;  // cleared by the batch's range pass
+    unsigned long long *ticket; // zero between launches (self-resetting)
+    fsz_stats *stats;           // one per job
+    StatsPartial *partials;     // one per segment
+};
+
+// Launch shape of the batched kernel: waves per workgroup (a chunk is 8 tiles
+// per wave) and a cap on resident workgroups per CU (0 = no cap).
+struct BatchShape {
+    int waves = 4;
+    int groups_per_cu = 0;
+};
+
 // Kernel launchers (fsz_kernels.hip).
 hipError_t launch_stats(const StatsArgs &a, hipStream_t s);
 // staged = write outputs through an LDS staging buffer with coalesced stores
 // instead of lane-per-block stores.
 hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s);
+// Range pass + flag clear, per-job stats, then the batched kernel.
+hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, const BatchShape &shape,
+                        hipStream_t s);
+bool batch_shape_supported(const BatchShape &shape);
 
 // Launch tuning knobs, process-wide, read once from the environment:
 // FSZ_STAGED (letters c / d / l: stage compress output / decompress output /

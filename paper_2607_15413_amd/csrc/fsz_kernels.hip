@@ -580,8 +580,9 @@ struct ChunkState {
     int order2, cent;
 };
 
+template <int W>
 struct CompressShared {
-    uint32_t wave_total[2][kWaves];
+    uint32_t wave_total[2][W];
     unsigned long long base;
     unsigned long long ticket[2];  // alternating broadcast slots
 };
@@ -593,14 +594,15 @@ struct CompressShared {
 //   3 adaptive select (strict minimum in the order LZ1, LZ2, LZ1c, LZ2c),
 //     rate header; the chunk's byte count is published for the lookback.
 // On return x holds the biased quantized values.
+template <int W>
 __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, const Resolved &R, uint64_t chunk,
-                                                     int (&x)[32], int slot, CompressShared &sh)
+                                                     int (&x)[32], int slot, CompressShared<W> &sh)
 {
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
     const int j = lane & 7;
-    const uint64_t tile0 = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    const uint64_t tile0 = chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     const uint64_t tile = tile0 + (lane >> 3);
     const bool tile_ok = tile < a.ntiles;
     const uint64_t eblk = tile * kTile + (uint64_t)j * kBlock;
@@ -703,7 +705,7 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
     if (tid == 0) {
         uint32_t chunk_total = 0;
 #pragma unroll
-        for (int k = 0; k < kWaves; k++) chunk_total += sh.wave_total[slot][k];
+        for (int k = 0; k < W; k++) chunk_total += sh.wave_total[slot][k];
         publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, false);
     }
     return cs;
@@ -712,9 +714,9 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
 // Steps 4-5 of one chunk whose rate pass is done: wait for the chunk's output
 // offset (decoupled lookback, Sec. IV-D), then the sign / bit-plane encoding
 // (Sec. IV-C) straight to the output.  B holds the biased quantized values.
-template <bool STAGED>
+template <bool STAGED, int W>
 __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Resolved &R, const ChunkState &cs,
-                                                int (&B)[32], int slot, CompressShared &sh, uint32_t *st)
+                                                int (&B)[32], int slot, CompressShared<W> &sh, uint32_t *st)
 {
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -722,7 +724,7 @@ __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Res
     const int j = lane & 7;
     uint32_t chunk_total = 0, wave_base = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; k++) {
+    for (int k = 0; k < W; k++) {
         if (k < w) wave_base += sh.wave_total[slot][k];
         chunk_total += sh.wave_total[slot][k];
     }
@@ -752,7 +754,7 @@ __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Res
     }
     __syncthreads();
     const uint64_t base = sh.base;
-    const uint64_t tile0 = cs.chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    const uint64_t tile0 = cs.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     if (a.data0 + base + chunk_total > a.capacity || tile0 >= a.ntiles) return;
 
     uint8_t *wave_out = a.out + a.data0 + base + wave_base;
@@ -806,38 +808,25 @@ __device__ __forceinline__ uint64_t next_ticket(unsigned long long *ticket, uint
     return t;
 }
 
-// Compression kernel: one chunk per workgroup, chunk ids from the ticket
-// counter, so the lookback only waits on chunks that are already running.
-// The kernel is kept small in registers so that many chunks are in flight per
-// CU: chunks waiting in the lookback leave the CU to the others.
-template <bool ALIGNED, bool LOAD_STAGED, bool STORE_STAGED>
-__global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
+// One chunk of a compression (Sec. III-A steps 1-5) by a workgroup of W
+// waves: bound resolution, coalesced load, rate pass, lookback, encode.
+template <bool ALIGNED, bool LOAD_STAGED, bool STORE_STAGED, int W>
+__device__ __forceinline__ void compress_chunk(const CompressArgs &a, uint64_t chunk, CompressShared<W> &sh,
+                                               uint32_t *st)
 {
-    __shared__ CompressShared sh;
-    __shared__ __attribute__((aligned(16))) uint32_t
-        stage[(LOAD_STAGED || STORE_STAGED) ? kWaves * kStageWaveDwords : 4];
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
-    uint32_t *st = stage + ((LOAD_STAGED || STORE_STAGED) ? w * kStageWaveDwords : 0);
-
-    int tslot = 0;
-    const uint64_t chunk = next_ticket(a.ticket, a.nchunks, sh, tslot);
-    if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
-
     const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
     if (R.status != FSZ_OK) {
         if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
         return;
     }
-    const uint64_t tile = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave + (lane >> 3);
-    const uint64_t eblk = tile * kTile + (uint64_t)(lane & 7) * kBlock;
-    const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
+    const uint64_t tile0 = chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     int x[32];
     {
         float f[32];
         if (LOAD_STAGED) {
-            const uint64_t tile0 = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
             if (tile0 < a.ntiles) {
                 load_blocks_staged<ALIGNED>(a.x, a.n, tile0 * kTile, st, lane, f);
             } else {
@@ -845,13 +834,33 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
                 for (int i = 0; i < 32; i++) f[i] = 0.0f;
             }
         } else {
+            const uint64_t eblk = (tile0 + (lane >> 3)) * kTile + (uint64_t)(lane & 7) * kBlock;
+            const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
             load_block<ALIGNED>(a.x, eblk, cnt, f);
         }
 #pragma unroll
         for (int i = 0; i < 32; i++) x[i] = __float_as_int(f[i]);
     }
-    const ChunkState cs = compress_rates(a, R, chunk, x, 0, sh);
-    compress_encode<STORE_STAGED>(a, R, cs, x, 0, sh, st);
+    const ChunkState cs = compress_rates<W>(a, R, chunk, x, 0, sh);
+    compress_encode<STORE_STAGED, W>(a, R, cs, x, 0, sh, st);
+}
+
+// Compression kernel: one chunk per workgroup, chunk ids from the ticket
+// counter, so the lookback only waits on chunks that are already running.
+// The kernel is kept small in registers so that many chunks are in flight per
+// CU: chunks waiting in the lookback leave the CU to the others.
+template <bool ALIGNED, bool LOAD_STAGED, bool STORE_STAGED>
+__global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
+{
+    __shared__ CompressShared<kWaves> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t
+        stage[(LOAD_STAGED || STORE_STAGED) ? kWaves * kStageWaveDwords : 4];
+    const int w = threadIdx.x >> 6;
+    uint32_t *st = stage + ((LOAD_STAGED || STORE_STAGED) ? w * kStageWaveDwords : 0);
+    int tslot = 0;
+    const uint64_t chunk = next_ticket(a.ticket, a.nchunks, sh, tslot);
+    if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
+    compress_chunk<ALIGNED, LOAD_STAGED, STORE_STAGED, kWaves>(a, chunk, sh, st);
 }
 
 // ------------------------------------------------------------------ decompress
@@ -863,8 +872,9 @@ struct DecChunk {
     int order2, cent;
 };
 
+template <int W>
 struct DecompressShared {
-    uint32_t wave_total[2][kWaves];
+    uint32_t wave_total[2][W];
     int bad[2];
     unsigned long long base;
     unsigned long long ticket[2];  // alternating broadcast slots
@@ -873,13 +883,15 @@ struct DecompressShared {
 // Decompression steps 1-2 (Sec. III-A): rate bytes and tile metadata ->
 // block and tile sizes -> this chunk's aggregate, published at once so that
 // successors' lookbacks rarely wait.
-__device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t chunk, int slot, DecompressShared &sh)
+template <int W>
+__device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t chunk, int slot,
+                                              DecompressShared<W> &sh)
 {
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
     const int j = lane & 7;
-    const uint64_t tile = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave + (lane >> 3);
+    const uint64_t tile = chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave + (lane >> 3);
     const bool tile_ok = tile < a.ntiles;
     const uint64_t gblock = tile * kBlocksPerTile + j;
     const bool blk_ok = gblock < a.nblocks;
@@ -907,7 +919,7 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
     __syncthreads();
     uint32_t chunk_total = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; k++) chunk_total += sh.wave_total[slot][k];
+    for (int k = 0; k < W; k++) chunk_total += sh.wave_total[slot][k];
     if (tid == 0) publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, sh.bad[slot] != 0);
     return d;
 }
@@ -915,9 +927,9 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
 // Decompression steps 3-5: lookback offset, bit-unshuffle, inverse
 // cross-block prediction (one inclusive scan for LZ1, two for LZ2, plus the
 // tile mean), x' = (float)q * E.
-template <bool ALIGNED, bool STAGED>
+template <bool ALIGNED, bool STAGED, int W>
 __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChunk &d, int slot, float E,
-                                           uint64_t total, uint32_t *st, DecompressShared &sh)
+                                           uint64_t total, uint32_t *st, DecompressShared<W> &sh)
 {
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -925,7 +937,7 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     const int j = lane & 7;
     uint32_t chunk_total = 0, wave_base = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; k++) {
+    for (int k = 0; k < W; k++) {
         if (k < w) wave_base += sh.wave_total[slot][k];
         chunk_total += sh.wave_total[slot][k];
     }
@@ -943,7 +955,7 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     }
     __syncthreads();
     const uint64_t base = sh.base;
-    const uint64_t tile0 = d.chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    const uint64_t tile0 = d.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     if (bad || a.data0 + base + chunk_total > total || tile0 >= a.ntiles) return;
 
     const uint64_t gblock = (tile0 + (lane >> 3)) * kBlocksPerTile + j;
@@ -1053,35 +1065,36 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
+// Stream header validation (identical in every workgroup): status, step E
+// and the stream's total size.
+__device__ __forceinline__ int dec_header(const DecompressArgs &a, float &E, uint64_t &total)
+{
+    const uint32_t *h = reinterpret_cast<const uint32_t *>(a.cmp);
+    E = 1.0f;
+    total = 0;
+    const uint32_t h1 = h[1];
+    if (h[0] != 0x315A5346u || (h1 & 0xFFFFu) != 1u || ((h1 >> 16) & 0xFFu) > 1u || ((h1 >> 24) & ~1u) != 0u)
+        return FSZ_ERR_CORRUPT;
+    if (((uint64_t)h[3] << 32 | h[2]) != a.n) return FSZ_ERR_SIZE_MISMATCH;
+    E = __uint_as_float(h[4]);
+    total = (uint64_t)h[7] << 32 | h[6];
+    if (!__builtin_isfinite(E) || !(E > 0.0f) || total > a.cmp_size || total < a.data0) return FSZ_ERR_CORRUPT;
+    return FSZ_OK;
+}
+
 // Persistent decompression kernel: the size pass of the next chunk (which
 // publishes its aggregate) runs before the decode of the current one.
 template <bool ALIGNED, bool STAGED>
 __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint32_t stage[STAGED ? kWaves * kStageWaveDwords : 4];
-    __shared__ DecompressShared sh;
+    __shared__ DecompressShared<kWaves> sh;
     const int tid = threadIdx.x;
     uint32_t *st = stage + (STAGED ? (tid >> 6) * kStageWaveDwords : 0);
 
-    // ---- header validation (identical in every workgroup)
-    const uint32_t *h = reinterpret_cast<const uint32_t *>(a.cmp);
-    int hst = FSZ_OK;
-    float E = 1.0f;
-    uint64_t total = 0;
-    {
-        const uint32_t h1 = h[1];
-        if (h[0] != 0x315A5346u || (h1 & 0xFFFFu) != 1u || ((h1 >> 16) & 0xFFu) > 1u ||
-            ((h1 >> 24) & ~1u) != 0u) {
-            hst = FSZ_ERR_CORRUPT;
-        } else if (((uint64_t)h[3] << 32 | h[2]) != a.n) {
-            hst = FSZ_ERR_SIZE_MISMATCH;
-        } else {
-            E = __uint_as_float(h[4]);
-            total = (uint64_t)h[7] << 32 | h[6];
-            if (!__builtin_isfinite(E) || !(E > 0.0f) || total > a.cmp_size || total < a.data0)
-                hst = FSZ_ERR_CORRUPT;
-        }
-    }
+    float E;
+    uint64_t total;
+    const int hst = dec_header(a, E, total);
     if (hst != FSZ_OK) {
         if (tid == 0 && blockIdx.x == 0) write_final(a.final, 0, hst, a.epoch);
         return;
@@ -1092,15 +1105,159 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
     uint64_t cur = next_ticket(a.ticket, takes, sh, tslot);
     if (cur >= a.nchunks) return;
     int slot = 0;
-    DecChunk dc = dec_sizes(a, cur, slot, sh);
+    DecChunk dc = dec_sizes<kWaves>(a, cur, slot, sh);
     for (;;) {
         const uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
         DecChunk dn;
-        if (nxt < a.nchunks) dn = dec_sizes(a, nxt, slot ^ 1, sh);
-        dec_decode<ALIGNED, STAGED>(a, dc, slot, E, total, st, sh);
+        if (nxt < a.nchunks) dn = dec_sizes<kWaves>(a, nxt, slot ^ 1, sh);
+        dec_decode<ALIGNED, STAGED, kWaves>(a, dc, slot, E, total, st, sh);
         if (nxt >= a.nchunks) break;
         dc = dn;
         slot ^= 1;
+    }
+}
+
+// ------------------------------------------------------------------ batched form
+
+// Index of the job owning global item t, given the non-decreasing array
+// end[j] = first item after job j: the number of jobs with end[j] <= t.
+// Run by a whole wave (64 jobs per probe); the result is wave-uniform.
+__device__ __forceinline__ uint32_t find_job(const uint64_t *end, uint32_t njobs, uint64_t t)
+{
+    const int lane = __lane_id();
+    for (uint32_t base = 0; base < njobs; base += 64) {
+        const uint32_t idx = base + lane;
+        const unsigned long long m = __ballot(idx < njobs && end[idx] <= t);
+        if (m != ~0ull) return base + (uint32_t)__builtin_popcountll(m);
+    }
+    return njobs;
+}
+
+// Batched range pass: workgroup s reduces segment s (kSegElems elements of
+// one compress job) into partials[s]; every workgroup also clears a slice of
+// the batch's chunk flags for the kernel that follows.
+template <bool ALIGNED>
+__global__ __launch_bounds__(kStatsThreads) void batch_stats_kernel(BatchArgs b)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kStatsThreads + threadIdx.x; i < b.nflags;
+         i += (uint64_t)gridDim.x * kStatsThreads)
+        b.flags[i] = 0;
+    const uint64_t seg = blockIdx.x;
+    if (seg >= b.total_segs) return;
+    const uint32_t job = __builtin_amdgcn_readfirstlane(find_job(b.seg_end, b.njobs, seg));
+    if (job >= b.njobs) return;
+    const BatchJob &J = b.jobs[job];
+    const float *x = static_cast<const float *>(J.src);
+    const uint64_t e0 = (seg - J.seg_base) * kSegElems;
+    const uint64_t e1 = J.n - e0 < (uint64_t)kSegElems ? J.n : e0 + kSegElems;
+    float mn = INFINITY, mx = -INFINITY, ma = 0.0f;
+    uint32_t nonfinite = 0;
+    auto take = [&](float v) {
+        if (__builtin_isfinite(v)) {
+            mn = fminf(mn, v);
+            mx = fmaxf(mx, v);
+            ma = fmaxf(ma, fabsf(v));
+        } else {
+            nonfinite = 1;
+        }
+    };
+    const int tid = threadIdx.x;
+    if (ALIGNED && e1 - e0 == (uint64_t)kSegElems) {
+        const f4 *x4 = reinterpret_cast<const f4 *>(x + e0);
+#pragma unroll 8
+        for (int k = 0; k < kSegElems / (4 * kStatsThreads); k++) {
+            const f4 f = __builtin_nontemporal_load(x4 + k * kStatsThreads + tid);
+            take(f.x);
+            take(f.y);
+            take(f.z);
+            take(f.w);
+        }
+    } else {
+        for (uint64_t i = e0 + tid; i < e1; i += kStatsThreads) take(x[i]);
+    }
+    const StatsPartial p = stats_block_reduce(mn, mx, ma, nonfinite);
+    if (tid == 0) b.partials[seg] = p;
+}
+
+// Per-job fold of the batched range pass (one workgroup per job).
+__global__ __launch_bounds__(kStatsThreads) void batch_stats_final_kernel(BatchArgs b)
+{
+    const BatchJob &J = b.jobs[blockIdx.x];
+    if (J.op != FSZ_OP_COMPRESS) return;
+    float mn = INFINITY, mx = -INFINITY, ma = 0.0f;
+    uint32_t nf = 0;
+    for (uint64_t i = threadIdx.x; i < J.nsegs; i += kStatsThreads)
+        stats_combine(mn, mx, ma, nf, b.partials[J.seg_base + i]);
+    const StatsPartial p = stats_block_reduce(mn, mx, ma, nf);
+    if (threadIdx.x == 0) b.stats[blockIdx.x] = fsz_stats{p.xmin, p.xmax, p.maxabs, p.flags};
+}
+
+// Batched kernel: one (job, chunk) work item per workgroup, items taken from
+// one ticket counter in job order, so every lookback waits only on chunks of
+// its own job that are already running.  A chunk runs exactly the code of
+// the plain kernels, hence the same output bytes.
+template <bool ALIGNED, int W>
+__global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
+{
+    __shared__ union {
+        CompressShared<W> c;
+        DecompressShared<W> d;
+    } sh;
+    __shared__ __attribute__((aligned(16))) uint32_t stage[W * kStageWaveDwords];
+    __shared__ unsigned long long tk;
+    const int tid = threadIdx.x;
+    uint32_t *st = stage + (tid >> 6) * kStageWaveDwords;
+    if (tid == 0) tk = take_ticket(b.ticket, b.total_chunks);
+    __syncthreads();
+    const uint64_t t = tk;
+    if (t >= b.total_chunks) return;
+    const uint32_t job = __builtin_amdgcn_readfirstlane(find_job(b.chunk_end, b.njobs, t));
+    if (job >= b.njobs) return;
+    const BatchJob &J = b.jobs[job];
+    const uint64_t chunk = t - J.chunk_base;
+    if (J.op == FSZ_OP_COMPRESS) {
+        CompressArgs a;
+        a.x = static_cast<const float *>(J.src);
+        a.n = J.n;
+        a.ntiles = J.ntiles;
+        a.nblocks = J.nblocks;
+        a.nchunks = J.nchunks;
+        a.data0 = J.data0;
+        a.out = static_cast<uint8_t *>(J.dst);
+        a.capacity = J.dst_capacity;
+        a.stats = b.stats + job;
+        a.value = J.value;
+        a.mode = J.mode;
+        a.epoch = b.epoch;
+        a.flag_epoch = 1;
+        a.flags = b.flags + J.chunk_base;
+        a.ticket = nullptr;
+        a.final = J.final;
+        compress_chunk<ALIGNED, true, true, W>(a, chunk, sh.c, st);
+    } else {
+        DecompressArgs a;
+        a.cmp = static_cast<const uint8_t *>(J.src);
+        a.cmp_size = J.src_size;
+        a.out = static_cast<float *>(J.dst);
+        a.n = J.n;
+        a.ntiles = J.ntiles;
+        a.nblocks = J.nblocks;
+        a.nchunks = J.nchunks;
+        a.data0 = J.data0;
+        a.epoch = b.epoch;
+        a.flag_epoch = 1;
+        a.flags = b.flags + J.chunk_base;
+        a.ticket = nullptr;
+        a.final = J.final;
+        float E;
+        uint64_t total;
+        const int hst = dec_header(a, E, total);
+        if (hst != FSZ_OK) {
+            if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, hst, a.epoch);
+            return;
+        }
+        const DecChunk dc = dec_sizes<W>(a, chunk, 0, sh.d);
+        dec_decode<ALIGNED, true, W>(a, dc, 0, E, total, st, sh.d);
     }
 }
 
@@ -1167,6 +1324,80 @@ hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool s
     if (out_aligned16)
         return staged ? launch_decompress_t<true, true>(a, s) : launch_decompress_t<true, false>(a, s);
     return staged ? launch_decompress_t<false, true>(a, s) : launch_decompress_t<false, false>(a, s);
+}
+
+constexpr size_t kLdsPerCu = 160 * 1024;
+
+// Dynamic LDS that caps resident workgroups per CU at `groups` (0 = none);
+// returns false when the cap needs more LDS per workgroup than allowed or
+// would change nothing.
+template <typename K>
+static bool batch_lds_pad(K kernel, int groups, size_t *pad)
+{
+    *pad = 0;
+    if (groups <= 0) return true;
+    hipFuncAttributes attr{};
+    int dev = 0, max_lds = 0;
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(kernel)) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return false;
+    const size_t per = kLdsPerCu / (size_t)groups;
+    const size_t want = per > attr.sharedSizeBytes ? (per - attr.sharedSizeBytes) / 256 * 256 : 0;
+    if (want == 0) return false;  // the kernel's own LDS already allows no more than `groups`
+    if (attr.sharedSizeBytes + want > (size_t)max_lds) return false;
+    // the pad must make the next workgroup not fit
+    if ((size_t)(groups + 1) * (attr.sharedSizeBytes + want) <= kLdsPerCu) return false;
+    *pad = want;
+    return true;
+}
+
+template <bool ALIGNED, int W>
+static hipError_t launch_batch_t(const BatchArgs &b, int groups, hipStream_t s)
+{
+    size_t pad = 0;
+    if (!batch_lds_pad(batch_kernel<ALIGNED, W>, groups, &pad)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((batch_kernel<ALIGNED, W>), dim3((unsigned)b.total_chunks), dim3(W * 64), pad, s, b);
+    return hipGetLastError();
+}
+
+bool batch_shape_supported(const BatchShape &shape)
+{
+    if (shape.groups_per_cu < 0 || shape.groups_per_cu > 8) return false;
+    size_t pad = 0;
+    switch (shape.waves) {
+    case 2: return batch_lds_pad(batch_kernel<true, 2>, shape.groups_per_cu, &pad);
+    case 4: return batch_lds_pad(batch_kernel<true, 4>, shape.groups_per_cu, &pad);
+    case 8: return batch_lds_pad(batch_kernel<true, 8>, shape.groups_per_cu, &pad);
+    default: return false;
+    }
+}
+
+hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, const BatchShape &shape,
+                        hipStream_t s)
+{
+    uint64_t grid = b.total_segs;
+    const uint64_t clear = ceil_div(b.nflags, kStatsThreads);
+    if (grid < clear) grid = clear < kStatsMaxBlocks ? clear : kStatsMaxBlocks;
+    if (grid < 1) grid = 1;
+    if (aligned16)
+        hipLaunchKernelGGL(batch_stats_kernel<true>, dim3((unsigned)grid), dim3(kStatsThreads), 0, s, b);
+    else
+        hipLaunchKernelGGL(batch_stats_kernel<false>, dim3((unsigned)grid), dim3(kStatsThreads), 0, s, b);
+    if (any_compress)
+        hipLaunchKernelGGL(batch_stats_final_kernel, dim3(b.njobs), dim3(kStatsThreads), 0, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (b.total_chunks == 0) return hipSuccess;
+    switch (shape.waves) {
+    case 2: return aligned16 ? launch_batch_t<true, 2>(b, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 2>(b, shape.groups_per_cu, s);
+    case 4: return aligned16 ? launch_batch_t<true, 4>(b, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 4>(b, shape.groups_per_cu, s);
+    case 8: return aligned16 ? launch_batch_t<true, 8>(b, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 8>(b, shape.groups_per_cu, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace fsz

@@ -41,7 +41,16 @@ EXPORTS = (
     "fsz_decompress",
     "fsz_compress_async",
     "fsz_decompress_async",
+    "fsz_batch_async",
+    "fsz_autotune",
+    "fsz_plan_create",
+    "fsz_plan_launch",
+    "fsz_plan_get_tuning",
+    "fsz_plan_destroy",
 )
+
+FSZ_OP_COMPRESS = 0
+FSZ_OP_DECOMPRESS = 1
 
 
 class FszError(RuntimeError):
@@ -57,6 +66,16 @@ class FszStats(ctypes.Structure):
 
 class FszResult(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint64), ("status", ctypes.c_uint32), ("epoch", ctypes.c_uint32)]
+
+
+class FszJob(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("d_src", ctypes.c_void_p), ("src_size", ctypes.c_size_t),
+                ("d_dst", ctypes.c_void_p), ("dst_capacity", ctypes.c_size_t), ("n", ctypes.c_size_t),
+                ("mode", ctypes.c_int), ("value", ctypes.c_double), ("d_result", ctypes.c_void_p)]
+
+
+class FszTuning(ctypes.Structure):
+    _fields_ = [("waves_per_group", ctypes.c_int), ("groups_per_cu", ctypes.c_int)]
 
 
 _lib = None
@@ -90,6 +109,19 @@ def load_library():
     lib.fsz_compress_async.restype = ctypes.c_int
     lib.fsz_decompress_async.argtypes = [vp, sz, vp, sz, vp, vp]
     lib.fsz_decompress_async.restype = ctypes.c_int
+    jp, tp = ctypes.POINTER(FszJob), ctypes.POINTER(FszTuning)
+    lib.fsz_batch_async.argtypes = [jp, sz, tp, vp]
+    lib.fsz_batch_async.restype = ctypes.c_int
+    lib.fsz_autotune.argtypes = [jp, sz, ctypes.c_int, vp, tp]
+    lib.fsz_autotune.restype = ctypes.c_int
+    lib.fsz_plan_create.argtypes = [jp, sz, tp, ctypes.POINTER(vp)]
+    lib.fsz_plan_create.restype = ctypes.c_int
+    lib.fsz_plan_launch.argtypes = [vp, vp]
+    lib.fsz_plan_launch.restype = ctypes.c_int
+    lib.fsz_plan_get_tuning.argtypes = [vp, tp]
+    lib.fsz_plan_get_tuning.restype = ctypes.c_int
+    lib.fsz_plan_destroy.argtypes = [vp]
+    lib.fsz_plan_destroy.restype = None
     _lib = lib
     return lib
 
@@ -141,6 +173,64 @@ def fsz_compress_async(d_in: int, n: int, mode: int, value: float, d_stats, d_ou
 def fsz_decompress_async(d_cmp: int, cmp_size: int, d_out: int, n: int, d_result: int,
                          stream=None) -> int:
     return load_library().fsz_decompress_async(d_cmp, cmp_size, d_out, n, d_result, stream)
+
+
+def _job_array(jobs):
+    arr = (FszJob * max(len(jobs), 1))()
+    for k, j in enumerate(jobs):
+        arr[k] = j
+    return arr
+
+
+def _tuning_ptr(tuning):
+    if tuning is None:
+        return None
+    return ctypes.byref(FszTuning(*tuning))
+
+
+def fsz_batch_async(jobs, tuning=None, stream=None) -> int:
+    """jobs: sequence of FszJob; tuning: None or (waves_per_group, groups_per_cu)."""
+    arr = _job_array(jobs)
+    return load_library().fsz_batch_async(arr, len(jobs), _tuning_ptr(tuning), stream)
+
+
+def fsz_autotune(jobs, reps: int = 3, stream=None):
+    """Returns (status, (waves_per_group, groups_per_cu))."""
+    arr = _job_array(jobs)
+    best = FszTuning(0, 0)
+    st = load_library().fsz_autotune(arr, len(jobs), reps, stream, ctypes.byref(best))
+    return st, (best.waves_per_group, best.groups_per_cu)
+
+
+def fsz_plan_create(jobs, tuning=None):
+    """Returns (status, plan handle or None)."""
+    arr = _job_array(jobs)
+    h = ctypes.c_void_p(None)
+    st = load_library().fsz_plan_create(arr, len(jobs), _tuning_ptr(tuning), ctypes.byref(h))
+    return st, (h.value if st == FSZ_OK else None)
+
+
+def fsz_plan_launch(plan, stream=None) -> int:
+    return load_library().fsz_plan_launch(plan, stream)
+
+
+def fsz_plan_get_tuning(plan):
+    t = FszTuning(0, 0)
+    st = load_library().fsz_plan_get_tuning(plan, ctypes.byref(t))
+    return st, (t.waves_per_group, t.groups_per_cu)
+
+
+def fsz_plan_destroy(plan) -> None:
+    load_library().fsz_plan_destroy(plan)
+
+
+def compress_job(d_in: int, n: int, mode: int, value: float, d_out: int, capacity: int,
+                 d_result: int) -> FszJob:
+    return FszJob(FSZ_OP_COMPRESS, d_in, 0, d_out, capacity, n, mode, value, d_result)
+
+
+def decompress_job(d_cmp: int, cmp_size: int, d_out: int, n: int, d_result: int) -> FszJob:
+    return FszJob(FSZ_OP_DECOMPRESS, d_cmp, cmp_size, d_out, 0, n, 0, 0.0, d_result)
 
 
 def read_result(result_tensor):

@@ -57,3 +57,31 @@ def test_invalid_arguments_rejected_on_host():
     assert st == fsz.FSZ_ERR_CAPACITY
     assert fsz.fsz_decompress(16, 8, 16, 10, None) == fsz.FSZ_ERR_CORRUPT
     assert fsz.fsz_decompress(0, 100, 16, 10, None) == fsz.FSZ_ERR_INVALID_ARG
+
+
+def test_batch_invalid_jobs_rejected_on_host():
+    # every job is validated before any device work; explicit shapes avoid device queries
+    T = (4, 0)
+    ok_c = fsz.compress_job(16, 1000, fsz.FSZ_REL, 1e-3, 16, fsz.fsz_compressed_bound(1000), 16)
+    ok_d = fsz.decompress_job(16, 64, 16, 1000, 16)
+    lib = fsz.load_library()
+    assert lib.fsz_batch_async(None, 3, None, None) == fsz.FSZ_ERR_INVALID_ARG
+    bad_op = fsz.FszJob(7, 16, 0, 16, 4096, 10, 1, 1e-3, 16)
+    assert fsz.fsz_batch_async([ok_c, bad_op], T) == fsz.FSZ_ERR_INVALID_ARG
+    no_result = fsz.compress_job(16, 1000, fsz.FSZ_REL, 1e-3, 16, 4096, 0)
+    assert fsz.fsz_batch_async([ok_d, no_result], T) == fsz.FSZ_ERR_INVALID_ARG
+    small = fsz.compress_job(16, 1000, fsz.FSZ_REL, 1e-3, 16, 40, 16)
+    assert fsz.fsz_batch_async([ok_c, small], T) == fsz.FSZ_ERR_CAPACITY
+    short = fsz.decompress_job(16, 31, 16, 1000, 16)
+    assert fsz.fsz_batch_async([ok_c, short], T) == fsz.FSZ_ERR_CORRUPT
+    bad_bound = fsz.compress_job(16, 1000, fsz.FSZ_REL, float("inf"), 16, 4096, 16)
+    assert fsz.fsz_batch_async([bad_bound], T) == fsz.FSZ_ERR_INVALID_ARG
+    misaligned = fsz.decompress_job(16, 64, 18, 1000, 16)
+    assert fsz.fsz_batch_async([misaligned], T) == fsz.FSZ_ERR_INVALID_ARG
+    for shape in ((3, 0), (16, 0), (4, -1), (4, 9)):
+        assert fsz.fsz_batch_async([ok_c], shape) == fsz.FSZ_ERR_INVALID_ARG
+    st, plan = fsz.fsz_plan_create([ok_c, small], T)
+    assert st == fsz.FSZ_ERR_CAPACITY and plan is None
+    assert fsz.fsz_plan_launch(None) == fsz.FSZ_ERR_INVALID_ARG
+    st, _ = fsz.fsz_autotune([ok_c], reps=0)
+    assert st == fsz.FSZ_ERR_INVALID_ARG
