@@ -171,6 +171,179 @@ def batched_comparison(torch, fsz, workloads, reps: int, verify_oracle: bool):
     }
 
 
+def served_benchmark(args):
+    """Served form: open-loop Poisson requests (seed 4; 70% compress / 30%
+    decompress of previously compressed streams; log-uniform 1K-64M elements
+    sliced from the 269x500x500 piecewise-quadratic master field; REL from
+    {1e-3, 1e-4}) against a server with a 64 GB HBM admission budget, at
+    offered loads given as fractions of the plain kernels' measured
+    closed-loop throughput on the same requests.  Reports p50/p99 latency
+    (arrival to completion seen by the host) and sustained GB/s (original
+    bytes / span from first arrival to last completion)."""
+    import torch
+
+    from paper_2607_15413_amd import fsz, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    loads = [float(v) for v in args.served_loads.split(",")]
+    counts = [int(v) for v in args.served_requests.split(",")]
+    if len(counts) == 1:
+        counts = counts * len(loads)
+    nmax = max(counts)
+    t0 = time.time()
+    shape = (269, 500, 500)
+    master_np = workloads.piecewise_quadratic(shape, 2)
+    master = torch.from_numpy(master_np).to(dev)
+    reqs = workloads.request_stream(1.0, nmax, 4, master_n=master_np.size)
+    print(f"[served] master {shape} + {nmax} requests generated in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    def check(st, what):
+        if st != fsz.FSZ_OK:
+            raise RuntimeError(f"{what}: {fsz.fsz_status_string(st)}")
+
+    # streams that decompress requests read: compressed once by the plain path
+    res = torch.zeros((nmax, 4), dtype=torch.int32, device=dev)
+    streams = {}
+    for k, r in enumerate(reqs):
+        if r.op == "decompress":
+            cap = fsz.fsz_compressed_bound(r.n)
+            buf = torch.empty(cap, dtype=torch.uint8, device=dev)
+            check(fsz.fsz_compress_async(master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel, None,
+                                         buf.data_ptr(), cap, res[k].data_ptr(), sh), "precompress")
+            streams[k] = buf
+    torch.cuda.synchronize()
+    rr = res.cpu().numpy().astype(np.uint32)
+    ssize = {k: int(rr[k, 0]) | (int(rr[k, 1]) << 32) for k in streams}
+    print(f"[served] {len(streams)} decompress inputs ready", file=sys.stderr, flush=True)
+
+    # plain closed loop over the same requests: every request one plain call,
+    # back to back on one stream (calls on a stream are ordered, so one output
+    # buffer per operation serves them all)
+    nmax_n = max(r.n for r in reqs)
+    out_c = torch.empty(fsz.fsz_compressed_bound(nmax_n), dtype=torch.uint8, device=dev)
+    out_d = torch.empty(nmax_n, dtype=torch.float32, device=dev)
+
+    def plain_pass(n_req):
+        for k in range(n_req):
+            r = reqs[k]
+            if r.op == "compress":
+                check(fsz.fsz_compress_async(master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel, None,
+                                             out_c.data_ptr(), out_c.numel(), res[k].data_ptr(), sh),
+                      "plain compress")
+            else:
+                check(fsz.fsz_decompress_async(streams[k].data_ptr(), ssize[k], out_d.data_ptr(), r.n,
+                                               res[k].data_ptr(), sh), "plain decompress")
+
+    n_plain = min(nmax, args.served_plain_requests)
+    plain_pass(n_plain)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    plain_pass(n_plain)
+    b.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = a.elapsed_time(b)
+    plain_bytes = sum(4 * reqs[k].n for k in range(n_plain))
+    plain_gbps = plain_bytes / plain_ms / 1e6
+    rr = res.cpu().numpy().astype(np.uint32)
+    if any(int(rr[k, 2]) != 0 for k in range(n_plain)):
+        raise RuntimeError("a plain call failed")
+    del out_c, out_d
+    torch.cuda.empty_cache()
+    print(f"[served] plain closed loop: {n_plain} requests, {plain_gbps:.1f} GB/s", file=sys.stderr, flush=True)
+
+    budget = int(args.served_budget_gb * 1e9)
+    results = []
+    for load, count in zip(loads, counts):
+        mean_bytes = float(np.mean([4 * reqs[k].n for k in range(count)]))
+        rate = load * plain_gbps * 1e9 / mean_bytes  # requests per second
+        st, server = fsz.fsz_server_create(budget, args.served_jobs_per_round, args.served_rounds, True, (4, 0))
+        check(st, "server create")
+        try:
+            start = fsz.fsz_server_now_ns() + 20_000_000
+            batch = []
+            for k in range(count):
+                r = reqs[k]
+                arr = start + int(r.arrival_s / rate * 1e9)
+                if r.op == "compress":
+                    batch.append(fsz.compress_request(master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel,
+                                                      k, arr))
+                else:
+                    batch.append(fsz.decompress_request(streams[k].data_ptr(), ssize[k], r.n, k, arr))
+            check(fsz.fsz_server_submit(server, batch), "submit")
+            done = {}
+            last_print = time.time()
+            while len(done) < count:
+                for c in fsz.fsz_server_poll(server, 4096, 200):
+                    done[c.tag] = (c.status, c.arrival_ns, c.admit_ns, c.launch_ns, c.complete_ns, c.size)
+                if time.time() - last_print > 5:
+                    print(f"[served] load {load}: {len(done)}/{count} done", file=sys.stderr, flush=True)
+                    last_print = time.time()
+            stats = fsz.fsz_server_get_stats(server)
+        finally:
+            fsz.fsz_server_destroy(server)
+        bad = [k for k, v in done.items() if v[0] != fsz.FSZ_OK]
+        if bad:
+            raise RuntimeError(f"served requests failed: {bad[:5]}")
+        for k, v in done.items():  # stream sizes equal the plain path's
+            if reqs[k].op == "decompress" and v[5] != ssize[k]:
+                raise RuntimeError(f"request {k}: size {v[5]} != {ssize[k]}")
+        lat = np.array([(v[4] - v[1]) / 1e6 for v in done.values()])
+        queue = np.array([(v[3] - v[1]) / 1e6 for v in done.values()])
+        span_s = (max(v[4] for v in done.values()) - min(v[1] for v in done.values())) / 1e9
+        total_bytes = sum(4 * reqs[k].n for k in range(count))
+        entry = {
+            "offered_load": load,
+            "requests": count,
+            "rate_per_s": round(rate, 1),
+            "offered_GBps": round(load * plain_gbps, 1),
+            "sustained_GBps": round(total_bytes / span_s / 1e9, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "mean_ms": round(float(lat.mean()), 4),
+            "p50_wait_to_launch_ms": round(float(np.percentile(queue, 50)), 4),
+            "rounds": int(stats.rounds),
+            "mean_jobs_per_round": round(count / max(int(stats.rounds), 1), 2),
+            "max_rounds_overlapping": int(stats.max_rounds_overlapping),
+            "hbm_peak_GB": round(stats.hbm_peak / 1e9, 3),
+        }
+        results.append(entry)
+        print(f"[served] {json.dumps(entry)}", file=sys.stderr, flush=True)
+
+    top = max((e for e in results if e["offered_load"] <= 0.9), key=lambda e: e["offered_load"],
+              default=results[-1])
+    line = {
+        "metric": "served: sustained GB/s and p50/p99 latency under open-loop Poisson load on 1 MI355X",
+        "value": top["sustained_GBps"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": len(results),
+        "warmup": 1,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "Poisson requests, seed 4, 70% compress / 30% decompress, 1K-64M elements log-uniform "
+                        "from the 269x500x500 piecewise-quadratic field (seed 2), REL {1e-3,1e-4}; "
+                        f"HBM budget {args.served_budget_gb} GB, {args.served_rounds} rounds in flight, "
+                        f"up to {args.served_jobs_per_round} jobs per round",
+            "requests_per_load": counts,
+        },
+        "plain_closed_loop_GBps": round(plain_gbps, 1),
+        "plain_closed_loop_requests": n_plain,
+        "per_load": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +356,15 @@ def parse_args():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form comparison on the 64-field workload")
     ap.add_argument("--batched-reps", type=int, default=10)
+    ap.add_argument("--served", action="store_true",
+                    help="run the served request-loop workload instead of the default one")
+    ap.add_argument("--served-loads", type=str, default="0.1,0.3,0.5,0.7,0.9,1.2,1.5")
+    ap.add_argument("--served-requests", type=str, default="10000",
+                    help="requests per load point (one value for all, or one per load)")
+    ap.add_argument("--served-plain-requests", type=int, default=10000)
+    ap.add_argument("--served-budget-gb", type=float, default=64.0)
+    ap.add_argument("--served-rounds", type=int, default=4)
+    ap.add_argument("--served-jobs-per-round", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain device copy of the input (n floats) so that "
                          "profiler counters can be calibrated against a kernel of known traffic")
@@ -196,6 +378,9 @@ def main():
               "multi-GPU sharding is described in the design notes but not launched.",
               file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.served:
+        served_benchmark(args)
+        return
 
     import torch
 

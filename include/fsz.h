@@ -202,6 +202,92 @@ fsz_status fsz_plan_launch(fsz_plan *plan, void *stream);
 fsz_status fsz_plan_get_tuning(const fsz_plan *plan, fsz_tuning *out);
 void fsz_plan_destroy(fsz_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * Served form: a request loop with admission by memory and continuous
+ * batching (one device, one process).
+ *
+ * A server owns a worker thread, a device arena of `hbm_budget` bytes for job
+ * outputs, and `rounds_in_flight` HIP streams.  Requests may be submitted
+ * ahead of time: each carries its arrival time on the fsz_server_now_ns
+ * clock and counts as arrived once that time has passed.  Arrived requests
+ * are admitted in arrival order as soon as their output reservation fits in
+ * the arena: fsz_compressed_bound(n) bytes for a compression, 4n for a
+ * decompression (a request larger than the whole budget completes at once
+ * with FSZ_ERR_CAPACITY).  Admitted requests are folded into one batched
+ * launch (as fsz_batch_async) on the next idle stream, so requests that
+ * arrive while earlier rounds run are launched beside them and overlap on
+ * the device.  Inputs stay where the caller put them (device memory that
+ * must remain valid until the request completes); outputs live in the
+ * arena until released.  Every result equals the plain call's.
+ * ------------------------------------------------------------------------ */
+typedef struct fsz_server fsz_server;
+
+typedef struct {
+    size_t hbm_budget;      /* bytes of device memory for outputs (> 0) */
+    int max_jobs_per_round; /* jobs folded into one launch, 1..65536 */
+    int rounds_in_flight;   /* launches in flight, one HIP stream each, 1..16 */
+    int auto_release;       /* nonzero: free a job's output when it completes
+                               (its bytes are then not kept; size and status
+                               are still reported) */
+    fsz_tuning tuning;      /* launch shape; {0, 0} = {4, 0} */
+} fsz_server_config;
+
+typedef struct {
+    int op;               /* fsz_op */
+    const void *d_src;    /* compress: const float[n]; decompress: the stream */
+    size_t src_size;      /* decompress: stream bytes; compress: ignored */
+    size_t n;             /* element count of the float field */
+    int mode;             /* compress: fsz_eb_mode */
+    double value;         /* compress: bound value */
+    uint64_t tag;         /* caller's identifier, returned in the completion */
+    uint64_t arrival_ns;  /* arrival time on the fsz_server_now_ns clock */
+} fsz_request;
+
+typedef struct {
+    uint64_t tag;
+    uint32_t status;      /* fsz_status of the job */
+    uint32_t op;
+    uint64_t size;        /* stream bytes written (compress) or read (decompress) */
+    void *d_out;          /* server-owned output (stream or floats); NULL when
+                             auto_release is set or the job failed */
+    uint64_t arrival_ns;  /* as submitted */
+    uint64_t admit_ns;    /* output reserved in the arena */
+    uint64_t launch_ns;   /* its round was enqueued */
+    uint64_t complete_ns; /* the worker saw its round finish */
+} fsz_completion;
+
+typedef struct {
+    uint64_t submitted, completed, rounds;
+    uint64_t max_jobs_in_round;
+    uint64_t max_rounds_overlapping; /* most rounds in flight at once */
+    size_t hbm_in_use, hbm_peak;     /* arena bytes reserved now / at most */
+} fsz_server_stats;
+
+/* Monotonic clock (nanoseconds) used for arrival and completion times. */
+uint64_t fsz_server_now_ns(void);
+
+/* Create a server on the current device.  Errors: FSZ_ERR_INVALID_ARG (bad
+ * config), FSZ_ERR_DEVICE (allocation of the arena or streams failed). */
+fsz_status fsz_server_create(const fsz_server_config *cfg, fsz_server **server);
+
+/* Queue `count` requests (thread-safe; returns at once).  Every request is
+ * validated first (as fsz_batch_async validates jobs); on an error nothing
+ * is queued. */
+fsz_status fsz_server_submit(fsz_server *server, const fsz_request *reqs, size_t count);
+
+/* Move up to `max` completions into out[], waiting up to wait_ms
+ * milliseconds for the first one (0 = do not wait).  Returns the count. */
+size_t fsz_server_poll(fsz_server *server, fsz_completion *out, size_t max, int wait_ms);
+
+/* Return a completion's output to the arena (d_out as reported). */
+fsz_status fsz_server_release(fsz_server *server, void *d_out);
+
+fsz_status fsz_server_get_stats(fsz_server *server, fsz_server_stats *out);
+
+/* Wait for every submitted request to complete, then free the server and
+ * every output it still holds. */
+void fsz_server_destroy(fsz_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfsz.so")
 ARCH = os.environ.get("FSZ_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fsz_kernels.hip", "fsz_api.cpp"]
+SOURCES = ["fsz_kernels.hip", "fsz_api.cpp", "fsz_server.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

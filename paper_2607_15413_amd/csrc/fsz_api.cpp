@@ -37,6 +37,33 @@ const Tuning &tuning()
 }
 }  // namespace fsz
 
+namespace fsz {
+
+bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+bool valid_bound(int mode, double value)
+{
+    return (mode == FSZ_ABS || mode == FSZ_REL) && std::isfinite(value) && value > 0.0;
+}
+
+fsz_status check_compress_args(const float *d_in, size_t n, int mode, double value, const void *d_out,
+                               size_t cap)
+{
+    if (!valid_bound(mode, value) || !d_out || (n > 0 && !d_in) || !aligned(d_in, 4) || !aligned(d_out, 4))
+        return FSZ_ERR_INVALID_ARG;
+    if (cap < kHeaderBytes + pad16(ceil_div(n, kBlock))) return FSZ_ERR_CAPACITY;
+    return FSZ_OK;
+}
+
+fsz_status check_decompress_args(const void *d_cmp, size_t cmp_size, const float *d_out, size_t n)
+{
+    if (!d_cmp || (n > 0 && !d_out) || !aligned(d_cmp, 4) || !aligned(d_out, 4)) return FSZ_ERR_INVALID_ARG;
+    if (cmp_size < (size_t)kHeaderBytes) return FSZ_ERR_CORRUPT;
+    return FSZ_OK;
+}
+
+}  // namespace fsz
+
 namespace {
 
 // Pinned staging + device copy of one batch's job table.  A slot is reused
@@ -153,29 +180,6 @@ fsz_status finish(Workspace *ws, uint32_t epoch, size_t *size_out)
     if (r.epoch != epoch) return FSZ_ERR_DEVICE;
     if (r.status == FSZ_OK && size_out) *size_out = (size_t)r.size;
     return (fsz_status)r.status;
-}
-
-bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
-
-bool valid_bound(int mode, double value)
-{
-    return (mode == FSZ_ABS || mode == FSZ_REL) && std::isfinite(value) && value > 0.0;
-}
-
-fsz_status check_compress_args(const float *d_in, size_t n, int mode, double value, const void *d_out,
-                               size_t cap)
-{
-    if (!valid_bound(mode, value) || !d_out || (n > 0 && !d_in) || !aligned(d_in, 4) || !aligned(d_out, 4))
-        return FSZ_ERR_INVALID_ARG;
-    if (cap < kHeaderBytes + pad16(ceil_div(n, kBlock))) return FSZ_ERR_CAPACITY;
-    return FSZ_OK;
-}
-
-fsz_status check_decompress_args(const void *d_cmp, size_t cmp_size, const float *d_out, size_t n)
-{
-    if (!d_cmp || (n > 0 && !d_out) || !aligned(d_cmp, 4) || !aligned(d_out, 4)) return FSZ_ERR_INVALID_ARG;
-    if (cmp_size < (size_t)kHeaderBytes) return FSZ_ERR_CORRUPT;
-    return FSZ_OK;
 }
 
 // Enqueue (range pass if d_stats is NULL) + compression kernel.
@@ -342,14 +346,22 @@ std::mutex g_tune_mu;
 std::map<std::string, fsz_tuning> g_tune;
 bool g_tune_loaded = false;
 
+// Architecture name of the current device (cached per device; the caller
+// holds g_tune_mu).
 std::string arch_name()
 {
+    static std::map<int, std::string> names;
     int dev = 0;
+    if (!ok(hipGetDevice(&dev))) return "unknown";
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
     hipDeviceProp_t prop{};
-    if (!ok(hipGetDevice(&dev)) || !ok(hipGetDeviceProperties(&prop, dev))) return "unknown";
+    if (!ok(hipGetDeviceProperties(&prop, dev))) return "unknown";
     std::string a = prop.gcnArchName;
     const size_t colon = a.find(':');
-    return colon == std::string::npos ? a : a.substr(0, colon);
+    a = colon == std::string::npos ? a : a.substr(0, colon);
+    names[dev] = a;
+    return a;
 }
 
 int ilog2(uint64_t v)

@@ -134,6 +134,13 @@ hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, c
                         hipStream_t s);
 bool batch_shape_supported(const BatchShape &shape);
 
+// Host-side argument checks shared by every entry point (fsz_api.cpp).
+bool aligned(const void *p, uintptr_t a);
+bool valid_bound(int mode, double value);
+fsz_status check_compress_args(const float *d_in, size_t n, int mode, double value, const void *d_out,
+                               size_t cap);
+fsz_status check_decompress_args(const void *d_cmp, size_t cmp_size, const float *d_out, size_t n);
+
 // Launch tuning knobs, process-wide, read once from the environment:
 // FSZ_STAGED (letters c / d / l: stage compress output / decompress output /
 // compress input through LDS) and FSZ_GRID_FACTOR (persistent workgroups per

@@ -47,6 +47,13 @@ EXPORTS = (
     "fsz_plan_launch",
     "fsz_plan_get_tuning",
     "fsz_plan_destroy",
+    "fsz_server_now_ns",
+    "fsz_server_create",
+    "fsz_server_submit",
+    "fsz_server_poll",
+    "fsz_server_release",
+    "fsz_server_get_stats",
+    "fsz_server_destroy",
 )
 
 FSZ_OP_COMPRESS = 0
@@ -76,6 +83,29 @@ class FszJob(ctypes.Structure):
 
 class FszTuning(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_int), ("groups_per_cu", ctypes.c_int)]
+
+
+class FszServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_jobs_per_round", ctypes.c_int),
+                ("rounds_in_flight", ctypes.c_int), ("auto_release", ctypes.c_int), ("tuning", FszTuning)]
+
+
+class FszRequest(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("d_src", ctypes.c_void_p), ("src_size", ctypes.c_size_t),
+                ("n", ctypes.c_size_t), ("mode", ctypes.c_int), ("value", ctypes.c_double),
+                ("tag", ctypes.c_uint64), ("arrival_ns", ctypes.c_uint64)]
+
+
+class FszCompletion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_uint32), ("op", ctypes.c_uint32),
+                ("size", ctypes.c_uint64), ("d_out", ctypes.c_void_p), ("arrival_ns", ctypes.c_uint64),
+                ("admit_ns", ctypes.c_uint64), ("launch_ns", ctypes.c_uint64), ("complete_ns", ctypes.c_uint64)]
+
+
+class FszServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("max_jobs_in_round", ctypes.c_uint64), ("max_rounds_overlapping", ctypes.c_uint64),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t)]
 
 
 _lib = None
@@ -122,6 +152,20 @@ def load_library():
     lib.fsz_plan_get_tuning.restype = ctypes.c_int
     lib.fsz_plan_destroy.argtypes = [vp]
     lib.fsz_plan_destroy.restype = None
+    lib.fsz_server_now_ns.argtypes = []
+    lib.fsz_server_now_ns.restype = ctypes.c_uint64
+    lib.fsz_server_create.argtypes = [ctypes.POINTER(FszServerConfig), ctypes.POINTER(vp)]
+    lib.fsz_server_create.restype = ctypes.c_int
+    lib.fsz_server_submit.argtypes = [vp, ctypes.POINTER(FszRequest), sz]
+    lib.fsz_server_submit.restype = ctypes.c_int
+    lib.fsz_server_poll.argtypes = [vp, ctypes.POINTER(FszCompletion), sz, ctypes.c_int]
+    lib.fsz_server_poll.restype = sz
+    lib.fsz_server_release.argtypes = [vp, vp]
+    lib.fsz_server_release.restype = ctypes.c_int
+    lib.fsz_server_get_stats.argtypes = [vp, ctypes.POINTER(FszServerStats)]
+    lib.fsz_server_get_stats.restype = ctypes.c_int
+    lib.fsz_server_destroy.argtypes = [vp]
+    lib.fsz_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -224,6 +268,56 @@ def fsz_plan_destroy(plan) -> None:
     load_library().fsz_plan_destroy(plan)
 
 
+def fsz_server_now_ns() -> int:
+    return int(load_library().fsz_server_now_ns())
+
+
+def fsz_server_create(hbm_budget: int, max_jobs_per_round: int = 256, rounds_in_flight: int = 2,
+                      auto_release: bool = False, tuning=(0, 0)):
+    """Returns (status, server handle or None)."""
+    cfg = FszServerConfig(hbm_budget, max_jobs_per_round, rounds_in_flight, int(auto_release),
+                          FszTuning(*tuning))
+    h = ctypes.c_void_p(None)
+    st = load_library().fsz_server_create(ctypes.byref(cfg), ctypes.byref(h))
+    return st, (h.value if st == FSZ_OK else None)
+
+
+def fsz_server_submit(server, requests) -> int:
+    arr = (FszRequest * max(len(requests), 1))()
+    for k, r in enumerate(requests):
+        arr[k] = r
+    return load_library().fsz_server_submit(server, arr, len(requests))
+
+
+def fsz_server_poll(server, max_count: int = 1024, wait_ms: int = 0):
+    """List of FszCompletion (possibly empty)."""
+    arr = (FszCompletion * max_count)()
+    k = load_library().fsz_server_poll(server, arr, max_count, wait_ms)
+    return [arr[i] for i in range(k)]
+
+
+def fsz_server_release(server, d_out: int) -> int:
+    return load_library().fsz_server_release(server, d_out)
+
+
+def fsz_server_get_stats(server) -> FszServerStats:
+    st = FszServerStats()
+    load_library().fsz_server_get_stats(server, ctypes.byref(st))
+    return st
+
+
+def fsz_server_destroy(server) -> None:
+    load_library().fsz_server_destroy(server)
+
+
+def compress_request(d_in: int, n: int, mode: int, value: float, tag: int, arrival_ns: int) -> FszRequest:
+    return FszRequest(FSZ_OP_COMPRESS, d_in, 0, n, mode, value, tag, arrival_ns)
+
+
+def decompress_request(d_cmp: int, cmp_size: int, n: int, tag: int, arrival_ns: int) -> FszRequest:
+    return FszRequest(FSZ_OP_DECOMPRESS, d_cmp, cmp_size, n, 0, 0.0, tag, arrival_ns)
+
+
 def compress_job(d_in: int, n: int, mode: int, value: float, d_out: int, capacity: int,
                  d_result: int) -> FszJob:
     return FszJob(FSZ_OP_COMPRESS, d_in, 0, d_out, capacity, n, mode, value, d_result)
@@ -272,6 +366,22 @@ def decompress(stream_bytes, n: int, out=None, check: bool = True):
     if check and st != FSZ_OK:
         raise FszError(st, "fsz_decompress")
     return out, st
+
+
+class _DeviceBuffer:
+    """A raw device range exposed through the CUDA array interface."""
+
+    def __init__(self, ptr: int, nbytes: int):
+        self.__cuda_array_interface__ = {"shape": (nbytes,), "typestr": "|u1", "data": (ptr, False),
+                                         "version": 2}
+
+
+def device_view(ptr: int, nbytes: int, dtype=None):
+    """A torch tensor viewing nbytes of device memory at ptr (no copy), e.g.
+    a served request's output; reinterpreted as dtype when given."""
+    import torch
+    t = torch.as_tensor(_DeviceBuffer(ptr, nbytes), device="cuda")
+    return t if dtype is None or dtype == torch.uint8 else t.view(dtype)
 
 
 def field_stats(x, out=None):

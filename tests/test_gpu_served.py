@@ -1,0 +1,193 @@
+"""GPU tests of the served form: admission by memory, continuous batching,
+and results that are the same alone and in the mix (byte-identical streams,
+bit-identical reconstructions, checked against the CPU oracle)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_15413_amd import fsz, workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def announce(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+class Workload:
+    """Requests over one resident master field; decompress requests read
+    streams the oracle wrote for the same slice and bound."""
+
+    def __init__(self, count, seed, hi=1 << 18, shape=(20, 100, 500)):
+        self.master_np = workloads.piecewise_quadratic(shape, 2)
+        self.master = torch.from_numpy(self.master_np).to(_dev())
+        self.reqs = workloads.request_stream(1000.0, count, seed, lo=1 << 10, hi=hi,
+                                             master_n=self.master_np.size)
+        self.streams = {}
+        for k, r in enumerate(self.reqs):
+            if r.op == "decompress":
+                data = oracle.compress(self.slice(r), oracle.REL, r.rel)
+                buf = torch.from_numpy(np.frombuffer(data, dtype=np.uint8).copy()).to(_dev())
+                self.streams[k] = (data, buf)
+
+    def slice(self, r):
+        return self.master_np[r.offset:r.offset + r.n]
+
+    def request(self, k, arrival_ns):
+        r = self.reqs[k]
+        if r.op == "compress":
+            return fsz.compress_request(self.master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel, k,
+                                        arrival_ns)
+        data, buf = self.streams[k]
+        return fsz.decompress_request(buf.data_ptr(), len(data), r.n, k, arrival_ns)
+
+    def expected(self, k):
+        r = self.reqs[k]
+        if r.op == "compress":
+            return oracle.compress(self.slice(r), oracle.REL, r.rel)
+        return oracle.decompress(self.streams[k][0], r.n)
+
+
+def fetch(c, n):
+    """Host copy of a completion's output (stream bytes or floats)."""
+    if c.op == fsz.FSZ_OP_COMPRESS:
+        return fsz.device_view(c.d_out, c.size, torch.uint8).cpu().numpy().tobytes()
+    return fsz.device_view(c.d_out, 4 * n, torch.float32).cpu().numpy()
+
+
+def drain(server, count, w=None, timeout_s=60.0):
+    """Collect `count` completions; outputs still held are copied to the host
+    (completion tag -> (completion, output)) and released at once, so that
+    requests waiting for memory can be admitted."""
+    import time
+    got = {}
+    t0 = time.time()
+    while len(got) < count:
+        for c in fsz.fsz_server_poll(server, 256, 100):
+            out = None
+            if c.d_out:
+                out = fetch(c, w.reqs[c.tag].n)
+                assert fsz.fsz_server_release(server, c.d_out) == fsz.FSZ_OK
+                assert fsz.fsz_server_release(server, c.d_out) == fsz.FSZ_ERR_INVALID_ARG
+            got[c.tag] = (c, out)
+        assert time.time() - t0 < timeout_s, f"only {len(got)} of {count} completions"
+    return got
+
+
+def run_server(w, tags, budget, jobs_per_round, rounds, stagger_ns=0):
+    st, server = fsz.fsz_server_create(budget, jobs_per_round, rounds, False, (4, 0))
+    assert st == fsz.FSZ_OK, fsz.fsz_status_string(st)
+    outputs = {}
+    try:
+        t0 = fsz.fsz_server_now_ns() + 2_000_000
+        reqs = [w.request(k, t0 + i * stagger_ns) for i, k in enumerate(tags)]
+        assert fsz.fsz_server_submit(server, reqs) == fsz.FSZ_OK
+        import time
+        pending = set(tags)
+        t_start = time.time()
+        while pending:
+            for c in fsz.fsz_server_poll(server, 256, 100):
+                assert c.status == fsz.FSZ_OK, (c.tag, c.status)
+                assert c.complete_ns >= c.launch_ns >= c.admit_ns >= c.arrival_ns
+                outputs[c.tag] = fetch(c, w.reqs[c.tag].n)
+                assert fsz.fsz_server_release(server, c.d_out) == fsz.FSZ_OK
+                pending.discard(c.tag)
+            assert time.time() - t_start < 120, f"{len(pending)} requests never completed"
+        stats = fsz.fsz_server_get_stats(server)
+    finally:
+        fsz.fsz_server_destroy(server)
+    return outputs, stats
+
+
+def same(a, b):
+    if isinstance(a, bytes):
+        return a == b
+    return np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_served_results_same_alone_and_in_mix():
+    w = Workload(96, 4)
+    tags = list(range(len(w.reqs)))
+    budget = 6 << 20  # far below the sum of reservations: admission waits for released outputs
+    announce(f"served mix: {len(tags)} requests, budget {budget} B, 3 rounds in flight")
+    mixed, stats = run_server(w, tags, budget, 4, 3)
+    assert stats.completed == len(tags)
+    assert stats.hbm_peak <= budget
+    assert stats.max_rounds_overlapping >= 2, "rounds never overlapped"
+    assert stats.rounds >= len(tags) // 4
+    announce("served alone: one request at a time")
+    alone, stats1 = run_server(w, tags, budget, 1, 1, stagger_ns=0)
+    assert stats1.max_jobs_in_round == 1
+    for k in tags:
+        exp = w.expected(k)
+        assert same(mixed[k], exp), f"request {k} ({w.reqs[k].op}, n={w.reqs[k].n}) differs in the mix"
+        assert same(alone[k], exp), f"request {k} differs alone"
+
+
+def test_served_admission_and_errors():
+    w = Workload(8, 5, hi=1 << 16)
+    budget = 1 << 20
+    st, server = fsz.fsz_server_create(budget, 8, 2, False, (4, 0))
+    assert st == fsz.FSZ_OK
+    announce("served admission: too-large request, NaN input, corrupt stream")
+    try:
+        big_n = 1 << 20  # reservation fsz_compressed_bound(1M) > 1 MiB budget
+        big = torch.zeros(big_n, dtype=torch.float32, device=_dev())
+        nan = torch.ones(5000, dtype=torch.float32, device=_dev())
+        nan[77] = float("nan")
+        data = oracle.compress(workloads.sinusoid_field(4000, 9), oracle.REL, 1e-3)
+        bad = bytearray(data)
+        bad[32] |= 0x20
+        badt = torch.from_numpy(np.frombuffer(bytes(bad), dtype=np.uint8).copy()).to(_dev())
+        now = fsz.fsz_server_now_ns()
+        reqs = [fsz.compress_request(big.data_ptr(), big_n, fsz.FSZ_REL, 1e-3, 100, now),
+                fsz.compress_request(nan.data_ptr(), 5000, fsz.FSZ_REL, 1e-3, 101, now),
+                fsz.decompress_request(badt.data_ptr(), len(bad), 4000, 102, now)]
+        reqs += [w.request(k, now) for k in range(len(w.reqs))]
+        assert fsz.fsz_server_submit(server, reqs) == fsz.FSZ_OK
+        got = drain(server, len(reqs), w)
+        for tag, st in ((100, fsz.FSZ_ERR_CAPACITY), (101, fsz.FSZ_ERR_NONFINITE), (102, fsz.FSZ_ERR_CORRUPT)):
+            c, out = got[tag]
+            assert c.status == st and out is None, (tag, c.status)
+        for k in range(len(w.reqs)):
+            c, out = got[k]
+            assert c.status == fsz.FSZ_OK
+            assert same(out, w.expected(k))
+        stats = fsz.fsz_server_get_stats(server)
+        assert stats.hbm_in_use == 0 and stats.hbm_peak <= budget
+    finally:
+        fsz.fsz_server_destroy(server)
+
+
+def test_served_open_loop_poisson():
+    w = Workload(200, 6, hi=1 << 17)
+    st, server = fsz.fsz_server_create(64 << 20, 64, 2, True, (4, 0))
+    assert st == fsz.FSZ_OK
+    announce("served open loop: 200 Poisson arrivals at 4000/s, auto release")
+    try:
+        t0 = fsz.fsz_server_now_ns() + 5_000_000
+        rate = 4000.0
+        arrivals = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, len(w.reqs)))
+        reqs = [w.request(k, t0 + int(arrivals[k] * 1e9)) for k in range(len(w.reqs))]
+        assert fsz.fsz_server_submit(server, reqs) == fsz.FSZ_OK
+        got = {k: c for k, (c, _) in drain(server, len(reqs)).items()}
+        lat = np.array([(c.complete_ns - c.arrival_ns) / 1e6 for c in got.values()])
+        assert all(c.status == fsz.FSZ_OK and not c.d_out for c in got.values())
+        assert all(c.admit_ns >= c.arrival_ns for c in got.values())
+        sizes = {k: got[k].size for k in got}
+        for k, r in enumerate(w.reqs):  # stream sizes equal the oracle's
+            exp = w.expected(k)
+            if r.op == "compress":
+                assert sizes[k] == len(exp)
+            else:
+                assert sizes[k] == len(w.streams[k][0])
+        print(f"p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms", flush=True)
+        assert np.percentile(lat, 50) > 0
+    finally:
+        fsz.fsz_server_destroy(server)

@@ -85,3 +85,32 @@ def test_batch_invalid_jobs_rejected_on_host():
     assert fsz.fsz_plan_launch(None) == fsz.FSZ_ERR_INVALID_ARG
     st, _ = fsz.fsz_autotune([ok_c], reps=0)
     assert st == fsz.FSZ_ERR_INVALID_ARG
+
+
+def test_arena_allocator_against_brute_force(tmp_path):
+    # the served form's admission allocator, compiled for the host and run
+    # against a unit-map first-fit model with invariant checks after every op
+    import subprocess
+    exe = tmp_path / "arena_check"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-I",
+                    os.path.join(ROOT, "paper_2607_15413_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "arena_check.cpp"), "-o", str(exe)], check=True)
+    for seed in (1, 2, 3):
+        r = subprocess.run([str(exe), str(seed)], capture_output=True, text=True)
+        assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout
+
+
+def test_server_invalid_config_rejected_on_host():
+    lib = fsz.load_library()
+    cfg = fsz.FszServerConfig(0, 16, 2, 0, fsz.FszTuning(4, 0))
+    h = ctypes.c_void_p(None)
+    assert lib.fsz_server_create(ctypes.byref(cfg), ctypes.byref(h)) == fsz.FSZ_ERR_INVALID_ARG
+    for jobs, rounds, tuning in ((0, 2, (4, 0)), (16, 0, (4, 0)), (16, 17, (4, 0)), (16, 2, (3, 0))):
+        cfg = fsz.FszServerConfig(1 << 20, jobs, rounds, 0, fsz.FszTuning(*tuning))
+        assert lib.fsz_server_create(ctypes.byref(cfg), ctypes.byref(h)) == fsz.FSZ_ERR_INVALID_ARG
+    assert lib.fsz_server_create(None, ctypes.byref(h)) == fsz.FSZ_ERR_INVALID_ARG
+    req = fsz.compress_request(16, 10, fsz.FSZ_REL, 1e-3, 0, 0)
+    assert fsz.fsz_server_submit(None, [req]) == fsz.FSZ_ERR_INVALID_ARG
+    assert fsz.fsz_server_poll(None) == []
+    assert fsz.fsz_server_release(None, 16) == fsz.FSZ_ERR_INVALID_ARG
+    assert fsz.fsz_server_now_ns() > 0
