@@ -259,34 +259,56 @@ def served_benchmark(args):
 
     budget = int(args.served_budget_gb * 1e9)
     results = []
-    for load, count in zip(loads, counts):
-        mean_bytes = float(np.mean([4 * reqs[k].n for k in range(count)]))
-        rate = load * plain_gbps * 1e9 / mean_bytes  # requests per second
-        st, server = fsz.fsz_server_create(budget, args.served_jobs_per_round, args.served_rounds, True, (4, 0))
-        check(st, "server create")
-        try:
-            start = fsz.fsz_server_now_ns() + 20_000_000
-            batch = []
-            for k in range(count):
-                r = reqs[k]
-                arr = start + int(r.arrival_s / rate * 1e9)
-                if r.op == "compress":
-                    batch.append(fsz.compress_request(master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel,
-                                                      k, arr))
-                else:
-                    batch.append(fsz.decompress_request(streams[k].data_ptr(), ssize[k], r.n, k, arr))
-            check(fsz.fsz_server_submit(server, batch), "submit")
-            done = {}
-            last_print = time.time()
-            while len(done) < count:
-                for c in fsz.fsz_server_poll(server, 4096, 200):
-                    done[c.tag] = (c.status, c.arrival_ns, c.admit_ns, c.launch_ns, c.complete_ns, c.size)
-                if time.time() - last_print > 5:
-                    print(f"[served] load {load}: {len(done)}/{count} done", file=sys.stderr, flush=True)
-                    last_print = time.time()
-            stats = fsz.fsz_server_get_stats(server)
-        finally:
-            fsz.fsz_server_destroy(server)
+    # one long-running server for every load point, warmed up by one short pass
+    st, server = fsz.fsz_server_create(budget, args.served_jobs_per_round, args.served_rounds, True, (4, 0))
+    check(st, "server create")
+
+    # request table built once; arrival times are stamped just before each submission
+    table = fsz.request_table(nmax)
+    for k, r in enumerate(reqs):
+        if r.op == "compress":
+            table[k] = (fsz.FSZ_OP_COMPRESS, master.data_ptr() + 4 * r.offset, 0, r.n, fsz.FSZ_REL, r.rel, k, 0)
+        else:
+            table[k] = (fsz.FSZ_OP_DECOMPRESS, streams[k].data_ptr(), ssize[k], r.n, 0, 0.0, k, 0)
+    arrival_s = np.array([r.arrival_s for r in reqs])
+
+    def serve(count, rate):
+        sub = table[:count]
+        before = fsz.fsz_server_get_stats(server)
+        start = fsz.fsz_server_now_ns() + 5_000_000
+        sub["arrival_ns"] = start + (arrival_s[:count] / rate * 1e9).astype(np.uint64)
+        check(fsz.fsz_server_submit_table(server, sub), "submit")
+        lead_ms = (start - fsz.fsz_server_now_ns()) / 1e6  # > 0: submitted before the first arrival
+        done = {}
+        last_print = time.time()
+        while len(done) < count:
+            for c in fsz.fsz_server_poll(server, 4096, 200):
+                done[c.tag] = (c.status, c.arrival_ns, c.admit_ns, c.launch_ns, c.complete_ns, c.size)
+            if time.time() - last_print > 5:
+                print(f"[served] {len(done)}/{count} done", file=sys.stderr, flush=True)
+                last_print = time.time()
+        after = fsz.fsz_server_get_stats(server)
+        return done, int(after.rounds - before.rounds), after, lead_ms
+
+    import gc
+    gc.disable()  # no collector pauses in the client while requests are in flight
+    try:
+        n_warm = min(200, nmax)
+        serve(n_warm, 0.5 * plain_gbps * 1e9 / float(np.mean([4 * reqs[k].n for k in range(n_warm)])))
+        runs = []
+        for load, count in zip(loads, counts):
+            mean_bytes = float(np.mean([4 * reqs[k].n for k in range(count)]))
+            rate = load * plain_gbps * 1e9 / mean_bytes  # requests per second
+            runs.append((load, count, rate) + serve(count, rate))
+    finally:
+        fsz.fsz_server_destroy(server)
+        gc.enable()
+    if args.served_timeline:
+        np.savez(args.served_timeline, **{
+            f"load_{load}": np.array([[done[k][1], done[k][2], done[k][3], done[k][4], reqs[k].n,
+                                       int(reqs[k].op == "compress")] for k in range(count)], dtype=np.int64)
+            for load, count, rate, done, rounds, stats, lead in runs})
+    for load, count, rate, done, rounds, stats, lead in runs:
         bad = [k for k, v in done.items() if v[0] != fsz.FSZ_OK]
         if bad:
             raise RuntimeError(f"served requests failed: {bad[:5]}")
@@ -295,7 +317,11 @@ def served_benchmark(args):
                 raise RuntimeError(f"request {k}: size {v[5]} != {ssize[k]}")
         lat = np.array([(v[4] - v[1]) / 1e6 for v in done.values()])
         queue = np.array([(v[3] - v[1]) / 1e6 for v in done.values()])
-        span_s = (max(v[4] for v in done.values()) - min(v[1] for v in done.values())) / 1e9
+        t_first = min(v[1] for v in done.values())
+        span_s = (max(v[4] for v in done.values()) - t_first) / 1e9
+        comp = np.sort(np.array([v[4] for v in done.values()], dtype=np.int64))
+        gaps = np.diff(comp)
+        gap_at = int(np.argmax(gaps)) if gaps.size else 0
         total_bytes = sum(4 * reqs[k].n for k in range(count))
         entry = {
             "offered_load": load,
@@ -307,10 +333,11 @@ def served_benchmark(args):
             "p99_ms": round(float(np.percentile(lat, 99)), 4),
             "mean_ms": round(float(lat.mean()), 4),
             "p50_wait_to_launch_ms": round(float(np.percentile(queue, 50)), 4),
-            "rounds": int(stats.rounds),
-            "mean_jobs_per_round": round(count / max(int(stats.rounds), 1), 2),
-            "max_rounds_overlapping": int(stats.max_rounds_overlapping),
-            "hbm_peak_GB": round(stats.hbm_peak / 1e9, 3),
+            "rounds": rounds,
+            "mean_jobs_per_round": round(count / max(rounds, 1), 2),
+            "submit_lead_ms": round(lead, 3),
+            "max_completion_gap_ms": round(float(gaps[gap_at]) / 1e6, 3) if gaps.size else 0.0,
+            "max_gap_at_ms": round(float(comp[gap_at] - t_first) / 1e6, 3) if gaps.size else 0.0,
         }
         results.append(entry)
         print(f"[served] {json.dumps(entry)}", file=sys.stderr, flush=True)
@@ -337,6 +364,8 @@ def served_benchmark(args):
                         f"up to {args.served_jobs_per_round} jobs per round",
             "requests_per_load": counts,
         },
+        "server_max_rounds_overlapping": int(runs[-1][5].max_rounds_overlapping),
+        "server_hbm_peak_GB": round(runs[-1][5].hbm_peak / 1e9, 3),
         "plain_closed_loop_GBps": round(plain_gbps, 1),
         "plain_closed_loop_requests": n_plain,
         "per_load": results,
@@ -365,6 +394,8 @@ def parse_args():
     ap.add_argument("--served-budget-gb", type=float, default=64.0)
     ap.add_argument("--served-rounds", type=int, default=4)
     ap.add_argument("--served-jobs-per-round", type=int, default=256)
+    ap.add_argument("--served-timeline", type=str, default=None,
+                    help="write per-request times (arrival, admit, launch, complete; ns) per load to this .npz")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain device copy of the input (n floats) so that "
                          "profiler counters can be calibrated against a kernel of known traffic")

@@ -460,6 +460,23 @@ BatchArgs batch_args(const BatchLayout &L, void *d_desc, uint32_t epoch, unsigne
     return b;
 }
 
+// Make a job-table slot hold `bytes` (the slot is idle).  Freeing device
+// memory synchronizes the device, so long-running callers reserve up front
+// (reserve_batch).
+bool grow_slot(DescSlot &slot, size_t bytes)
+{
+    if (bytes <= slot.cap) return true;
+    if (slot.h && !ok(hipHostFree(slot.h))) return false;
+    if (slot.d && !ok(hipFree(slot.d))) return false;
+    slot.h = slot.d = nullptr;
+    slot.cap = 0;
+    size_t c = 4096;
+    while (c < bytes) c *= 2;
+    if (!ok(hipHostMalloc(&slot.h, c, hipHostMallocDefault)) || !ok(hipMalloc(&slot.d, c))) return false;
+    slot.cap = c;
+    return true;
+}
+
 // Enqueue one batch on the workspace's stream (caller holds ws->mu).
 fsz_status enqueue_batch(Workspace *ws, const fsz_job *jobs, size_t njobs, const BatchShape &shape)
 {
@@ -473,17 +490,7 @@ fsz_status enqueue_batch(Workspace *ws, const fsz_job *jobs, size_t njobs, const
     DescSlot &slot = ws->ring[ws->ring_next++ % ws->ring.size()];
     if (slot.used && !ok(hipEventSynchronize(slot.ev))) return FSZ_ERR_DEVICE;
     const size_t bytes = L.desc_bytes();
-    if (bytes > slot.cap) {
-        if (slot.h && !ok(hipHostFree(slot.h))) return FSZ_ERR_DEVICE;
-        if (slot.d && !ok(hipFree(slot.d))) return FSZ_ERR_DEVICE;
-        slot.h = slot.d = nullptr;
-        slot.cap = 0;
-        size_t c = 4096;
-        while (c < bytes) c *= 2;
-        if (!ok(hipHostMalloc(&slot.h, c, hipHostMallocDefault)) || !ok(hipMalloc(&slot.d, c)))
-            return FSZ_ERR_DEVICE;
-        slot.cap = c;
-    }
+    if (!grow_slot(slot, bytes)) return FSZ_ERR_DEVICE;
     L.pack(slot.h);
     if (!ok(hipMemcpyAsync(slot.d, slot.h, bytes, hipMemcpyHostToDevice, ws->stream))) return FSZ_ERR_DEVICE;
     if (++ws->call == 0) ++ws->call;
@@ -495,6 +502,28 @@ fsz_status enqueue_batch(Workspace *ws, const fsz_job *jobs, size_t njobs, const
 }
 
 }  // namespace
+
+namespace fsz {
+
+bool reserve_batch(hipStream_t stream, uint64_t jobs, uint64_t chunks, uint64_t segs)
+{
+    fsz_status st = FSZ_OK;
+    Workspace *ws = get_workspace(stream, &st);
+    if (!ws) return false;
+    std::lock_guard<std::mutex> g(ws->mu);
+    if (!grow(&ws->b_flags, &ws->b_flags_cap, std::max<uint64_t>(chunks, 1), ws->stream) ||
+        !grow(&ws->b_partials, &ws->b_partials_cap, std::max<uint64_t>(segs, 1), ws->stream) ||
+        !grow(&ws->b_stats, &ws->b_stats_cap, std::max<uint64_t>(jobs, 1), ws->stream))
+        return false;
+    const size_t bytes = jobs * (sizeof(BatchJob) + 2 * sizeof(uint64_t));
+    for (auto &slot : ws->ring) {
+        if (slot.used && !ok(hipEventSynchronize(slot.ev))) return false;
+        if (!grow_slot(slot, bytes)) return false;
+    }
+    return true;
+}
+
+}  // namespace fsz
 
 // A captured batch (see fsz_plan_create).
 struct fsz_plan {

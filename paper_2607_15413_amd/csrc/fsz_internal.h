@@ -141,6 +141,11 @@ fsz_status check_compress_args(const float *d_in, size_t n, int mode, double val
                                size_t cap);
 fsz_status check_decompress_args(const void *d_cmp, size_t cmp_size, const float *d_out, size_t n);
 
+// Sizes the batch workspace of `stream` for rounds of up to `jobs` jobs,
+// `chunks` work items and `segs` range-pass segments, so that later batches
+// within those limits allocate (and synchronize the device) never again.
+bool reserve_batch(hipStream_t stream, uint64_t jobs, uint64_t chunks, uint64_t segs);
+
 // Launch tuning knobs, process-wide, read once from the environment:
 // FSZ_STAGED (letters c / d / l: stage compress output / decompress output /
 // compress input through LDS) and FSZ_GRID_FACTOR (persistent workgroups per

@@ -378,6 +378,24 @@ fsz_status fsz_server_create(const fsz_server_config *cfg, fsz_server **server)
         good = good && ok(hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking)) &&
                ok(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
     }
+    // Everything a round can need is allocated now: growing it later would
+    // free device memory, which waits for every stream of the device.
+    // Outputs of one round fit in the arena, and every output reserves at
+    // least 4 bytes per element, so a round covers at most budget / 4
+    // elements.
+    const uint64_t jobs = (uint64_t)c.max_jobs_per_round;
+    const uint64_t elems = c.hbm_budget / 4;
+    const uint64_t chunks = elems / ((uint64_t)kTile * kTilesPerWave * (uint64_t)c.tuning.waves_per_group) + jobs;
+    const uint64_t segs = elems / kSegElems + jobs;
+    for (auto &slot : s->slots) {
+        if (!good) break;
+        size_t cap = 64;
+        while (cap < jobs) cap *= 2;
+        good = reserve_batch(slot.stream, jobs, chunks, segs) &&
+               ok(hipMalloc(&slot.d_res, cap * sizeof(fsz_result))) &&
+               ok(hipHostMalloc(&slot.h_res, cap * sizeof(fsz_result), hipHostMallocDefault));
+        if (good) slot.cap = cap;
+    }
     if (!good) {
         free_server(s);
         return FSZ_ERR_DEVICE;

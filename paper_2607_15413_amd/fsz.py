@@ -289,6 +289,24 @@ def fsz_server_submit(server, requests) -> int:
     return load_library().fsz_server_submit(server, arr, len(requests))
 
 
+def request_table(count: int):
+    """numpy structured array laid out as fsz_request[count] (for large
+    submissions: fill columns vectorized, then fsz_server_submit_table)."""
+    import numpy as np
+    dt = np.dtype({"names": [f[0] for f in FszRequest._fields_],
+                   "formats": [np.int32, np.uint64, np.uint64, np.uint64, np.int32, np.float64, np.uint64,
+                               np.uint64],
+                   "offsets": [getattr(FszRequest, f[0]).offset for f in FszRequest._fields_],
+                   "itemsize": ctypes.sizeof(FszRequest)})
+    return np.zeros(count, dtype=dt)
+
+
+def fsz_server_submit_table(server, table) -> int:
+    """Submit a request_table() array in one call."""
+    ptr = ctypes.cast(table.ctypes.data, ctypes.POINTER(FszRequest))
+    return load_library().fsz_server_submit(server, ptr, len(table))
+
+
 def fsz_server_poll(server, max_count: int = 1024, wait_ms: int = 0):
     """List of FszCompletion (possibly empty)."""
     arr = (FszCompletion * max_count)()
