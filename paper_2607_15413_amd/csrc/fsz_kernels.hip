@@ -87,6 +87,17 @@ __device__ __forceinline__ int wave_incl_scan(int v)
     return v;
 }
 
+// Workgroup barrier that orders LDS only: the waves of a workgroup exchange
+// data through LDS alone, so outstanding global loads and stores (such as
+// the asynchronous copies of a prefetched chunk, which a release fence would
+// wait for) stay in flight across it.  The wave's own LDS accesses complete
+// before the barrier (lgkmcnt(0)); the memory clobber keeps the compiler
+// from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
@@ -701,7 +712,7 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
     cs.wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
     cs.blk_off = cs.tile_excl + group_excl_scan(S, j) + 4u * cs.cent;
     if (lane == 0) sh.wave_total[slot][w] = cs.wave_total;
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) {
         uint32_t chunk_total = 0;
 #pragma unroll
@@ -752,7 +763,7 @@ __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Res
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     const uint64_t base = sh.base;
     const uint64_t tile0 = cs.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     if (a.data0 + base + chunk_total > a.capacity || tile0 >= a.ntiles) return;
@@ -802,7 +813,7 @@ template <typename Shared>
 __device__ __forceinline__ uint64_t next_ticket(unsigned long long *ticket, uint64_t takes, Shared &sh, int &slot)
 {
     if (threadIdx.x == 0) sh.ticket[slot] = take_ticket(ticket, takes);
-    __syncthreads();
+    lds_barrier();
     const uint64_t t = sh.ticket[slot];
     slot ^= 1;
     return t;
@@ -863,6 +874,153 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
     compress_chunk<ALIGNED, LOAD_STAGED, STORE_STAGED, kWaves>(a, chunk, sh, st);
 }
 
+// ------------------------------------------------------------------ pipelined compress
+//
+// Persistent form of the compression kernel for 16-byte aligned inputs: each
+// workgroup keeps the next chunk's input in flight while it works on the
+// current ones, through asynchronous global->LDS copies that hold no
+// registers.  Per iteration, with chunk c rate-passed and chunk c+1 landing
+// in LDS:
+//   take the ticket of chunk c+2; read chunk c+1 from LDS; start copying
+//   chunk c+2 into the other buffer; rate pass of c+1 (its aggregate is
+//   published at once); lookback of c (its predecessors published theirs
+//   long ago); encode c into the buffer c+1 was read from.
+// The LDS image of a wave's 8 tiles is unpadded and rotated: piece m (16 B)
+// of block b sits at 16-byte slot 8b + ((m + b) & 7), so that both the
+// copies (each instruction covers 1 KiB of contiguous input) and the
+// lane-per-block reads (lane b reads piece m at step m) are free of bank
+// conflicts.
+
+constexpr int kPipeWaveDwords = 2056;  // 8 tiles of input, or the wave's output (<= 8 x 1028 B)
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Input of the wave's 8 tiles (element e0 onward, all in bounds) -> LDS.
+__device__ __forceinline__ void chunk_copy_async(const float *__restrict__ x, uint64_t e0, uint32_t *wbuf, int lane)
+{
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int b = 8 * k + (lane >> 3);
+        const int m = ((lane & 7) - b) & 7;
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(x + e0 + 32 * b + 4 * m),
+                                         (lds_void *)(wbuf + 256 * k), 16, 0, 0);
+    }
+}
+
+// Same image, loaded synchronously; elements at or beyond n read as +0.
+__device__ __forceinline__ void chunk_copy_sync(const float *__restrict__ x, uint64_t n, uint64_t e0, uint32_t *wbuf,
+                                                int lane)
+{
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int b = 8 * k + (lane >> 3);
+        const int m = ((lane & 7) - b) & 7;
+        const uint64_t e = e0 + 32 * b + 4 * m;
+        f4 f;
+        f.x = e + 0 < n ? x[e + 0] : 0.0f;
+        f.y = e + 1 < n ? x[e + 1] : 0.0f;
+        f.z = e + 2 < n ? x[e + 2] : 0.0f;
+        f.w = e + 3 < n ? x[e + 3] : 0.0f;
+        *reinterpret_cast<f4 *>(wbuf + 4 * (64 * k + lane)) = f;
+    }
+}
+
+// Starts bringing the wave's part of `chunk` into wbuf.
+__device__ __forceinline__ void chunk_fetch(const CompressArgs &a, uint64_t chunk, uint32_t *wbuf, int w, int lane)
+{
+    const uint64_t e0 = (chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave) * kTile;
+    if (e0 + kTilesPerWave * kTile <= a.n)
+        chunk_copy_async(a.x, e0, wbuf, lane);
+    else
+        chunk_copy_sync(a.x, a.n, e0, wbuf, lane);
+}
+
+// Lane-per-block read of the wave's image (block = lane).
+__device__ __forceinline__ void chunk_read(const uint32_t *wbuf, int lane, int (&v)[32])
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's copies have landed
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int t = 0; t < 8; t++) {
+        const int slot = 8 * lane + ((t + lane) & 7);
+        const f4 f = *reinterpret_cast<const f4 *>(wbuf + 4 * slot);
+        v[4 * t + 0] = __float_as_int(f.x);
+        v[4 * t + 1] = __float_as_int(f.y);
+        v[4 * t + 2] = __float_as_int(f.z);
+        v[4 * t + 3] = __float_as_int(f.w);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+struct PipeShared {
+    CompressShared<kWaves> c;
+};
+
+// One pipeline step: read chunk nxt (landing in nbuf), start chunk c2 into
+// obuf, rate pass of nxt into (y, cn), then lookback + encode of cur (x, cs)
+// staged in nbuf.
+__device__ __forceinline__ void pipe_step(const CompressArgs &a, const Resolved &R, int (&x)[32], const ChunkState &cs,
+                                          int pslot, uint64_t nxt, uint64_t c2, int (&y)[32], ChunkState &cn,
+                                          uint32_t *nbuf, uint32_t *obuf, CompressShared<kWaves> &sh, int w, int lane)
+{
+    if (nxt < a.nchunks) {
+        chunk_read(nbuf, lane, y);
+        if (c2 < a.nchunks) chunk_fetch(a, c2, obuf, w, lane);
+        cn = compress_rates<kWaves>(a, R, nxt, y, pslot ^ 1, sh);
+    }
+    compress_encode<true, kWaves>(a, R, cs, x, pslot, sh, nbuf);
+}
+
+__global__ __launch_bounds__(kThreads) void compress_pipe_kernel(CompressArgs a)
+{
+    __shared__ CompressShared<kWaves> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t bufA[kWaves * kPipeWaveDwords];
+    __shared__ __attribute__((aligned(16))) uint32_t bufB[kWaves * kPipeWaveDwords];
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    uint32_t *ba = bufA + w * kPipeWaveDwords;
+    uint32_t *bb = bufB + w * kPipeWaveDwords;
+    const uint64_t takes = a.nchunks + gridDim.x;
+    int tslot = 0;
+
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status != FSZ_OK) {  // no data work: hand out the tickets, the last chunk reports
+        for (;;) {
+            const uint64_t t = next_ticket(a.ticket, takes, sh, tslot);
+            if (t >= a.nchunks) return;
+            if (tid == 0 && t == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
+        }
+    }
+
+    uint64_t cur = next_ticket(a.ticket, takes, sh, tslot);
+    if (cur >= a.nchunks) return;
+    chunk_fetch(a, cur, ba, w, lane);
+    uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
+    int x[32], y[32];
+    chunk_read(ba, lane, x);
+    if (nxt < a.nchunks) chunk_fetch(a, nxt, bb, w, lane);
+    ChunkState cs = compress_rates<kWaves>(a, R, cur, x, 0, sh);
+    ChunkState cn = cs;
+    // x/cs = chunk in slot 0 (input buffer A consumed), nxt lands in B
+    for (;;) {
+        uint64_t c2 = a.nchunks;
+        if (nxt < a.nchunks) c2 = next_ticket(a.ticket, takes, sh, tslot);
+        pipe_step(a, R, x, cs, 0, nxt, c2, y, cn, bb, ba, sh, w, lane);
+        if (nxt >= a.nchunks) return;
+        // y/cn = chunk nxt in slot 1 (input buffer B consumed), c2 lands in A
+        cur = nxt;
+        nxt = c2;
+        uint64_t c3 = a.nchunks;
+        if (nxt < a.nchunks) c3 = next_ticket(a.ticket, takes, sh, tslot);
+        pipe_step(a, R, y, cn, 1, nxt, c3, x, cs, ba, bb, sh, w, lane);
+        if (nxt >= a.nchunks) return;
+        cur = nxt;
+        nxt = c3;
+    }
+}
+
 // ------------------------------------------------------------------ decompress
 
 // Per-lane state of one chunk between the size pass and the decode pass.
@@ -914,9 +1072,9 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
         sh.wave_total[slot][w] = d.wave_total;
         if (w == 0) sh.bad[slot] = 0;
     }
-    __syncthreads();
+    lds_barrier();
     if (lane == 0 && wave_bad) sh.bad[slot] = 1;
-    __syncthreads();
+    lds_barrier();
     uint32_t chunk_total = 0;
 #pragma unroll
     for (int k = 0; k < W; k++) chunk_total += sh.wave_total[slot][k];
@@ -953,7 +1111,7 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     const uint64_t base = sh.base;
     const uint64_t tile0 = d.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     if (bad || a.data0 + base + chunk_total > total || tile0 >= a.ntiles) return;
@@ -1208,7 +1366,7 @@ __global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
     const int tid = threadIdx.x;
     uint32_t *st = stage + (tid >> 6) * kStageWaveDwords;
     if (tid == 0) tk = take_ticket(b.ticket, b.total_chunks);
-    __syncthreads();
+    lds_barrier();
     const uint64_t t = tk;
     if (t >= b.total_chunks) return;
     const uint32_t job = __builtin_amdgcn_readfirstlane(find_job(b.chunk_end, b.njobs, t));
@@ -1310,6 +1468,12 @@ static hipError_t launch_decompress_t(const DecompressArgs &a, hipStream_t s)
 
 hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s)
 {
+    if (in_aligned16 && tuning().pipe_compress) {
+        static const unsigned cap = persistent_grid(compress_pipe_kernel, ~0ull);
+        const unsigned grid = (unsigned)(a.nchunks < cap ? a.nchunks : cap);
+        hipLaunchKernelGGL(compress_pipe_kernel, dim3(grid), dim3(kThreads), 0, s, a);
+        return hipGetLastError();
+    }
     const bool ls = tuning().staged_compress_loads;
     if (in_aligned16) {
         if (ls) return staged ? launch_compress_t<true, true, true>(a, s) : launch_compress_t<true, true, false>(a, s);
