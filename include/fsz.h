@@ -57,7 +57,7 @@ typedef enum {
 
 /* Field statistics used to resolve the error bound (written by
  * fsz_field_stats, read by fsz_compress_ex).  flags bit 0 = a non-finite
- * value was seen (then xmin/xmax/maxabs cover the finite values only). */
+ * value was seen (then xmin/xmax/maxabs are unspecified). */
 typedef struct {
     float xmin;
     float xmax;

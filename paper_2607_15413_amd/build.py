@@ -17,6 +17,12 @@ ARCH = os.environ.get("FSZ_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["fsz_kernels.hip", "fsz_api.cpp", "fsz_server.cpp"]
 
+# Kernel-file only: every read-modify-write atomic in the kernels is issued by
+# one lane, so the compiler's wave-aggregation rewrite of atomics only adds an
+# immediate wait for the result (which also waits for every earlier memory
+# operation of the wave, such as in-flight prefetches).
+KERNEL_FLAGS = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
+
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -37,7 +43,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = ["hipcc", *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        extra = KERNEL_FLAGS if src.endswith(".hip") else []
+        cmd = ["hipcc", *FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))

@@ -296,7 +296,18 @@ __device__ __forceinline__ void publish_aggregate(unsigned long long *flags, uin
 // the 64 nearest unresolved predecessors; while one of them is not ready the
 // wave re-reads only that single flag word (with a short sleep), so waiting
 // chunks add little memory traffic, and then probes the window again.
-__device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint32_t ep, uint64_t total, bool err)
+// The first window's flags, read ahead of time by the whole wave (lane l
+// reads the flag of chunk - 1 - l); lookback_wait re-reads whatever was not
+// ready yet.
+__device__ __forceinline__ unsigned long long lookback_probe(unsigned long long *flags, uint64_t chunk, uint32_t ep)
+{
+    const long long idx = (long long)chunk - 1 - __lane_id();
+    return idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : pack_flag(kFlagInclusive, ep, false, 0);
+}
+
+__device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint32_t ep, uint64_t total, bool err,
+                                bool has_probe = false, unsigned long long probe = 0)
 {
     const int lane = __lane_id();
     if (chunk == 0) return Prefix{0, err};
@@ -307,11 +318,14 @@ __device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint3
     auto state_of = [&](unsigned long long f) -> uint32_t {
         return (uint32_t)((f >> kEpochShift) & kEpochMask) == ep ? (uint32_t)(f >> 62) : 0u;
     };
+    bool use_probe = has_probe;
     for (;;) {
         const long long idx = pos - lane;
         const unsigned long long f =
-            idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                     : pack_flag(kFlagInclusive, ep, false, 0);
+            use_probe ? probe
+                      : (idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : pack_flag(kFlagInclusive, ep, false, 0));
+        use_probe = false;
         const uint32_t state = state_of(f);
         const unsigned long long not_ready = __ballot(state == 0);
         const unsigned long long incl = __ballot(state == kFlagInclusive);
@@ -451,39 +465,62 @@ __device__ StatsPartial stats_block_reduce(float mn, float mx, float ma, uint32_
     return p;
 }
 
+// Running (min, max, max |x| bit pattern) of a thread.  The largest |x|
+// pattern doubles as the finiteness test: it is >= 0x7F800000 exactly when
+// an Inf or NaN was seen (min and max are then of no use).
+struct RangeAcc {
+    float mn = INFINITY, mx = -INFINITY;
+    uint32_t ma = 0;
+    __device__ __forceinline__ void take(float v)
+    {
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+        ma = max(ma, __float_as_uint(v) & 0x7FFFFFFFu);
+    }
+    __device__ __forceinline__ void take4(const f4 &f)
+    {
+        mn = fminf(fminf(mn, f.x), fminf(fminf(f.y, f.z), f.w));
+        mx = fmaxf(fmaxf(mx, f.x), fmaxf(fmaxf(f.y, f.z), f.w));
+        const uint32_t m = 0x7FFFFFFFu;
+        ma = max(max(ma, __float_as_uint(f.x) & m),
+                 max(max(__float_as_uint(f.y) & m, __float_as_uint(f.z) & m), __float_as_uint(f.w) & m));
+    }
+    __device__ __forceinline__ StatsPartial reduce() const
+    {
+        const uint32_t nf = ma >= 0x7F800000u ? 1u : 0u;
+        return stats_block_reduce(mn, mx, __uint_as_float(ma & 0x7FFFFFFFu), nf);
+    }
+};
+
 // Value-range pass, part 1: one partial (min, max, max|x|, non-finite) per
-// workgroup over a grid-stride slice of x.
+// workgroup over a grid-stride slice of x (four 16-byte loads in flight per
+// thread).
 template <bool ALIGNED>
 __global__ __launch_bounds__(kStatsThreads) void stats_partial_kernel(StatsArgs a)
 {
-    float mn = INFINITY, mx = -INFINITY, ma = 0.0f;
-    uint32_t nonfinite = 0;
-    auto take = [&](float v) {
-        if (__builtin_isfinite(v)) {
-            mn = fminf(mn, v);
-            mx = fmaxf(mx, v);
-            ma = fmaxf(ma, fabsf(v));
-        } else {
-            nonfinite = 1;
-        }
-    };
+    RangeAcc acc;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
     if (ALIGNED) {
         const uint64_t nvec = a.n / 4;
-        const float4 *x4 = reinterpret_cast<const float4 *>(a.x);
-        for (uint64_t i = tid; i < nvec; i += nthreads) {
-            const float4 f = x4[i];
-            take(f.x);
-            take(f.y);
-            take(f.z);
-            take(f.w);
+        const f4 *x4 = reinterpret_cast<const f4 *>(a.x);
+        uint64_t i = tid;
+        for (; i + 3 * nthreads < nvec; i += 4 * nthreads) {
+            const f4 f0 = __builtin_nontemporal_load(x4 + i);
+            const f4 f1 = __builtin_nontemporal_load(x4 + i + nthreads);
+            const f4 f2 = __builtin_nontemporal_load(x4 + i + 2 * nthreads);
+            const f4 f3 = __builtin_nontemporal_load(x4 + i + 3 * nthreads);
+            acc.take4(f0);
+            acc.take4(f1);
+            acc.take4(f2);
+            acc.take4(f3);
         }
-        for (uint64_t i = nvec * 4 + tid; i < a.n; i += nthreads) take(a.x[i]);
+        for (; i < nvec; i += nthreads) acc.take4(x4[i]);
+        for (uint64_t k = nvec * 4 + tid; k < a.n; k += nthreads) acc.take(a.x[k]);
     } else {
-        for (uint64_t i = tid; i < a.n; i += nthreads) take(a.x[i]);
+        for (uint64_t k = tid; k < a.n; k += nthreads) acc.take(a.x[k]);
     }
-    const StatsPartial p = stats_block_reduce(mn, mx, ma, nonfinite);
+    const StatsPartial p = acc.reduce();
     if (threadIdx.x == 0) a.partials[blockIdx.x] = p;
 }
 
@@ -589,6 +626,7 @@ struct ChunkState {
     int carry_b, carry_l1, mu;
     uint32_t vm, r, blk_off, tile_excl, wave_total;
     int order2, cent;
+    uint32_t rbyte;  // the block's rate byte (Sec. III-A)
 };
 
 template <int W>
@@ -605,7 +643,9 @@ struct CompressShared {
 //   3 adaptive select (strict minimum in the order LZ1, LZ2, LZ1c, LZ2c),
 //     rate header; the chunk's byte count is published for the lookback.
 // On return x holds the biased quantized values.
-template <int W>
+// DEFER: leave the rate byte in cs.rbyte for the caller to store, and publish
+// the aggregate from wave 1 (whose memory queue the lookback does not wait on).
+template <int W, bool DEFER = false>
 __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, const Resolved &R, uint64_t chunk,
                                                      int (&x)[32], int slot, CompressShared<W> &sh)
 {
@@ -703,7 +743,8 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
     cs.cent = (dec >> 6) & 1;
     const uint32_t Z = (uint32_t)dec >> 8;
     cs.r = j == 0 ? (uint32_t)(dec & 31) : (cs.order2 ? r2 : r1);
-    if (cnt > 0) a.out[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)(j == 0 ? (dec & 0xFF) : cs.r);
+    cs.rbyte = j == 0 ? (uint32_t)(dec & 0xFF) : cs.r;
+    if (!DEFER && cnt > 0) a.out[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)cs.rbyte;
     const uint32_t S = block_bytes(cs.r);
 
     // ---- offsets inside the wave / chunk, aggregate for the lookback
@@ -713,13 +754,36 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
     cs.blk_off = cs.tile_excl + group_excl_scan(S, j) + 4u * cs.cent;
     if (lane == 0) sh.wave_total[slot][w] = cs.wave_total;
     lds_barrier();
-    if (tid == 0) {
+    if (tid == (DEFER && W > 1 ? 64 : 0)) {
         uint32_t chunk_total = 0;
 #pragma unroll
         for (int k = 0; k < W; k++) chunk_total += sh.wave_total[slot][k];
         publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, false);
     }
     return cs;
+}
+
+// Run by the thread that learns the last chunk's prefix: the stream header,
+// the rate header's zero padding and the call's result.
+__device__ __forceinline__ void finish_stream(const CompressArgs &a, const Resolved &R, const Prefix &pre,
+                                              uint32_t chunk_total)
+{
+    const uint64_t total = a.data0 + pre.excl + chunk_total;
+    uint32_t status = pre.err ? (uint32_t)FSZ_ERR_DEVICE : (uint32_t)FSZ_OK;
+    if (status == FSZ_OK && total > a.capacity) status = FSZ_ERR_CAPACITY;
+    if (status == FSZ_OK) {
+        uint32_t *h = reinterpret_cast<uint32_t *>(a.out);
+        h[0] = 0x315A5346u;  // "FSZ1"
+        h[1] = 1u | ((uint32_t)a.mode << 16) | (R.flags << 24);
+        h[2] = (uint32_t)a.n;
+        h[3] = (uint32_t)(a.n >> 32);
+        h[4] = __float_as_uint(R.E);
+        h[5] = __float_as_uint((float)a.value);
+        h[6] = (uint32_t)total;
+        h[7] = (uint32_t)(total >> 32);
+        for (uint64_t k = kHeaderBytes + a.nblocks; k < a.data0; k++) a.out[k] = 0;
+    }
+    write_final(a.final, total, status, a.epoch);
 }
 
 // Steps 4-5 of one chunk whose rate pass is done: wait for the chunk's output
@@ -743,24 +807,7 @@ __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Res
         const Prefix pre = lookback_wait(a.flags, cs.chunk, a.flag_epoch, chunk_total, false);
         if (lane == 0) {
             sh.base = pre.excl;
-            if (cs.chunk == a.nchunks - 1) {
-                const uint64_t total = a.data0 + pre.excl + chunk_total;
-                uint32_t status = pre.err ? (uint32_t)FSZ_ERR_DEVICE : (uint32_t)FSZ_OK;
-                if (status == FSZ_OK && total > a.capacity) status = FSZ_ERR_CAPACITY;
-                if (status == FSZ_OK) {
-                    uint32_t *h = reinterpret_cast<uint32_t *>(a.out);
-                    h[0] = 0x315A5346u;  // "FSZ1"
-                    h[1] = 1u | ((uint32_t)a.mode << 16) | (R.flags << 24);
-                    h[2] = (uint32_t)a.n;
-                    h[3] = (uint32_t)(a.n >> 32);
-                    h[4] = __float_as_uint(R.E);
-                    h[5] = __float_as_uint((float)a.value);
-                    h[6] = (uint32_t)total;
-                    h[7] = (uint32_t)(total >> 32);
-                    for (uint64_t k = kHeaderBytes + a.nblocks; k < a.data0; k++) a.out[k] = 0;
-                }
-                write_final(a.final, total, status, a.epoch);
-            }
+            if (cs.chunk == a.nchunks - 1) finish_stream(a, R, pre, chunk_total);
         }
     }
     lds_barrier();
@@ -1019,6 +1066,199 @@ __global__ __launch_bounds__(kThreads) void compress_pipe_kernel(CompressArgs a)
         cur = nxt;
         nxt = c3;
     }
+}
+
+// ---- second form of the pipeline: nothing the lookback or the next read
+// waits on is issued just before them.  Vector memory operations of a wave
+// complete in issue order, so every wait also waits for what was issued
+// before it.  Here wave 2 takes the next ticket one step early, wave 1
+// publishes aggregates, wave 0 reads the lookback's first window before the
+// rate pass, rate bytes go out with the chunk's data, and the next chunk is
+// read from LDS after staging but before the stores.  One LDS buffer per wave
+// always receives the copy in flight, the other stages output.
+
+// Lookback of cs.chunk by wave 0 (W0) from the pre-read window `probe`; the
+// last chunk finishes the stream.  Wave 0 also resolves the ticket `traw` it
+// took at the start of the step (resetting the counter if it was the last
+// take) and broadcasts it.  Returns the chunk's exclusive prefix in every
+// thread and the broadcast ticket in *next.
+template <bool W0>
+__device__ __forceinline__ uint64_t pipe2_lookback(const CompressArgs &a, const Resolved &R, const ChunkState &cs,
+                                                   int slot, CompressShared<kWaves> &sh, unsigned long long probe,
+                                                   bool took, unsigned long long traw, uint64_t takes,
+                                                   uint64_t *next)
+{
+    const int lane = threadIdx.x & 63;
+    if (W0) {
+        uint32_t chunk_total = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; k++) chunk_total += sh.wave_total[slot][k];
+        // the probe is consumed on every path (also for chunk 0), so the
+        // next step's read into its register does not wait on stale loads
+        asm volatile("; probe %0" ::"v"(probe));
+        const Prefix pre = lookback_wait(a.flags, cs.chunk, a.flag_epoch, chunk_total, false, true, probe);
+        const unsigned long long tk =
+            took ? ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(traw >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)traw)
+                 : a.nchunks;
+        if (lane == 0) {
+            if (took && tk == takes - 1)
+                __hip_atomic_store(a.ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh.base = pre.excl;
+            sh.ticket[0] = tk;
+            if (cs.chunk == a.nchunks - 1) finish_stream(a, R, pre, chunk_total);
+        }
+    }
+    lds_barrier();
+    *next = sh.ticket[0];
+    return sh.base;
+}
+
+// Residual codes and bit planes of one wave's blocks into its staging area
+// (offsets relative to the wave's first byte).
+__device__ __forceinline__ void pipe2_stage(const ChunkState &cs, int (&B)[32], uint32_t *st)
+{
+    const int j = __lane_id() & 7;
+    if (cs.vm != 0 && j == 0 && cs.cent) st[cs.tile_excl >> 2] = (uint32_t)cs.mu;
+    const unsigned long long o2 = __ballot(cs.order2 != 0);
+    const unsigned long long o1 = __ballot(cs.order2 == 0);
+    if (o2 == 0)
+        block_codes<1>(B, cs.carry_b, cs.carry_l1, j, 0, cs.cent, cs.mu);
+    else if (o1 == 0)
+        block_codes<2>(B, cs.carry_b, cs.carry_l1, j, 1, cs.cent, cs.mu);
+    else
+        block_codes<0>(B, cs.carry_b, cs.carry_l1, j, cs.order2, cs.cent, cs.mu);
+    const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(cs.vm));
+    const uint32_t nwords = cs.r ? cs.r + 1 : 0;
+    uint32_t *words = st + (cs.blk_off >> 2);
+    for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
+        uint32_t Rg[8];
+#pragma unroll
+        for (int rho = 0; rho < 8; rho++)
+            Rg[rho] = pack_byte_g((uint32_t)B[7 - rho], (uint32_t)B[15 - rho], (uint32_t)B[23 - rho],
+                                  (uint32_t)B[31 - rho], g);
+        transpose8(Rg);
+#pragma unroll
+        for (int p = 0; p < 8; p++)
+            if (8 * g + p < nwords) words[8 * g + p] = Rg[p] & keep;
+    }
+}
+
+// One step with chunk A rate-passed (registers xa, wave totals in slot sa),
+// chunk B read (registers yb) and chunk C being copied into qb: rate pass of
+// B, lookback + staging of A, read C into xa, start the copy of the ticket
+// taken in this step, store A.  Returns that ticket (nchunks if none).
+// W0: the calling wave is wave 0, which takes the ticket and reads the
+// lookback window at the start and uses both after the rate pass.
+template <bool W0>
+__device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Resolved &R, uint64_t takes,
+                                               const ChunkState &ca, int (&xa)[32], int sa, uint64_t B,
+                                               int (&yb)[32], ChunkState &cb, uint64_t C, uint32_t *qb,
+                                               uint32_t *pb, CompressShared<kWaves> &sh, int w)
+{
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 7;
+    const bool take = C < a.nchunks;
+    unsigned long long traw = 0, probe = 0;
+    if (W0) {
+        if (take && lane == 0) traw = atomicAdd(a.ticket, 1ull);
+        probe = lookback_probe(a.flags, ca.chunk, a.flag_epoch);
+    }
+    if (B < a.nchunks) cb = compress_rates<kWaves, true>(a, R, B, yb, sa ^ 1, sh);
+    uint64_t D;
+    const uint64_t base = pipe2_lookback<W0>(a, R, ca, sa, sh, probe, take, traw, takes, &D);
+
+    uint32_t chunk_total = 0, wave_base = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; k++) {
+        if (k < w) wave_base += sh.wave_total[sa][k];
+        chunk_total += sh.wave_total[sa][k];
+    }
+    const uint64_t tile0 = ca.chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    const bool ok = a.data0 + base + chunk_total <= a.capacity && tile0 < a.ntiles;
+    if (ok) pipe2_stage(ca, xa, pb);
+    if (C < a.nchunks) chunk_read(qb, lane, xa);
+    if (D < a.nchunks) {
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the read of qb is done before it is overwritten
+        chunk_fetch(a, D, qb, w, lane);
+    }
+    if (ca.vm != 0)
+        a.out[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
+    if (ok) {
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        uint32_t *dst = reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base);
+        for (uint32_t k = lane; k < (ca.wave_total >> 2); k += 64) dst[k] = pb[k];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    return D;
+}
+
+// The whole pipeline of one wave (W0: wave 0's role), from the first ticket on.
+template <bool W0>
+__device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved &R, CompressShared<kWaves> &sh,
+                                          uint32_t *qb, uint32_t *pb, int w)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t N = a.nchunks;
+    const uint64_t takes = N + gridDim.x;
+    int tslot = 0;
+    const uint64_t A = next_ticket(a.ticket, takes, sh, tslot);
+    if (A >= N) return;
+    chunk_fetch(a, A, qb, w, lane);
+    uint64_t B = next_ticket(a.ticket, takes, sh, tslot);
+    int x[32], y[32];
+    chunk_read(qb, lane, x);
+    if (B < N) {
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        chunk_fetch(a, B, qb, w, lane);
+    }
+    ChunkState ca = compress_rates<kWaves, true>(a, R, A, x, 0, sh);
+    ChunkState cb = ca;
+    uint64_t C = N;
+    if (B < N) {
+        C = next_ticket(a.ticket, takes, sh, tslot);
+        chunk_read(qb, lane, y);
+        if (C < N) {
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            chunk_fetch(a, C, qb, w, lane);
+        }
+    }
+    // loop invariant: A rate-passed in x (slot 0), B read into y, C in flight
+    for (;;) {
+        const uint64_t D = pipe2_step<W0>(a, R, takes, ca, x, 0, B, y, cb, C, qb, pb, sh, w);
+        if (B >= N) return;
+        const uint64_t E = pipe2_step<W0>(a, R, takes, cb, y, 1, C, x, ca, D, qb, pb, sh, w);
+        if (C >= N) return;
+        B = D;
+        C = E;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void compress_pipe2_kernel(CompressArgs a)
+{
+    __shared__ CompressShared<kWaves> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t inbuf[kWaves * kPipeWaveDwords];
+    __shared__ __attribute__((aligned(16))) uint32_t stbuf[kWaves * kPipeWaveDwords];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    uint32_t *qb = inbuf + w * kPipeWaveDwords;
+    uint32_t *pb = stbuf + w * kPipeWaveDwords;
+
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status != FSZ_OK) {  // no data work: hand out the tickets, the last chunk reports
+        const uint64_t takes = a.nchunks + gridDim.x;
+        int tslot = 0;
+        for (;;) {
+            const uint64_t t = next_ticket(a.ticket, takes, sh, tslot);
+            if (t >= a.nchunks) return;
+            if (threadIdx.x == 0 && t == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
+        }
+    }
+    if (w == 0)
+        pipe2_run<true>(a, R, sh, qb, pb, w);
+    else
+        pipe2_run<false>(a, R, sh, qb, pb, w);
 }
 
 // ------------------------------------------------------------------ decompress
@@ -1308,32 +1548,17 @@ __global__ __launch_bounds__(kStatsThreads) void batch_stats_kernel(BatchArgs b)
     const float *x = static_cast<const float *>(J.src);
     const uint64_t e0 = (seg - J.seg_base) * kSegElems;
     const uint64_t e1 = J.n - e0 < (uint64_t)kSegElems ? J.n : e0 + kSegElems;
-    float mn = INFINITY, mx = -INFINITY, ma = 0.0f;
-    uint32_t nonfinite = 0;
-    auto take = [&](float v) {
-        if (__builtin_isfinite(v)) {
-            mn = fminf(mn, v);
-            mx = fmaxf(mx, v);
-            ma = fmaxf(ma, fabsf(v));
-        } else {
-            nonfinite = 1;
-        }
-    };
+    RangeAcc acc;
     const int tid = threadIdx.x;
     if (ALIGNED && e1 - e0 == (uint64_t)kSegElems) {
         const f4 *x4 = reinterpret_cast<const f4 *>(x + e0);
 #pragma unroll 8
-        for (int k = 0; k < kSegElems / (4 * kStatsThreads); k++) {
-            const f4 f = __builtin_nontemporal_load(x4 + k * kStatsThreads + tid);
-            take(f.x);
-            take(f.y);
-            take(f.z);
-            take(f.w);
-        }
+        for (int k = 0; k < kSegElems / (4 * kStatsThreads); k++)
+            acc.take4(__builtin_nontemporal_load(x4 + k * kStatsThreads + tid));
     } else {
-        for (uint64_t i = e0 + tid; i < e1; i += kStatsThreads) take(x[i]);
+        for (uint64_t i = e0 + tid; i < e1; i += kStatsThreads) acc.take(x[i]);
     }
-    const StatsPartial p = stats_block_reduce(mn, mx, ma, nonfinite);
+    const StatsPartial p = acc.reduce();
     if (tid == 0) b.partials[seg] = p;
 }
 
@@ -1468,10 +1693,16 @@ static hipError_t launch_decompress_t(const DecompressArgs &a, hipStream_t s)
 
 hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s)
 {
-    if (in_aligned16 && tuning().pipe_compress) {
+    if (in_aligned16 && tuning().pipe_compress == 1) {
         static const unsigned cap = persistent_grid(compress_pipe_kernel, ~0ull);
         const unsigned grid = (unsigned)(a.nchunks < cap ? a.nchunks : cap);
         hipLaunchKernelGGL(compress_pipe_kernel, dim3(grid), dim3(kThreads), 0, s, a);
+        return hipGetLastError();
+    }
+    if (in_aligned16 && tuning().pipe_compress == 2) {
+        static const unsigned cap = persistent_grid(compress_pipe2_kernel, ~0ull);
+        const unsigned grid = (unsigned)(a.nchunks < cap ? a.nchunks : cap);
+        hipLaunchKernelGGL(compress_pipe2_kernel, dim3(grid), dim3(kThreads), 0, s, a);
         return hipGetLastError();
     }
     const bool ls = tuning().staged_compress_loads;
