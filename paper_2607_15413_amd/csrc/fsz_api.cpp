@@ -27,7 +27,7 @@ const Tuning &tuning()
             v.staged_decompress = std::strchr(e, 'd') != nullptr;
             v.staged_compress_loads = std::strchr(e, 'l') != nullptr;
         }
-        if (const char *e = std::getenv("FSZ_PIPE")) v.pipe_compress = std::atoi(e);
+        if (const char *e = std::getenv("FSZ_PIPE")) v.pipe_compress = std::atoi(e) != 0;
         if (const char *e = std::getenv("FSZ_GRID_FACTOR")) {
             const int f = std::atoi(e);
             if (f >= 1 && f <= 64) v.grid_factor = f;

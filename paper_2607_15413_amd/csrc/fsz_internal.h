@@ -155,7 +155,7 @@ struct Tuning {
     bool staged_compress = true;
     bool staged_decompress = true;
     bool staged_compress_loads = true;
-    int pipe_compress = 2;  // persistent compression with asynchronous LDS prefetch (0 off, 1, 2)
+    bool pipe_compress = true;  // persistent compression with asynchronous LDS prefetch
     int grid_factor = 1;
 };
 const Tuning &tuning();

@@ -926,15 +926,9 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
 // Persistent form of the compression kernel for 16-byte aligned inputs: each
 // workgroup keeps the next chunk's input in flight while it works on the
 // current ones, through asynchronous global->LDS copies that hold no
-// registers.  Per iteration, with chunk c rate-passed and chunk c+1 landing
-// in LDS:
-//   take the ticket of chunk c+2; read chunk c+1 from LDS; start copying
-//   chunk c+2 into the other buffer; rate pass of c+1 (its aggregate is
-//   published at once); lookback of c (its predecessors published theirs
-//   long ago); encode c into the buffer c+1 was read from.
-// The LDS image of a wave's 8 tiles is unpadded and rotated: piece m (16 B)
-// of block b sits at 16-byte slot 8b + ((m + b) & 7), so that both the
-// copies (each instruction covers 1 KiB of contiguous input) and the
+// registers.  The LDS image of a wave's 8 tiles is unpadded and rotated:
+// piece m (16 B) of block b sits at 16-byte slot 8b + ((m + b) & 7), so that
+// both the copies (each instruction covers 1 KiB of contiguous input) and the
 // lane-per-block reads (lane b reads piece m at step m) are free of bank
 // conflicts.
 
@@ -1000,82 +994,14 @@ __device__ __forceinline__ void chunk_read(const uint32_t *wbuf, int lane, int (
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
-struct PipeShared {
-    CompressShared<kWaves> c;
-};
-
-// One pipeline step: read chunk nxt (landing in nbuf), start chunk c2 into
-// obuf, rate pass of nxt into (y, cn), then lookback + encode of cur (x, cs)
-// staged in nbuf.
-__device__ __forceinline__ void pipe_step(const CompressArgs &a, const Resolved &R, int (&x)[32], const ChunkState &cs,
-                                          int pslot, uint64_t nxt, uint64_t c2, int (&y)[32], ChunkState &cn,
-                                          uint32_t *nbuf, uint32_t *obuf, CompressShared<kWaves> &sh, int w, int lane)
-{
-    if (nxt < a.nchunks) {
-        chunk_read(nbuf, lane, y);
-        if (c2 < a.nchunks) chunk_fetch(a, c2, obuf, w, lane);
-        cn = compress_rates<kWaves>(a, R, nxt, y, pslot ^ 1, sh);
-    }
-    compress_encode<true, kWaves>(a, R, cs, x, pslot, sh, nbuf);
-}
-
-__global__ __launch_bounds__(kThreads) void compress_pipe_kernel(CompressArgs a)
-{
-    __shared__ CompressShared<kWaves> sh;
-    __shared__ __attribute__((aligned(16))) uint32_t bufA[kWaves * kPipeWaveDwords];
-    __shared__ __attribute__((aligned(16))) uint32_t bufB[kWaves * kPipeWaveDwords];
-    const int tid = threadIdx.x;
-    const int w = tid >> 6;
-    const int lane = tid & 63;
-    uint32_t *ba = bufA + w * kPipeWaveDwords;
-    uint32_t *bb = bufB + w * kPipeWaveDwords;
-    const uint64_t takes = a.nchunks + gridDim.x;
-    int tslot = 0;
-
-    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
-    if (R.status != FSZ_OK) {  // no data work: hand out the tickets, the last chunk reports
-        for (;;) {
-            const uint64_t t = next_ticket(a.ticket, takes, sh, tslot);
-            if (t >= a.nchunks) return;
-            if (tid == 0 && t == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
-        }
-    }
-
-    uint64_t cur = next_ticket(a.ticket, takes, sh, tslot);
-    if (cur >= a.nchunks) return;
-    chunk_fetch(a, cur, ba, w, lane);
-    uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
-    int x[32], y[32];
-    chunk_read(ba, lane, x);
-    if (nxt < a.nchunks) chunk_fetch(a, nxt, bb, w, lane);
-    ChunkState cs = compress_rates<kWaves>(a, R, cur, x, 0, sh);
-    ChunkState cn = cs;
-    // x/cs = chunk in slot 0 (input buffer A consumed), nxt lands in B
-    for (;;) {
-        uint64_t c2 = a.nchunks;
-        if (nxt < a.nchunks) c2 = next_ticket(a.ticket, takes, sh, tslot);
-        pipe_step(a, R, x, cs, 0, nxt, c2, y, cn, bb, ba, sh, w, lane);
-        if (nxt >= a.nchunks) return;
-        // y/cn = chunk nxt in slot 1 (input buffer B consumed), c2 lands in A
-        cur = nxt;
-        nxt = c2;
-        uint64_t c3 = a.nchunks;
-        if (nxt < a.nchunks) c3 = next_ticket(a.ticket, takes, sh, tslot);
-        pipe_step(a, R, y, cn, 1, nxt, c3, x, cs, ba, bb, sh, w, lane);
-        if (nxt >= a.nchunks) return;
-        cur = nxt;
-        nxt = c3;
-    }
-}
-
-// ---- second form of the pipeline: nothing the lookback or the next read
-// waits on is issued just before them.  Vector memory operations of a wave
-// complete in issue order, so every wait also waits for what was issued
-// before it.  Here wave 2 takes the next ticket one step early, wave 1
-// publishes aggregates, wave 0 reads the lookback's first window before the
-// rate pass, rate bytes go out with the chunk's data, and the next chunk is
-// read from LDS after staging but before the stores.  One LDS buffer per wave
-// always receives the copy in flight, the other stages output.
+// The pipeline keeps every wait away from memory operations issued just
+// before it: the vector memory operations of a wave complete in issue order,
+// so a wait also waits for everything issued earlier.  Per step, wave 0 takes
+// the next ticket and reads the lookback's first window before the rate
+// pass and uses both after it; wave 1 publishes the aggregates; rate bytes go
+// out with the chunk's data; the next chunk is read from LDS after staging
+// but before the stores.  One LDS buffer per wave always receives the copy in
+// flight, the other stages output.
 
 // Lookback of cs.chunk by wave 0 (W0) from the pre-read window `probe`; the
 // last chunk finishes the stream.  Wave 0 also resolves the ticket `traw` it
@@ -1693,13 +1619,7 @@ static hipError_t launch_decompress_t(const DecompressArgs &a, hipStream_t s)
 
 hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s)
 {
-    if (in_aligned16 && tuning().pipe_compress == 1) {
-        static const unsigned cap = persistent_grid(compress_pipe_kernel, ~0ull);
-        const unsigned grid = (unsigned)(a.nchunks < cap ? a.nchunks : cap);
-        hipLaunchKernelGGL(compress_pipe_kernel, dim3(grid), dim3(kThreads), 0, s, a);
-        return hipGetLastError();
-    }
-    if (in_aligned16 && tuning().pipe_compress == 2) {
+    if (in_aligned16 && tuning().pipe_compress) {
         static const unsigned cap = persistent_grid(compress_pipe2_kernel, ~0ull);
         const unsigned grid = (unsigned)(a.nchunks < cap ? a.nchunks : cap);
         hipLaunchKernelGGL(compress_pipe2_kernel, dim3(grid), dim3(kThreads), 0, s, a);
