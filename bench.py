@@ -7,9 +7,12 @@ asynchronously on one stream (inputs and outputs resident in HBM).
 
 Printed JSON line (rank 0): value = original bytes compressed + decompressed
 per second over the timed steps (GB/s, 1 GB = 1e9 B), with per-bound
-compress / decompress GB/s (4n / kernel time), compression ratios, the
-roofline of the dominant kernel measured with HIP events on the launch
-stream, and the CPU oracle timed on the host as a baseline.
+compress / decompress GB/s (4n / kernel time), compression ratios and
+max|x - x'|/eb, the roofline of the dominant kernel measured with HIP events
+on the launch stream, a plain device copy as the practical ceiling, the CPU
+oracle timed on the host as a baseline, the batched form against per-field
+calls on 64 uneven fields, and the two smaller field configurations.
+`--served` runs the served request loop instead (its own JSON line).
 """
 from __future__ import annotations
 
@@ -373,6 +376,75 @@ def served_benchmark(args):
     print(json.dumps(line), flush=True)
 
 
+def small_configs(torch, fsz, workloads, verify: bool, reps: int = 20):
+    """The 2^20 sinusoid field (REL 1e-3; warm and MALL-flushed) and the
+    100x500x500 piecewise-quadratic field (REL 1e-2/1e-3/1e-4; flushed: a
+    512 MB scratch buffer is rewritten before every timed call, since both
+    fields fit in the 256 MB MALL).  Median of `reps` calls per row, HIP
+    events around each asynchronous call (range pass precomputed)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    scratch = torch.empty(128 << 20, dtype=torch.float32, device=dev)  # 512 MiB
+    rows = []
+    cases = [("sinusoid 2^20, seed 0", workloads.sinusoid_field(1 << 20, 0), [1e-3], [False, True]),
+             ("piecewise quadratic 100x500x500, seed 2", workloads.piecewise_quadratic((100, 500, 500), 2),
+              [1e-2, 1e-3, 1e-4], [True])]
+    for name, x_np, rels, modes in cases:
+        n = x_np.size
+        x = torch.from_numpy(x_np).to(dev)
+        cap = fsz.fsz_compressed_bound(n)
+        out = torch.empty(cap, dtype=torch.uint8, device=dev)
+        y = torch.empty(n, dtype=torch.float32, device=dev)
+        stats = fsz.field_stats(x)
+        res = torch.zeros(4, dtype=torch.int32, device=dev)
+        st_np = stats.cpu().numpy().view(np.float32)
+        span = float(st_np[1]) - float(st_np[0])
+        for rel in rels:
+            for flushed in modes:
+                def timed(fn):
+                    ts = []
+                    for it in range(reps + 3):
+                        if flushed:
+                            scratch.fill_(float(it))
+                        a = torch.cuda.Event(enable_timing=True)
+                        b = torch.cuda.Event(enable_timing=True)
+                        a.record(stream)
+                        fn()
+                        b.record(stream)
+                        torch.cuda.synchronize()
+                        if it >= 3:
+                            ts.append(a.elapsed_time(b))
+                    return float(np.median(ts))
+                c_ms = timed(lambda: fsz.fsz_compress_async(x.data_ptr(), n, fsz.FSZ_REL, rel, stats.data_ptr(),
+                                                            out.data_ptr(), cap, res.data_ptr(), sh))
+                size, st, _ = fsz.read_result(res)
+                if st != fsz.FSZ_OK:
+                    raise RuntimeError(f"{name}: {fsz.fsz_status_string(st)}")
+                d_ms = timed(lambda: fsz.fsz_decompress_async(out.data_ptr(), size, y.data_ptr(), n,
+                                                              res.data_ptr(), sh))
+                _, st, _ = fsz.read_result(res)
+                if st != fsz.FSZ_OK:
+                    raise RuntimeError(f"{name}: {fsz.fsz_status_string(st)}")
+                eb = rel * span
+                err = float((x.double() - y.double()).abs().max().item()) / eb
+                identical = None
+                if verify:
+                    import oracle
+                    identical = out[:size].cpu().numpy().tobytes() == oracle.compress(x_np, oracle.REL, rel)
+                alg = 4 * n + size
+                rows.append({
+                    "config": name, "rel": rel, "flushed": flushed, "cr": round(4 * n / size, 4),
+                    "compress_GBps": round(4 * n / c_ms / 1e6, 1), "decompress_GBps": round(4 * n / d_ms / 1e6, 1),
+                    "compress_hbm_frac": round(alg / c_ms / 1e6 / HBM_PEAK_GBPS, 4),
+                    "decompress_hbm_frac": round(alg / d_ms / 1e6 / HBM_PEAK_GBPS, 4),
+                    "compress_ms": round(c_ms, 4), "decompress_ms": round(d_ms, 4),
+                    "max_err_over_eb": round(err, 6), "oracle_identical": identical,
+                })
+        del x, out, y
+    return rows
+
+
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,7 +455,8 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true", help="skip the byte comparison with the oracle")
     ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched-form comparison on the 64-field workload")
+                    help="skip the batched-form comparison on the 64-field workload and the two small "
+                         "configurations (2^20 sinusoid, 100x500x500 piecewise quadratic)")
     ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--served", action="store_true",
                     help="run the served request-loop workload instead of the default one")
@@ -479,6 +552,16 @@ def main():
     if args.copy_probe:
         y.copy_(x)  # n floats read + n floats written: the counter calibration kernel
         torch.cuda.synchronize()
+    # practical ceiling: a plain device-to-device copy of the field (4n read + 4n written)
+    ca = torch.cuda.Event(enable_timing=True)
+    cb = torch.cuda.Event(enable_timing=True)
+    y.copy_(x)
+    ca.record(stream)
+    for _ in range(10):
+        y.copy_(x)
+    cb.record(stream)
+    torch.cuda.synchronize()
+    copy_GBps = 10 * 8 * n / ca.elapsed_time(cb) / 1e6
 
     comp_ms = [np.mean([ev[s][k][0].elapsed_time(ev[s][k][1]) for s in range(args.steps)])
                for k in range(len(RELS))]
@@ -492,12 +575,21 @@ def main():
         check(st, f"decompress result rel={RELS[k]}")
         sizes.append(int(size))
 
+    # pointwise error of every bound's reconstruction, relative to eb
+    st_np = stats.cpu().numpy().view(np.float32)
+    span = float(st_np[1]) - float(st_np[0])
+    max_err = []
+    for k, rel in enumerate(RELS):
+        check(fsz.fsz_decompress(outs[k].data_ptr(), sizes[k], y.data_ptr(), n, sh), "decompress")
+        max_err.append(float((x.double() - y.double()).abs().max().item()) / (rel * span))
+
     per_bound = []
     comp_bytes = dec_bytes = 0
     comp_time = dec_time = 0.0
     for k, rel in enumerate(RELS):
         alg = 4 * n + sizes[k]  # bytes read + written by either direction
         per_bound.append({
+            "max_err_over_eb": round(max_err[k], 6),
             "rel": rel,
             "cr": round(4 * n / sizes[k], 4),
             "stream_bytes": sizes[k],
@@ -564,6 +656,9 @@ def main():
                 "decompress_GBps": round(len(RELS) * 4 * n / t_d / 1e9, 4),
             }
 
+    others = None
+    if not args.no_batched:
+        others = small_configs(torch, fsz, workloads, not args.no_verify)
     batched = None
     if not args.no_batched:
         del outs, y  # room for the 64-field workload
@@ -595,10 +690,12 @@ def main():
         "range_pass_ms": round(stats_ms, 4),
         "compress_end_to_end_GBps": round(len(RELS) * 4 * n / (comp_time + len(RELS) * stats_ms) / 1e6, 1),
         "per_bound": per_bound,
+        "copy_ceiling_GBps": round(copy_GBps, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "oracle_identical": verified,
         "batched": batched,
+        "other_configs": others,
     }
     print(json.dumps(line), flush=True)
 

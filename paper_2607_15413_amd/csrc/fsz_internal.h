@@ -148,9 +148,9 @@ bool reserve_batch(hipStream_t stream, uint64_t jobs, uint64_t chunks, uint64_t 
 
 // Launch tuning knobs, process-wide, read once from the environment:
 // FSZ_STAGED (letters c / d / l: stage compress output / decompress output /
-// compress input through LDS), FSZ_PIPE (0 turns off the pipelined persistent compression
-// for 16-byte aligned inputs) and FSZ_GRID_FACTOR (persistent workgroups per
-// CU slot, default 1).
+// compress input through LDS), FSZ_PIPE (0: no pipelined persistent
+// compression for 16-byte aligned inputs) and FSZ_GRID_FACTOR (persistent
+// workgroups per CU slot, default 1).
 struct Tuning {
     bool staged_compress = true;
     bool staged_decompress = true;
