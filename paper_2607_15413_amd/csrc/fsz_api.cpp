@@ -28,6 +28,14 @@ const Tuning &tuning()
             v.staged_compress_loads = std::strchr(e, 'l') != nullptr;
         }
         if (const char *e = std::getenv("FSZ_PIPE")) v.pipe_compress = std::atoi(e) != 0;
+        if (const char *e = std::getenv("FSZ_PIPE_WAVES")) {
+            const int k = std::atoi(e);
+            if (k == 1 || k == 2 || k == 4 || k == 8) v.pipe_waves = k;
+        }
+        if (const char *e = std::getenv("FSZ_DEC_WAVES")) {
+            const int k = std::atoi(e);
+            if (k == 4 || k == 8 || k == 16) v.dec_waves = k;
+        }
         if (const char *e = std::getenv("FSZ_GRID_FACTOR")) {
             const int f = std::atoi(e);
             if (f >= 1 && f <= 64) v.grid_factor = f;
@@ -205,7 +213,8 @@ fsz_status enqueue_compress(Workspace *ws, const float *d_in, uint64_t n, int mo
     a.stats = d_stats;
     a.value = value;
     a.mode = mode;
-    if (!ensure_flags(ws, a.nchunks)) return FSZ_ERR_DEVICE;
+    // the pipelined kernel may use chunks as small as one wave's 8 tiles
+    if (!ensure_flags(ws, std::max<uint64_t>(a.nchunks, ceil_div(a.ntiles, kTilesPerWave)))) return FSZ_ERR_DEVICE;
     if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
     a.flags = ws->d_flags;
     a.ticket = ws->d_ticket;
@@ -227,7 +236,7 @@ fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_siz
     a.nblocks = ceil_div(n, kBlock);
     a.nchunks = a.ntiles ? ceil_div(a.ntiles, kTilesPerChunk) : 1;
     a.data0 = kHeaderBytes + pad16(a.nblocks);
-    if (!ensure_flags(ws, a.nchunks)) return FSZ_ERR_DEVICE;
+    if (!ensure_flags(ws, std::max<uint64_t>(a.nchunks, ceil_div(a.ntiles, kTilesPerWave)))) return FSZ_ERR_DEVICE;
     if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
     a.flags = ws->d_flags;
     a.ticket = ws->d_ticket;

@@ -149,13 +149,17 @@ bool reserve_batch(hipStream_t stream, uint64_t jobs, uint64_t chunks, uint64_t 
 // Launch tuning knobs, process-wide, read once from the environment:
 // FSZ_STAGED (letters c / d / l: stage compress output / decompress output /
 // compress input through LDS), FSZ_PIPE (0: no pipelined persistent
-// compression for 16-byte aligned inputs) and FSZ_GRID_FACTOR (persistent
-// workgroups per CU slot, default 1).
+// compression for 16-byte aligned inputs), FSZ_PIPE_WAVES (its waves per
+// workgroup: 1, 2, 4 or 8), FSZ_DEC_WAVES (waves per decompression
+// workgroup: 4, 8 or 16) and FSZ_GRID_FACTOR (persistent workgroups per CU slot,
+// default 1).
 struct Tuning {
     bool staged_compress = true;
     bool staged_decompress = true;
     bool staged_compress_loads = true;
     bool pipe_compress = true;  // persistent compression with asynchronous LDS prefetch
+    int pipe_waves = 8;         // waves per workgroup of the pipelined compression (1, 2, 4, 8)
+    int dec_waves = 8;          // waves per workgroup of the decompression (4, 8, 16)
     int grid_factor = 1;
 };
 const Tuning &tuning();

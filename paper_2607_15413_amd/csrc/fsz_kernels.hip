@@ -965,10 +965,11 @@ __device__ __forceinline__ void chunk_copy_sync(const float *__restrict__ x, uin
     }
 }
 
-// Starts bringing the wave's part of `chunk` into wbuf.
+// Starts bringing the wave's part of `chunk` (W waves per chunk) into wbuf.
+template <int W>
 __device__ __forceinline__ void chunk_fetch(const CompressArgs &a, uint64_t chunk, uint32_t *wbuf, int w, int lane)
 {
-    const uint64_t e0 = (chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave) * kTile;
+    const uint64_t e0 = (chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave) * kTile;
     if (e0 + kTilesPerWave * kTile <= a.n)
         chunk_copy_async(a.x, e0, wbuf, lane);
     else
@@ -1008,9 +1009,9 @@ __device__ __forceinline__ void chunk_read(const uint32_t *wbuf, int lane, int (
 // took at the start of the step (resetting the counter if it was the last
 // take) and broadcasts it.  Returns the chunk's exclusive prefix in every
 // thread and the broadcast ticket in *next.
-template <bool W0>
+template <bool W0, int W>
 __device__ __forceinline__ uint64_t pipe2_lookback(const CompressArgs &a, const Resolved &R, const ChunkState &cs,
-                                                   int slot, CompressShared<kWaves> &sh, unsigned long long probe,
+                                                   int slot, CompressShared<W> &sh, unsigned long long probe,
                                                    bool took, unsigned long long traw, uint64_t takes,
                                                    uint64_t *next)
 {
@@ -1018,7 +1019,7 @@ __device__ __forceinline__ uint64_t pipe2_lookback(const CompressArgs &a, const 
     if (W0) {
         uint32_t chunk_total = 0;
 #pragma unroll
-        for (int k = 0; k < kWaves; k++) chunk_total += sh.wave_total[slot][k];
+        for (int k = 0; k < W; k++) chunk_total += sh.wave_total[slot][k];
         // the probe is consumed on every path (also for chunk 0), so the
         // next step's read into its register does not wait on stale loads
         asm volatile("; probe %0" ::"v"(probe));
@@ -1076,11 +1077,11 @@ __device__ __forceinline__ void pipe2_stage(const ChunkState &cs, int (&B)[32], 
 // taken in this step, store A.  Returns that ticket (nchunks if none).
 // W0: the calling wave is wave 0, which takes the ticket and reads the
 // lookback window at the start and uses both after the rate pass.
-template <bool W0>
+template <bool W0, int W>
 __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Resolved &R, uint64_t takes,
                                                const ChunkState &ca, int (&xa)[32], int sa, uint64_t B,
                                                int (&yb)[32], ChunkState &cb, uint64_t C, uint32_t *qb,
-                                               uint32_t *pb, CompressShared<kWaves> &sh, int w)
+                                               uint32_t *pb, CompressShared<W> &sh, int w)
 {
     const int lane = threadIdx.x & 63;
     const int j = lane & 7;
@@ -1090,23 +1091,23 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
         if (take && lane == 0) traw = atomicAdd(a.ticket, 1ull);
         probe = lookback_probe(a.flags, ca.chunk, a.flag_epoch);
     }
-    if (B < a.nchunks) cb = compress_rates<kWaves, true>(a, R, B, yb, sa ^ 1, sh);
+    if (B < a.nchunks) cb = compress_rates<W, true>(a, R, B, yb, sa ^ 1, sh);
     uint64_t D;
-    const uint64_t base = pipe2_lookback<W0>(a, R, ca, sa, sh, probe, take, traw, takes, &D);
+    const uint64_t base = pipe2_lookback<W0, W>(a, R, ca, sa, sh, probe, take, traw, takes, &D);
 
     uint32_t chunk_total = 0, wave_base = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; k++) {
+    for (int k = 0; k < W; k++) {
         if (k < w) wave_base += sh.wave_total[sa][k];
         chunk_total += sh.wave_total[sa][k];
     }
-    const uint64_t tile0 = ca.chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    const uint64_t tile0 = ca.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     const bool ok = a.data0 + base + chunk_total <= a.capacity && tile0 < a.ntiles;
     if (ok) pipe2_stage(ca, xa, pb);
     if (C < a.nchunks) chunk_read(qb, lane, xa);
     if (D < a.nchunks) {
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the read of qb is done before it is overwritten
-        chunk_fetch(a, D, qb, w, lane);
+        chunk_fetch<W>(a, D, qb, w, lane);
     }
     if (ca.vm != 0)
         a.out[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
@@ -1122,8 +1123,8 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
 }
 
 // The whole pipeline of one wave (W0: wave 0's role), from the first ticket on.
-template <bool W0>
-__device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved &R, CompressShared<kWaves> &sh,
+template <bool W0, int W>
+__device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved &R, CompressShared<W> &sh,
                                           uint32_t *qb, uint32_t *pb, int w)
 {
     const int lane = threadIdx.x & 63;
@@ -1132,15 +1133,15 @@ __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved 
     int tslot = 0;
     const uint64_t A = next_ticket(a.ticket, takes, sh, tslot);
     if (A >= N) return;
-    chunk_fetch(a, A, qb, w, lane);
+    chunk_fetch<W>(a, A, qb, w, lane);
     uint64_t B = next_ticket(a.ticket, takes, sh, tslot);
     int x[32], y[32];
     chunk_read(qb, lane, x);
     if (B < N) {
         __builtin_amdgcn_s_waitcnt(0xC07F);
-        chunk_fetch(a, B, qb, w, lane);
+        chunk_fetch<W>(a, B, qb, w, lane);
     }
-    ChunkState ca = compress_rates<kWaves, true>(a, R, A, x, 0, sh);
+    ChunkState ca = compress_rates<W, true>(a, R, A, x, 0, sh);
     ChunkState cb = ca;
     uint64_t C = N;
     if (B < N) {
@@ -1148,25 +1149,28 @@ __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved 
         chunk_read(qb, lane, y);
         if (C < N) {
             __builtin_amdgcn_s_waitcnt(0xC07F);
-            chunk_fetch(a, C, qb, w, lane);
+            chunk_fetch<W>(a, C, qb, w, lane);
         }
     }
     // loop invariant: A rate-passed in x (slot 0), B read into y, C in flight
     for (;;) {
-        const uint64_t D = pipe2_step<W0>(a, R, takes, ca, x, 0, B, y, cb, C, qb, pb, sh, w);
+        const uint64_t D = pipe2_step<W0, W>(a, R, takes, ca, x, 0, B, y, cb, C, qb, pb, sh, w);
         if (B >= N) return;
-        const uint64_t E = pipe2_step<W0>(a, R, takes, cb, y, 1, C, x, ca, D, qb, pb, sh, w);
+        const uint64_t E = pipe2_step<W0, W>(a, R, takes, cb, y, 1, C, x, ca, D, qb, pb, sh, w);
         if (C >= N) return;
         B = D;
         C = E;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void compress_pipe2_kernel(CompressArgs a)
+// W waves per workgroup; a chunk is 8 tiles per wave.  a.nchunks must count
+// chunks of that size.
+template <int W>
+__global__ __launch_bounds__(W * 64) void compress_pipe2_kernel(CompressArgs a)
 {
-    __shared__ CompressShared<kWaves> sh;
-    __shared__ __attribute__((aligned(16))) uint32_t inbuf[kWaves * kPipeWaveDwords];
-    __shared__ __attribute__((aligned(16))) uint32_t stbuf[kWaves * kPipeWaveDwords];
+    __shared__ CompressShared<W> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t inbuf[W * kPipeWaveDwords];
+    __shared__ __attribute__((aligned(16))) uint32_t stbuf[W * kPipeWaveDwords];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     uint32_t *qb = inbuf + w * kPipeWaveDwords;
     uint32_t *pb = stbuf + w * kPipeWaveDwords;
@@ -1182,9 +1186,9 @@ __global__ __launch_bounds__(kThreads) void compress_pipe2_kernel(CompressArgs a
         }
     }
     if (w == 0)
-        pipe2_run<true>(a, R, sh, qb, pb, w);
-    else
-        pipe2_run<false>(a, R, sh, qb, pb, w);
+        pipe2_run<true, W>(a, R, sh, qb, pb, w);
+    else if (W > 1)
+        pipe2_run<false, W>(a, R, sh, qb, pb, w);
 }
 
 // ------------------------------------------------------------------ decompress
@@ -1408,11 +1412,13 @@ __device__ __forceinline__ int dec_header(const DecompressArgs &a, float &E, uin
 
 // Persistent decompression kernel: the size pass of the next chunk (which
 // publishes its aggregate) runs before the decode of the current one.
-template <bool ALIGNED, bool STAGED>
-__global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
+// W waves per workgroup; a chunk is 8 tiles per wave (a.nchunks counts chunks
+// of that size).
+template <bool ALIGNED, bool STAGED, int W>
+__global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint32_t stage[STAGED ? kWaves * kStageWaveDwords : 4];
-    __shared__ DecompressShared<kWaves> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t stage[STAGED ? W * kStageWaveDwords : 4];
+    __shared__ DecompressShared<W> sh;
     const int tid = threadIdx.x;
     uint32_t *st = stage + (STAGED ? (tid >> 6) * kStageWaveDwords : 0);
 
@@ -1429,12 +1435,12 @@ __global__ __launch_bounds__(kThreads) void decompress_kernel(DecompressArgs a)
     uint64_t cur = next_ticket(a.ticket, takes, sh, tslot);
     if (cur >= a.nchunks) return;
     int slot = 0;
-    DecChunk dc = dec_sizes<kWaves>(a, cur, slot, sh);
+    DecChunk dc = dec_sizes<W>(a, cur, slot, sh);
     for (;;) {
         const uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
         DecChunk dn;
-        if (nxt < a.nchunks) dn = dec_sizes<kWaves>(a, nxt, slot ^ 1, sh);
-        dec_decode<ALIGNED, STAGED, kWaves>(a, dc, slot, E, total, st, sh);
+        if (nxt < a.nchunks) dn = dec_sizes<W>(a, nxt, slot ^ 1, sh);
+        dec_decode<ALIGNED, STAGED, W>(a, dc, slot, E, total, st, sh);
         if (nxt >= a.nchunks) break;
         dc = dn;
         slot ^= 1;
@@ -1587,12 +1593,12 @@ hipError_t launch_stats(const StatsArgs &a, hipStream_t s)
 // Workgroups of a persistent grid: enough to fill every CU at the kernel's
 // occupancy, never more than there are chunks.
 template <typename K>
-static unsigned persistent_grid(K kernel, uint64_t nchunks)
+static unsigned persistent_grid(K kernel, uint64_t nchunks, int threads = kThreads)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || cus <= 0 ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || cus <= 0 ||
         per_cu <= 0) {
         cus = 256;
         per_cu = 2;
@@ -1608,21 +1614,62 @@ static hipError_t launch_compress_t(const CompressArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <bool ALIGNED, bool STAGED, int W>
+static hipError_t launch_decompress_w(const DecompressArgs &a, hipStream_t s)
+{
+    // the arguments count chunks of kTilesPerChunk tiles
+    DecompressArgs p = a;
+    p.nchunks = p.ntiles ? ceil_div(p.ntiles, (uint64_t)kTilesPerWave * W) : 1;
+    static const unsigned cap = persistent_grid(decompress_kernel<ALIGNED, STAGED, W>, ~0ull, W * 64);
+    const unsigned grid = (unsigned)(p.nchunks < cap ? p.nchunks : cap);
+    hipLaunchKernelGGL((decompress_kernel<ALIGNED, STAGED, W>), dim3(grid), dim3(W * 64), 0, s, p);
+    return hipGetLastError();
+}
+
 template <bool ALIGNED, bool STAGED>
 static hipError_t launch_decompress_t(const DecompressArgs &a, hipStream_t s)
 {
-    static const unsigned cap = persistent_grid(decompress_kernel<ALIGNED, STAGED>, ~0ull);
-    const unsigned grid = (unsigned)(a.nchunks < cap ? a.nchunks : cap);
-    hipLaunchKernelGGL((decompress_kernel<ALIGNED, STAGED>), dim3(grid), dim3(kThreads), 0, s, a);
-    return hipGetLastError();
+    switch (tuning().dec_waves) {
+    case 16: return launch_decompress_w<ALIGNED, STAGED, 16>(a, s);
+    case 8: return launch_decompress_w<ALIGNED, STAGED, 8>(a, s);
+    default: return launch_decompress_w<ALIGNED, STAGED, 4>(a, s);
+    }
 }
 
 hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s)
 {
     if (in_aligned16 && tuning().pipe_compress) {
-        static const unsigned cap = persistent_grid(compress_pipe2_kernel, ~0ull);
-        const unsigned grid = (unsigned)(a.nchunks < cap ? a.nchunks : cap);
-        hipLaunchKernelGGL(compress_pipe2_kernel, dim3(grid), dim3(kThreads), 0, s, a);
+        // the arguments count chunks of kTilesPerChunk tiles; the pipeline's
+        // chunks are 8 tiles per wave
+        CompressArgs p = a;
+        const int W = tuning().pipe_waves;
+        p.nchunks = p.ntiles ? ceil_div(p.ntiles, (uint64_t)kTilesPerWave * W) : 1;
+        switch (W) {
+        case 1: {
+            static const unsigned cap = persistent_grid(compress_pipe2_kernel<1>, ~0ull, 64);
+            hipLaunchKernelGGL(compress_pipe2_kernel<1>, dim3((unsigned)(p.nchunks < cap ? p.nchunks : cap)),
+                               dim3(64), 0, s, p);
+            break;
+        }
+        case 2: {
+            static const unsigned cap = persistent_grid(compress_pipe2_kernel<2>, ~0ull, 128);
+            hipLaunchKernelGGL(compress_pipe2_kernel<2>, dim3((unsigned)(p.nchunks < cap ? p.nchunks : cap)),
+                               dim3(128), 0, s, p);
+            break;
+        }
+        case 8: {
+            static const unsigned cap = persistent_grid(compress_pipe2_kernel<8>, ~0ull, 512);
+            hipLaunchKernelGGL(compress_pipe2_kernel<8>, dim3((unsigned)(p.nchunks < cap ? p.nchunks : cap)),
+                               dim3(512), 0, s, p);
+            break;
+        }
+        default: {
+            static const unsigned cap = persistent_grid(compress_pipe2_kernel<4>, ~0ull, 256);
+            hipLaunchKernelGGL(compress_pipe2_kernel<4>, dim3((unsigned)(p.nchunks < cap ? p.nchunks : cap)),
+                               dim3(256), 0, s, p);
+            break;
+        }
+        }
         return hipGetLastError();
     }
     const bool ls = tuning().staged_compress_loads;
