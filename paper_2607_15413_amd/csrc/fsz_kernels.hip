@@ -87,6 +87,29 @@ __device__ __forceinline__ int wave_incl_scan(int v)
     return v;
 }
 
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v)
+{
+    const uint32_t lo = (uint32_t)dpp<CTRL, ROW_MASK>((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)dpp<CTRL, ROW_MASK>((int)(uint32_t)(v >> 32));
+    return (unsigned long long)hi << 32 | lo;
+}
+
+// sum over the 64 lanes of the wave (register-only prefix, total of lane
+// 63); the result is wave-uniform.  Every lane must be active.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+    v += dpp64<kRowShr1>(v);
+    v += dpp64<kRowShr2>(v);
+    v += dpp64<kRowShr4>(v);
+    v += dpp64<kRowShr8>(v);
+    v += dpp64<kRowBcast15, 0xA>(v);
+    v += dpp64<kRowBcast31, 0xC>(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
+    return (unsigned long long)hi << 32 | lo;
+}
+
 // Workgroup barrier that orders LDS only: the waves of a workgroup exchange
 // data through LDS alone, so outstanding global loads and stores (such as
 // the asynchronous copies of a prefetched chunk, which a release fence would
@@ -98,10 +121,24 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Store of nw dwords from a wave's LDS staging area to global memory at a
+// 4-byte aligned address g, by the whole wave: 4-byte stores up to the first
+// 16-byte boundary of g and after the last one, 16-byte stores in between (a
+// quarter of the store instructions of a dword-wide copy).
+__device__ __forceinline__ void wave_store_staged(uint32_t *g, const uint32_t *st, uint32_t nw, int lane)
 {
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return v;
+    const uint32_t head = min(nw, ((16u - ((uint32_t)(uintptr_t)g & 15u)) & 15u) >> 2);
+    if ((uint32_t)lane < head) g[lane] = st[lane];
+    const uint32_t nq = (nw - head) >> 2;
+    for (uint32_t q = lane; q < nq; q += 64) {
+        const uint32_t o = head + 4 * q;
+        const u32x4 v = {st[o], st[o + 1], st[o + 2], st[o + 3]};
+        *reinterpret_cast<u32x4 *>(g + o) = v;
+    }
+    const uint32_t t0 = head + 4 * nq;
+    if ((uint32_t)lane < nw - t0) g[t0 + lane] = st[t0 + lane];
 }
 
 __device__ __forceinline__ uint32_t uabs(int v) { return v < 0 ? 0u - (uint32_t)v : (uint32_t)v; }
@@ -848,8 +885,7 @@ __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Res
     if (STAGED) {  // coalesced copy of the wave's contiguous output
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        uint32_t *dst = reinterpret_cast<uint32_t *>(wave_out);
-        for (uint32_t k = lane; k < (cs.wave_total >> 2); k += 64) dst[k] = st[k];
+        wave_store_staged(reinterpret_cast<uint32_t *>(wave_out), st, cs.wave_total >> 2, lane);
     }
 }
 
@@ -1114,8 +1150,8 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
     if (ok) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        uint32_t *dst = reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base);
-        for (uint32_t k = lane; k < (ca.wave_total >> 2); k += 64) dst[k] = pb[k];
+        wave_store_staged(reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base), pb, ca.wave_total >> 2,
+                          lane);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
