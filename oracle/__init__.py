@@ -23,6 +23,12 @@ ERR_EB_TOO_LARGE = 8
 ABS = 0
 REL = 1
 
+# feature switches of the ablation (Sec. VI-B); 0 = LZ1 on independent blocks
+FEAT_CROSS_BLOCK = 1
+FEAT_CENTERING = 2
+FEAT_LZ2 = 4
+FEATURES_ALL = 7
+
 _lib = None
 
 
@@ -46,6 +52,11 @@ def _load():
         lib.fszo_resolve.restype = ctypes.c_int
         lib.fszo_compress.argtypes = [p, u64, ctypes.c_int, ctypes.c_double, p, u64, p]
         lib.fszo_compress.restype = ctypes.c_int
+        lib.fszo_compress_features.argtypes = [p, u64, ctypes.c_int, ctypes.c_double, ctypes.c_uint32, p,
+                                               u64, p]
+        lib.fszo_compress_features.restype = ctypes.c_int
+        lib.fszo_tile_eval_features.argtypes = [p, ctypes.c_int, ctypes.c_float, ctypes.c_uint32, p, p, p, p, p]
+        lib.fszo_tile_eval_features.restype = ctypes.c_int
         lib.fszo_decompress.argtypes = [p, u64, p, u64]
         lib.fszo_decompress.restype = ctypes.c_int
         _lib = lib
@@ -71,21 +82,25 @@ def resolve(x, mode: int, value: float):
     return st, E.value, inv.value, flags.value
 
 
-def compress_status(x, mode: int, value: float, capacity=None):
+def compress_status(x, mode: int, value: float, capacity=None, features: int = FEATURES_ALL):
     """Return (status, stream bytes or None)."""
     x = _f32(x)
     cap = bound(x.size) if capacity is None else capacity
     out = np.zeros(max(cap, 1), dtype=np.uint8)
     size = ctypes.c_uint64()
-    st = _load().fszo_compress(x.ctypes.data, x.size, mode, value, out.ctypes.data, cap,
-                               ctypes.byref(size))
+    if features == FEATURES_ALL:
+        st = _load().fszo_compress(x.ctypes.data, x.size, mode, value, out.ctypes.data, cap,
+                                   ctypes.byref(size))
+    else:
+        st = _load().fszo_compress_features(x.ctypes.data, x.size, mode, value, features,
+                                            out.ctypes.data, cap, ctypes.byref(size))
     if st != OK:
         return st, None
     return st, out[: size.value].tobytes()
 
 
-def compress(x, mode: int, value: float) -> bytes:
-    st, s = compress_status(x, mode, value)
+def compress(x, mode: int, value: float, features: int = FEATURES_ALL) -> bytes:
+    st, s = compress_status(x, mode, value, features=features)
     if st != OK:
         raise OracleError(st, "compress")
     return s
@@ -129,3 +144,20 @@ def tile_eval(x, inv: float):
     if st != OK:
         raise OracleError(st, "tile_eval")
     return mu.value, bool(ok.value), cost, rates
+
+
+def tile_eval_features(x, inv: float, features: int):
+    """Evaluation of one tile under a feature subset:
+    (mu, centre_ok, cost[4], rates[4][8], selected variant)."""
+    x = _f32(x)
+    mu = ctypes.c_int32()
+    ok = ctypes.c_int()
+    best = ctypes.c_int()
+    cost = np.zeros(4, dtype=np.uint32)
+    rates = np.zeros((4, 8), dtype=np.uint32)
+    st = _load().fszo_tile_eval_features(x.ctypes.data, x.size, inv, features, ctypes.byref(mu),
+                                         ctypes.byref(ok), cost.ctypes.data, rates.ctypes.data,
+                                         ctypes.byref(best))
+    if st != OK:
+        raise OracleError(st, "tile_eval_features")
+    return mu.value, bool(ok.value), cost, rates, best.value

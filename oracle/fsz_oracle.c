@@ -40,6 +40,16 @@
  *     32-bit word is written most-significant byte first;
  *   - a 32-byte stream header precedes the rate bytes, which are zero-padded
  *     to a multiple of 16 bytes.
+ *
+ * Feature switches (the ablation of Sec. VI-B, Table IV; the base is the
+ * cuSZp-equivalent compressor: LZ1 only, independent blocks, no centering):
+ *   - cross-block state off: the zero predictor state is restored at every
+ *     block start instead of only at the tile start (header flags bit 1, so
+ *     the decoder restarts its running sums there too);
+ *   - centering off / second order off: those variants are never selected.
+ * Centering with independent blocks subtracts the tile mean from every
+ * value, which changes the first residual of every block (and the second
+ * one under LZ2).
  */
 #include "fsz_oracle.h"
 
@@ -196,6 +206,7 @@ int fszo_resolve(const float *x, uint64_t n, int mode, double value,
 /* ------------------------------------------------------------------ */
 
 typedef struct {
+    int indep;                      /* prediction restarts at every block */
     int m;                          /* valid elements in the tile */
     int nb;                         /* blocks in the tile */
     int32_t q[TILE];                /* quantized values */
@@ -209,16 +220,27 @@ typedef struct {
     uint32_t bytes;                 /* selected tile cost C */
 } tile_t;
 
-static void analyse_tile(const float *x, int m, float inv, tile_t *t)
+/* whether a variant may be selected under the feature switches */
+static int variant_allowed(int v, uint32_t features, int centre_ok)
 {
+    if ((v & 1) && !(features & FSZO_FEAT_LZ2)) return 0;
+    if ((v >> 1) && (!(features & FSZO_FEAT_CENTERING) || !centre_ok)) return 0;
+    return 1;
+}
+
+static void analyse_tile(const float *x, int m, float inv, uint32_t features, tile_t *t)
+{
+    t->indep = (features & FSZO_FEAT_CROSS_BLOCK) ? 0 : 1;
     t->m = m;
     t->nb = (m + BLOCK - 1) / BLOCK;
 
     /* Quantize + cross-block LZ1/LZ2 residuals in one loop (Sec. IV-A,
      * Eq. (2); Sec. IV-B items 1-2).  The predictor state runs across all
-     * blocks of the tile; only the tile start has no predecessor. */
+     * blocks of the tile; only the tile start has no predecessor (with
+     * independent blocks, Eq. (1), every block start has none). */
     int32_t qm1 = 0, qm2 = 0;
     for (int i = 0; i < TILE; i++) {
+        if (t->indep && i % BLOCK == 0) qm1 = qm2 = 0;
         if (i < m) {
             float y = x[i] * inv;
             int32_t q = (int32_t)rintf(y);
@@ -246,72 +268,62 @@ static void analyse_tile(const float *x, int m, float inv, tile_t *t)
     t->mu = t->centre_ok ? (int32_t)rintf(mean_q) : 0;
 
     /* Per-block rates.  By the cancellation property (Eq. (4)) the centered
-     * residuals equal the plain ones except the first k of the tile, so blocks
-     * 1..7 have one rate per order and block 0 is adjusted after the loop. */
-    uint32_t r1[BLOCKS_PER_TILE] = {0}, r2[BLOCKS_PER_TILE] = {0};
-    uint32_t inner1 = 0, inner2 = 0; /* block 0 without its first 1 / 2 residuals */
-    for (int b = 0; b < t->nb; b++) {
+     * residuals equal the plain ones except the first one (LZ1) or two (LZ2)
+     * after a prediction restart, so a block without a restart has one rate
+     * per order and a block with one (block 0; every block when blocks are
+     * independent) is rated per variant from its inner residuals and its
+     * first residuals: l[0] = q0 (or q0 - mu), LZ2 l[1] = q1 - 2 q0 (or
+     * q1 - 2 q0 + mu), absent when the block holds fewer than 2 values. */
+    for (int v = 0; v < 4; v++) t->cost[v] = (v >> 1) ? 4 : 0;
+    for (int b = 0; b < BLOCKS_PER_TILE; b++) {
+        if (b >= t->nb) {
+            for (int v = 0; v < 4; v++) t->vrate[v][b] = 0;
+            continue;
+        }
+        int restart = (b == 0 || t->indep);
+        int s0 = b * BLOCK;
         uint32_t a1 = 0, a2 = 0;
-        for (int i = b * BLOCK; i < (b + 1) * BLOCK; i++) {
+        for (int i = s0; i < s0 + BLOCK; i++) {
             uint32_t m1 = magnitude(t->l1[i]), m2 = magnitude(t->l2[i]);
-            if (b > 0 || i >= 1) a1 = m1 > a1 ? m1 : a1;
-            if (b > 0 || i >= 2) a2 = m2 > a2 ? m2 : a2;
+            if (!restart || i >= s0 + 1) a1 = m1 > a1 ? m1 : a1;
+            if (!restart || i >= s0 + 2) a2 = m2 > a2 ? m2 : a2;
         }
-        if (b == 0) {
-            inner1 = a1;
-            inner2 = a2;
-        } else {
-            r1[b] = rate_of(a1);
-            r2[b] = rate_of(a2);
+        for (int v = 0; v < 4; v++) {
+            int ord2 = v & 1, cen = v >> 1;
+            uint32_t a = ord2 ? a2 : a1;
+            if (restart) {
+                int mb = m - s0 < BLOCK ? m - s0 : BLOCK;
+                int32_t q0 = t->q[s0];
+                int32_t d1 = mb >= 2 ? t->l2[s0 + 1] : 0;
+                int32_t f0 = cen ? q0 - t->mu : q0;
+                int32_t f1 = mb >= 2 ? (cen ? d1 + t->mu : d1) : 0;
+                if (magnitude(f0) > a) a = magnitude(f0);
+                if (ord2 && magnitude(f1) > a) a = magnitude(f1);
+            }
+            t->vrate[v][b] = rate_of(a);
+            t->cost[v] += block_cost(t->vrate[v][b]);
         }
-    }
-    /* first residuals of the four variants: l[0] = q0 (or q0 - mu),
-     * LZ2 l[1] = q1 - 2 q0 (or q1 - 2 q0 + mu); absent when m < 2 */
-    int32_t q0 = t->q[0];
-    int32_t d1 = m >= 2 ? t->l2[1] : 0;
-    int32_t c0 = q0 - t->mu;
-    int32_t c1 = m >= 2 ? t->l2[1] + t->mu : 0;
-    uint32_t first[4][2] = {
-        {magnitude(q0), 0},              /* LZ1 */
-        {magnitude(q0), magnitude(d1)},  /* LZ2 */
-        {magnitude(c0), 0},              /* LZ1 + centering */
-        {magnitude(c0), magnitude(c1)},  /* LZ2 + centering */
-    };
-
-    for (int v = 0; v < 4; v++) {
-        int ord2 = v & 1, cen = v >> 1;
-        uint32_t a = ord2 ? inner2 : inner1;
-        if (first[v][0] > a) a = first[v][0];
-        if (first[v][1] > a) a = first[v][1];
-        t->vrate[v][0] = rate_of(a);
-        uint32_t c = block_cost(t->vrate[v][0]) + (cen ? 4 : 0);
-        for (int b = 1; b < BLOCKS_PER_TILE; b++) {
-            t->vrate[v][b] = b < t->nb ? (ord2 ? r2[b] : r1[b]) : 0;
-            c += block_cost(t->vrate[v][b]);
-        }
-        t->cost[v] = c;
     }
 
     /* Adaptive select: minimum C; ties keep the earlier of LZ1, LZ2, LZ1c,
-     * LZ2c; centered variants only with a finite mean. */
+     * LZ2c; centered variants only with a finite mean; variants switched
+     * off are never selected (LZ1 always may be). */
     int best = 0;
-    if (t->cost[1] < t->cost[best]) best = 1;
-    if (t->centre_ok) {
-        if (t->cost[2] < t->cost[best]) best = 2;
-        if (t->cost[3] < t->cost[best]) best = 3;
-    }
+    for (int v = 1; v < 4; v++)
+        if (variant_allowed(v, features, t->centre_ok) && t->cost[v] < t->cost[best]) best = v;
     t->order2 = best & 1;
     t->centred = best >> 1;
     t->bytes = t->cost[best];
     for (int b = 0; b < BLOCKS_PER_TILE; b++) t->rate[b] = t->vrate[best][b];
 }
 
-int fszo_tile_eval(const float *x, int m, float inv, int32_t *mu, int *centre_ok,
-                   uint32_t *cost4, uint32_t *rates4x8)
+int fszo_tile_eval_features(const float *x, int m, float inv, uint32_t features, int32_t *mu,
+                            int *centre_ok, uint32_t *cost4, uint32_t *rates4x8, int *best)
 {
-    if (m < 1 || m > TILE) return FSZO_ERR_INVALID_ARG;
+    if (m < 1 || m > TILE || (features & ~(uint32_t)FSZO_FEATURES_ALL)) return FSZO_ERR_INVALID_ARG;
     tile_t t;
-    analyse_tile(x, m, inv, &t);
+    analyse_tile(x, m, inv, features, &t);
+    *best = t.order2 | (t.centred << 1);
     *mu = t.mu;
     *centre_ok = t.centre_ok;
     for (int v = 0; v < 4; v++) {
@@ -321,14 +333,22 @@ int fszo_tile_eval(const float *x, int m, float inv, int32_t *mu, int *centre_ok
     return FSZO_OK;
 }
 
+int fszo_tile_eval(const float *x, int m, float inv, int32_t *mu, int *centre_ok,
+                   uint32_t *cost4, uint32_t *rates4x8)
+{
+    int best;
+    return fszo_tile_eval_features(x, m, inv, FSZO_FEATURES_ALL, mu, centre_ok, cost4, rates4x8, &best);
+}
+
 /* residual of the selected variant at tile position i */
 static int32_t selected_residual(const tile_t *t, int i)
 {
     if (i >= t->m) return 0;
     int32_t e = t->order2 ? t->l2[i] : t->l1[i];
     if (t->centred) {
-        if (i == 0) e = t->q[0] - t->mu;
-        else if (i == 1 && t->order2) e = t->l2[1] + t->mu;
+        int s0 = t->indep ? i / BLOCK * BLOCK : 0; /* start of the prediction run */
+        if (i == s0) e = t->q[i] - t->mu;
+        else if (i == s0 + 1 && t->order2) e = t->l2[i] + t->mu;
     }
     return e;
 }
@@ -356,9 +376,10 @@ static uint8_t *encode_block(const tile_t *t, int b, uint8_t *p)
     return p;
 }
 
-int fszo_compress(const float *x, uint64_t n, int mode, double value,
-                  uint8_t *out, uint64_t cap, uint64_t *out_size)
+int fszo_compress_features(const float *x, uint64_t n, int mode, double value, uint32_t features,
+                           uint8_t *out, uint64_t cap, uint64_t *out_size)
 {
+    if (features & ~(uint32_t)FSZO_FEATURES_ALL) return FSZO_ERR_INVALID_ARG;
     float E, inv;
     uint32_t flags;
     int st = fszo_resolve(x, n, mode, value, &E, &inv, &flags);
@@ -379,7 +400,7 @@ int fszo_compress(const float *x, uint64_t n, int mode, double value,
     for (uint64_t t = 0; t < ntiles; t++) {
         uint64_t start = t * TILE;
         int m = (int)(n - start < TILE ? n - start : TILE);
-        analyse_tile(x + start, m, inv, &tiles[t]);
+        analyse_tile(x + start, m, inv, features, &tiles[t]);
     }
 
     /* Pass 2: exclusive prefix sum of tile sizes (Sec. IV-D). */
@@ -400,7 +421,7 @@ int fszo_compress(const float *x, uint64_t n, int mode, double value,
     out[3] = '1';
     put_u16(out + 4, 1);
     out[6] = (uint8_t)mode;
-    out[7] = (uint8_t)flags;
+    out[7] = (uint8_t)(flags | ((features & FSZO_FEAT_CROSS_BLOCK) ? 0u : 2u));
     put_u64(out + 8, n);
     put_u32(out + 16, float_to_bits(E));
     put_u32(out + 20, float_to_bits((float)value));
@@ -433,6 +454,12 @@ int fszo_compress(const float *x, uint64_t n, int mode, double value,
     return FSZO_OK;
 }
 
+int fszo_compress(const float *x, uint64_t n, int mode, double value,
+                  uint8_t *out, uint64_t cap, uint64_t *out_size)
+{
+    return fszo_compress_features(x, n, mode, value, FSZO_FEATURES_ALL, out, cap, out_size);
+}
+
 /* ------------------------------------------------------------------ */
 /* decompression (Sec. III-A, decompression steps 1-5)                 */
 /* ------------------------------------------------------------------ */
@@ -442,7 +469,8 @@ int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t 
     if (cmp_size < HEADER_BYTES) return FSZO_ERR_CORRUPT;
     if (cmp[0] != 'F' || cmp[1] != 'S' || cmp[2] != 'Z' || cmp[3] != '1') return FSZO_ERR_CORRUPT;
     if ((cmp[4] | (cmp[5] << 8)) != 1) return FSZO_ERR_CORRUPT;
-    if (cmp[6] > 1 || (cmp[7] & ~1u) != 0) return FSZO_ERR_CORRUPT;
+    if (cmp[6] > 1 || (cmp[7] & ~3u) != 0) return FSZO_ERR_CORRUPT;
+    int indep = (cmp[7] >> 1) & 1; /* independent blocks: sums restart per block */
     uint64_t hn = get_u64(cmp + 8);
     if (hn != n) return FSZO_ERR_SIZE_MISMATCH;
     float E = bits_to_float(get_u32(cmp + 16));
@@ -513,6 +541,7 @@ int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t 
          * 32-bit arithmetic, so corrupt streams cannot overflow) */
         uint32_t acc1 = 0, acc2 = 0;
         for (int i = 0; i < m; i++) {
+            if (indep && i % BLOCK == 0) acc1 = acc2 = 0;
             acc1 += e[i];
             uint32_t qhat;
             if (order2) {

@@ -28,6 +28,16 @@ enum {
     FSZO_ERR_EB_TOO_LARGE = 8
 };
 
+/* Feature switches of the ablation (Sec. VI-B): cross-block prediction
+ * state, adaptive centering, second-order Lorenzo.  0 = the cuSZp-equivalent
+ * base (LZ1 on independent blocks), all three = the full method. */
+enum {
+    FSZO_FEAT_CROSS_BLOCK = 1,
+    FSZO_FEAT_CENTERING = 2,
+    FSZO_FEAT_LZ2 = 4,
+    FSZO_FEATURES_ALL = 7
+};
+
 /* Worst-case stream size for n floats. */
 uint64_t fszo_bound(uint64_t n);
 
@@ -40,11 +50,21 @@ int fszo_resolve(const float *x, uint64_t n, int mode, double value,
 int fszo_compress(const float *x, uint64_t n, int mode, double value,
                   uint8_t *out, uint64_t cap, uint64_t *out_size);
 
+/* Compression with a subset of the features (header flags bit 1 marks
+ * independent blocks). */
+int fszo_compress_features(const float *x, uint64_t n, int mode, double value, uint32_t features,
+                           uint8_t *out, uint64_t cap, uint64_t *out_size);
+
 /* Four-way evaluation of one tile of m (1..256) floats with reciprocal step
  * inv: quantized mean, whether centering is allowed, the cost C of LZ1, LZ2,
  * LZ1c, LZ2c and their per-block rates (4 x 8, row per variant). */
 int fszo_tile_eval(const float *x, int m, float inv, int32_t *mu, int *centre_ok,
                    uint32_t *cost4, uint32_t *rates4x8);
+
+/* The same evaluation under a feature subset; *best = the selected variant
+ * (order2 | centred << 1).  cost4/rates4x8 cover all four variants. */
+int fszo_tile_eval_features(const float *x, int m, float inv, uint32_t features, int32_t *mu,
+                            int *centre_ok, uint32_t *cost4, uint32_t *rates4x8, int *best);
 
 /* Full decompression of a stream of cmp_size bytes into n floats. */
 int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t n);

@@ -91,9 +91,13 @@ def pairwise_mean(xt: np.ndarray, inv: float):
     return True, int(np.rint(v))
 
 
-def residuals(q: np.ndarray, order2: int, mu: int) -> np.ndarray:
-    """Lorenzo residuals of q - mu with zero state before the tile start."""
+def residuals(q: np.ndarray, order2: int, mu: int, independent: bool = False) -> np.ndarray:
+    """Lorenzo residuals of q - mu with zero state before the tile start
+    (independent: before every block start)."""
     qc = np.asarray(q, dtype=np.int64) - mu
+    if independent:
+        return np.concatenate([residuals(qc[b:b + BLOCK], order2, 0)
+                               for b in range(0, qc.size, BLOCK)]).astype(np.int64)
     p1 = np.concatenate([[0], qc[:-1]])
     if not order2:
         return qc - p1
@@ -101,26 +105,37 @@ def residuals(q: np.ndarray, order2: int, mu: int) -> np.ndarray:
     return qc - 2 * p1 + p2
 
 
-def brute_force_tile(xt: np.ndarray, inv: float):
+# feature switches of the ablation (Sec. VI-B)
+CROSS_BLOCK, CENTERING, LZ2, ALL = 1, 2, 4, 7
+
+
+def allowed(v: int, features: int, centre_ok: bool) -> bool:
+    if (v & 1) and not features & LZ2:
+        return False
+    if (v >> 1) and (not features & CENTERING or not centre_ok):
+        return False
+    return True
+
+
+def brute_force_tile(xt: np.ndarray, inv: float, features: int = ALL):
     """Four separate full passes; returns (mu, centre_ok, costs[4], rates[4][8], best)."""
     m = xt.size
     nb = ceil_div(m, BLOCK)
     q = quantize(xt, inv)
     ok, mu = pairwise_mean(xt, inv)
+    indep = not features & CROSS_BLOCK
     costs, rates = [], []
     for v in range(4):
         order2, cen = v & 1, v >> 1
         res = np.zeros(TILE, dtype=np.int64)
-        res[:m] = residuals(q, order2, mu if cen else 0)
+        res[:m] = residuals(q, order2, mu if cen else 0, indep)
         rv = [bitlen(int(np.abs(res[b * BLOCK:(b + 1) * BLOCK]).max())) if b < nb else 0
               for b in range(8)]
         rates.append(rv)
         costs.append(sum(block_cost(r) for r in rv) + (4 if cen else 0))
     best = 0
     for v in (1, 2, 3):
-        if v >= 2 and not ok:
-            continue
-        if costs[v] < costs[best]:
+        if allowed(v, features, ok) and costs[v] < costs[best]:
             best = v
     return mu, ok, costs, rates, best
 
@@ -131,7 +146,8 @@ def _word_bytes(w: int) -> bytes:
 
 def encode_stream(x: np.ndarray, E: float, inv: float, mode: int, value: float, flags: int,
                   choices) -> bytes:
-    """Encode x with the given per-tile (order2, centred, mu) choices."""
+    """Encode x with the given per-tile (order2, centred, mu) choices
+    (flags bit 1: independent blocks)."""
     x = np.asarray(x, dtype=np.float32).reshape(-1)
     n = x.size
     q = quantize(x, inv)
@@ -143,7 +159,7 @@ def encode_stream(x: np.ndarray, E: float, inv: float, mode: int, value: float, 
         m = qt.size
         order2, cen, mu = choices[t]
         res = np.zeros(TILE, dtype=np.int64)
-        res[:m] = residuals(qt, order2, mu if cen else 0)
+        res[:m] = residuals(qt, order2, mu if cen else 0, bool(flags & 2))
         if cen:
             body += struct.pack("<i", mu)
         for b in range(ceil_div(m, BLOCK)):
