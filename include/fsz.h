@@ -133,6 +133,34 @@ fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out
                                 fsz_result *d_result, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Feature switches (the ablation of Sec. VI-B, Table IV): compression with a
+ * subset of the method's three prediction designs.  0 is the base the paper
+ * starts from (first-order Lorenzo on independent 32-element blocks, no
+ * centering); FSZ_FEATURES_ALL is the full method, i.e. what every other
+ * entry point does.
+ *   FSZ_FEAT_CROSS_BLOCK  prediction state carried across the 8 blocks of a
+ *                         tile (Sec. IV-A, Eq. (2)); off: every block starts
+ *                         from a zero state (Eq. (1)) and the stream header
+ *                         sets flags bit 1, which every decoder here honours
+ *   FSZ_FEAT_CENTERING    the tile-mean variants LZ1c / LZ2c (Sec. IV-B)
+ *   FSZ_FEAT_LZ2          the second-order variants LZ2 / LZ2c (Sec. IV-B)
+ * With independent blocks, centering subtracts the tile mean before every
+ * block's prediction.  The reconstruction x' = q E is the
+ * same under every setting; only the stream size differs.  Arguments,
+ * ownership and errors as fsz_compress_async, plus FSZ_ERR_INVALID_ARG for
+ * bits outside FSZ_FEATURES_ALL. */
+typedef enum {
+    FSZ_FEAT_CROSS_BLOCK = 1,
+    FSZ_FEAT_CENTERING = 2,
+    FSZ_FEAT_LZ2 = 4,
+    FSZ_FEATURES_ALL = 7
+} fsz_feature;
+
+fsz_status fsz_compress_features_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                                       const fsz_stats *d_stats, unsigned features, void *d_out,
+                                       size_t out_capacity, fsz_result *d_result, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: many fields of uneven sizes in one launch.
  *
  * Every job produces exactly the bytes (compress) or floats (decompress)

@@ -194,7 +194,7 @@ fsz_status finish(Workspace *ws, uint32_t epoch, size_t *size_out)
 // Enqueue (range pass if d_stats is NULL) + compression kernel.
 fsz_status enqueue_compress(Workspace *ws, const float *d_in, uint64_t n, int mode, double value,
                             const fsz_stats *d_stats, void *d_out, uint64_t cap, fsz_result *d_final,
-                            uint32_t *epoch_out)
+                            uint32_t *epoch_out, uint32_t features = kFeaturesAll)
 {
     if (!d_stats) {
         StatsArgs sa{d_in, n, ws->d_stats, ws->d_partials};
@@ -213,6 +213,7 @@ fsz_status enqueue_compress(Workspace *ws, const float *d_in, uint64_t n, int mo
     a.stats = d_stats;
     a.value = value;
     a.mode = mode;
+    a.features = features;
     // the pipelined kernel may use chunks as small as one wave's 8 tiles
     if (!ensure_flags(ws, std::max<uint64_t>(a.nchunks, ceil_div(a.ntiles, kTilesPerWave)))) return FSZ_ERR_DEVICE;
     if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
@@ -650,6 +651,20 @@ fsz_status fsz_compress_async(const float *d_in, size_t n, fsz_eb_mode mode, dou
     std::lock_guard<std::mutex> g(ws->mu);
     uint32_t epoch = 0;
     return enqueue_compress(ws, d_in, n, mode, value, d_stats, d_out, out_capacity, d_result, &epoch);
+}
+
+fsz_status fsz_compress_features_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                                       const fsz_stats *d_stats, unsigned features, void *d_out,
+                                       size_t out_capacity, fsz_result *d_result, void *stream)
+{
+    if (!d_result || (features & ~(unsigned)FSZ_FEATURES_ALL) != 0) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_compress_args(d_in, n, mode, value, d_out, out_capacity);
+    if (st != FSZ_OK) return st;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    uint32_t epoch = 0;
+    return enqueue_compress(ws, d_in, n, mode, value, d_stats, d_out, out_capacity, d_result, &epoch, features);
 }
 
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,

@@ -39,6 +39,9 @@ constexpr int kEpochShift = 44;
 constexpr int kErrorBit = 43;
 constexpr uint64_t kValueMask = (1ull << kErrorBit) - 1;
 
+// All prediction features on: cross-block state, centering, second order.
+constexpr uint32_t kFeaturesAll = FSZ_FEATURES_ALL;
+
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t pad16(uint64_t a) { return (a + 15) / 16 * 16; }
 
@@ -62,6 +65,7 @@ struct CompressArgs {
     const fsz_stats *stats;
     double value;
     int mode;
+    uint32_t features;    // FSZ_FEAT_* switches (kFeaturesAll = the full method)
     uint32_t epoch;       // 32-bit call epoch (result words)
     uint32_t flag_epoch;  // 18-bit nonzero epoch (chunk flags)
     unsigned long long *flags;

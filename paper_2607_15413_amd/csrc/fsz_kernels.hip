@@ -660,6 +660,7 @@ __device__ __forceinline__ void block_codes(int (&B)[32], int carry_b, int carry
 // Per-lane result of the rate pass of one chunk, kept until its encode.
 struct ChunkState {
     uint64_t chunk;
+    int first;  // the block restarts prediction (tile start; every block without cross-block state)
     int carry_b, carry_l1, mu;
     uint32_t vm, r, blk_off, tile_excl, wave_total;
     int order2, cent;
@@ -682,7 +683,10 @@ struct CompressShared {
 // On return x holds the biased quantized values.
 // DEFER: leave the rate byte in cs.rbyte for the caller to store, and publish
 // the aggregate from wave 1 (whose memory queue the lookback does not wait on).
-template <int W, bool DEFER = false>
+// FEAT: honour a.features (the ablation's switches, Sec. VI-B): without the
+// cross-block state every block restarts prediction and is re-rated per
+// variant like block 0; switched-off variants are never selected.
+template <int W, bool DEFER = false, bool FEAT = false>
 __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, const Resolved &R, uint64_t chunk,
                                                      int (&x)[32], int slot, CompressShared<W> &sh)
 {
@@ -723,19 +727,73 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
 #pragma unroll
     for (int i = 0; i < 32; i++) x[i] = __float_as_int(__int_as_float(x[i]) * R.inv + kQMagic);
 
-    // ---- cross-block state from block j-1 of the same tile
+    // ---- cross-block state from block j-1 of the same tile (none where the
+    // prediction restarts)
     const int t0 = dpp<kRowShr1>(x[31]);
     const int t1 = dpp<kRowShr1>(x[31] - x[30]);
-    cs.carry_b = j ? t0 : kQBias;
-    cs.carry_l1 = j ? t1 : 0;
+    const bool first = FEAT ? (j == 0 || !(a.features & FSZ_FEAT_CROSS_BLOCK)) : j == 0;
+    const int jr = first ? 0 : 1;  // 0: the leading residuals are re-rated per variant
+    cs.first = first;
+    cs.carry_b = first ? kQBias : t0;
+    cs.carry_l1 = first ? 0 : t1;
 
     uint32_t a1, a2;
     int l2_1;
     if (full)
-        block_extrema<true>(x, cs.carry_b, cs.carry_l1, j, cs.vm, a1, a2, l2_1);
+        block_extrema<true>(x, cs.carry_b, cs.carry_l1, jr, cs.vm, a1, a2, l2_1);
     else
-        block_extrema<false>(x, cs.carry_b, cs.carry_l1, j, cs.vm, a1, a2, l2_1);
+        block_extrema<false>(x, cs.carry_b, cs.carry_l1, jr, cs.vm, a1, a2, l2_1);
     const uint32_t r1 = bitlen(a1), r2 = bitlen(a2);
+    uint32_t Z;
+    if (FEAT) {
+        // every restarting block is rated per variant, the others have one
+        // rate per order; tile costs by 8-lane sums (same in all 8 lanes)
+        const int q0 = x[0] - kQBias;
+        const int d1 = cnt >= 2 ? l2_1 : 0;  // q1 - 2 q0
+        const int c0 = q0 - mu;
+        const int c1 = cnt >= 2 ? l2_1 + mu : 0;
+        uint32_t ra = r1, rb = r2, rc = r1, rd = r2;
+        if (first) {
+            ra = bitlen(max(uabs(q0), a1));
+            rb = bitlen(max(max(uabs(q0), uabs(d1)), a2));
+            rc = bitlen(max(uabs(c0), a1));
+            rd = bitlen(max(max(uabs(c0), uabs(c1)), a2));
+        }
+        if (cnt == 0) ra = rb = rc = rd = 0;  // blocks past the end of the field do not exist
+        const uint32_t Ca = (uint32_t)group_sum((int)block_bytes(ra));
+        const uint32_t Cb = (uint32_t)group_sum((int)block_bytes(rb));
+        const uint32_t Cc = (uint32_t)group_sum((int)block_bytes(rc)) + 4;
+        const uint32_t Cd = (uint32_t)group_sum((int)block_bytes(rd)) + 4;
+        const bool lz2 = (a.features & FSZ_FEAT_LZ2) != 0;
+        const bool cen = centre_ok && (a.features & FSZ_FEAT_CENTERING) != 0;
+        int best = 0;
+        uint32_t C = Ca, r = ra;
+        if (lz2 && Cb < C) {
+            best = 1;
+            C = Cb;
+            r = rb;
+        }
+        if (cen && Cc < C) {
+            best = 2;
+            C = Cc;
+            r = rc;
+        }
+        if (cen && lz2 && Cd < C) {
+            best = 3;
+            C = Cd;
+            r = rd;
+        }
+        if (!tile_ok) {
+            best = 0;
+            C = 0;
+            r = 0;
+        }
+        cs.order2 = best & 1;
+        cs.cent = best >> 1;
+        Z = C;
+        cs.r = r;
+        cs.rbyte = j == 0 ? (r | (uint32_t)cs.order2 << 7 | (uint32_t)cs.cent << 6) : r;
+    } else {
     const int T1 = group_sum(j ? (int)block_bytes(r1) : 0);
     const int T2 = group_sum(j ? (int)block_bytes(r2) : 0);
 
@@ -778,9 +836,10 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
     dec = group_head(dec);
     cs.order2 = (dec >> 7) & 1;
     cs.cent = (dec >> 6) & 1;
-    const uint32_t Z = (uint32_t)dec >> 8;
+    Z = (uint32_t)dec >> 8;
     cs.r = j == 0 ? (uint32_t)(dec & 31) : (cs.order2 ? r2 : r1);
     cs.rbyte = j == 0 ? (uint32_t)(dec & 0xFF) : cs.r;
+    }
     if (!DEFER && cnt > 0) a.out[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)cs.rbyte;
     const uint32_t S = block_bytes(cs.r);
 
@@ -811,7 +870,8 @@ __device__ __forceinline__ void finish_stream(const CompressArgs &a, const Resol
     if (status == FSZ_OK) {
         uint32_t *h = reinterpret_cast<uint32_t *>(a.out);
         h[0] = 0x315A5346u;  // "FSZ1"
-        h[1] = 1u | ((uint32_t)a.mode << 16) | (R.flags << 24);
+        const uint32_t hflags = R.flags | ((a.features & FSZ_FEAT_CROSS_BLOCK) ? 0u : 2u);  // bit 1: independent blocks
+        h[1] = 1u | ((uint32_t)a.mode << 16) | (hflags << 24);
         h[2] = (uint32_t)a.n;
         h[3] = (uint32_t)(a.n >> 32);
         h[4] = __float_as_uint(R.E);
@@ -826,7 +886,7 @@ __device__ __forceinline__ void finish_stream(const CompressArgs &a, const Resol
 // Steps 4-5 of one chunk whose rate pass is done: wait for the chunk's output
 // offset (decoupled lookback, Sec. IV-D), then the sign / bit-plane encoding
 // (Sec. IV-C) straight to the output.  B holds the biased quantized values.
-template <bool STAGED, int W>
+template <bool STAGED, int W, bool FEAT = false>
 __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Resolved &R, const ChunkState &cs,
                                                 int (&B)[32], int slot, CompressShared<W> &sh, uint32_t *st)
 {
@@ -862,11 +922,11 @@ __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Res
     const unsigned long long o2 = __ballot(cs.order2 != 0);
     const unsigned long long o1 = __ballot(cs.order2 == 0);
     if (o2 == 0)
-        block_codes<1>(B, cs.carry_b, cs.carry_l1, j, 0, cs.cent, cs.mu);
+        block_codes<1>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, 0, cs.cent, cs.mu);
     else if (o1 == 0)
-        block_codes<2>(B, cs.carry_b, cs.carry_l1, j, 1, cs.cent, cs.mu);
+        block_codes<2>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, 1, cs.cent, cs.mu);
     else
-        block_codes<0>(B, cs.carry_b, cs.carry_l1, j, cs.order2, cs.cent, cs.mu);
+        block_codes<0>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, cs.order2, cs.cent, cs.mu);
     // valid slots in stored bit order (element i at bit i ^ 7)
     const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(cs.vm));
     const uint32_t nwords = cs.r ? cs.r + 1 : 0;  // sign word + r planes
@@ -904,7 +964,7 @@ __device__ __forceinline__ uint64_t next_ticket(unsigned long long *ticket, uint
 
 // One chunk of a compression (Sec. III-A steps 1-5) by a workgroup of W
 // waves: bound resolution, coalesced load, rate pass, lookback, encode.
-template <bool ALIGNED, bool LOAD_STAGED, bool STORE_STAGED, int W>
+template <bool ALIGNED, bool LOAD_STAGED, bool STORE_STAGED, int W, bool FEAT = false>
 __device__ __forceinline__ void compress_chunk(const CompressArgs &a, uint64_t chunk, CompressShared<W> &sh,
                                                uint32_t *st)
 {
@@ -935,15 +995,15 @@ __device__ __forceinline__ void compress_chunk(const CompressArgs &a, uint64_t c
 #pragma unroll
         for (int i = 0; i < 32; i++) x[i] = __float_as_int(f[i]);
     }
-    const ChunkState cs = compress_rates<W>(a, R, chunk, x, 0, sh);
-    compress_encode<STORE_STAGED, W>(a, R, cs, x, 0, sh, st);
+    const ChunkState cs = compress_rates<W, false, FEAT>(a, R, chunk, x, 0, sh);
+    compress_encode<STORE_STAGED, W, FEAT>(a, R, cs, x, 0, sh, st);
 }
 
 // Compression kernel: one chunk per workgroup, chunk ids from the ticket
 // counter, so the lookback only waits on chunks that are already running.
 // The kernel is kept small in registers so that many chunks are in flight per
 // CU: chunks waiting in the lookback leave the CU to the others.
-template <bool ALIGNED, bool LOAD_STAGED, bool STORE_STAGED>
+template <bool ALIGNED, bool LOAD_STAGED, bool STORE_STAGED, bool FEAT = false>
 __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
 {
     __shared__ CompressShared<kWaves> sh;
@@ -954,7 +1014,7 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
     int tslot = 0;
     const uint64_t chunk = next_ticket(a.ticket, a.nchunks, sh, tslot);
     if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
-    compress_chunk<ALIGNED, LOAD_STAGED, STORE_STAGED, kWaves>(a, chunk, sh, st);
+    compress_chunk<ALIGNED, LOAD_STAGED, STORE_STAGED, kWaves, FEAT>(a, chunk, sh, st);
 }
 
 // ------------------------------------------------------------------ pipelined compress
@@ -1079,6 +1139,7 @@ __device__ __forceinline__ uint64_t pipe2_lookback(const CompressArgs &a, const 
 
 // Residual codes and bit planes of one wave's blocks into its staging area
 // (offsets relative to the wave's first byte).
+template <bool FEAT>
 __device__ __forceinline__ void pipe2_stage(const ChunkState &cs, int (&B)[32], uint32_t *st)
 {
     const int j = __lane_id() & 7;
@@ -1086,11 +1147,11 @@ __device__ __forceinline__ void pipe2_stage(const ChunkState &cs, int (&B)[32], 
     const unsigned long long o2 = __ballot(cs.order2 != 0);
     const unsigned long long o1 = __ballot(cs.order2 == 0);
     if (o2 == 0)
-        block_codes<1>(B, cs.carry_b, cs.carry_l1, j, 0, cs.cent, cs.mu);
+        block_codes<1>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, 0, cs.cent, cs.mu);
     else if (o1 == 0)
-        block_codes<2>(B, cs.carry_b, cs.carry_l1, j, 1, cs.cent, cs.mu);
+        block_codes<2>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, 1, cs.cent, cs.mu);
     else
-        block_codes<0>(B, cs.carry_b, cs.carry_l1, j, cs.order2, cs.cent, cs.mu);
+        block_codes<0>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, cs.order2, cs.cent, cs.mu);
     const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(cs.vm));
     const uint32_t nwords = cs.r ? cs.r + 1 : 0;
     uint32_t *words = st + (cs.blk_off >> 2);
@@ -1113,7 +1174,7 @@ __device__ __forceinline__ void pipe2_stage(const ChunkState &cs, int (&B)[32], 
 // taken in this step, store A.  Returns that ticket (nchunks if none).
 // W0: the calling wave is wave 0, which takes the ticket and reads the
 // lookback window at the start and uses both after the rate pass.
-template <bool W0, int W>
+template <bool W0, int W, bool FEAT>
 __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Resolved &R, uint64_t takes,
                                                const ChunkState &ca, int (&xa)[32], int sa, uint64_t B,
                                                int (&yb)[32], ChunkState &cb, uint64_t C, uint32_t *qb,
@@ -1127,7 +1188,7 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
         if (take && lane == 0) traw = atomicAdd(a.ticket, 1ull);
         probe = lookback_probe(a.flags, ca.chunk, a.flag_epoch);
     }
-    if (B < a.nchunks) cb = compress_rates<W, true>(a, R, B, yb, sa ^ 1, sh);
+    if (B < a.nchunks) cb = compress_rates<W, true, FEAT>(a, R, B, yb, sa ^ 1, sh);
     uint64_t D;
     const uint64_t base = pipe2_lookback<W0, W>(a, R, ca, sa, sh, probe, take, traw, takes, &D);
 
@@ -1139,7 +1200,7 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
     }
     const uint64_t tile0 = ca.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     const bool ok = a.data0 + base + chunk_total <= a.capacity && tile0 < a.ntiles;
-    if (ok) pipe2_stage(ca, xa, pb);
+    if (ok) pipe2_stage<FEAT>(ca, xa, pb);
     if (C < a.nchunks) chunk_read(qb, lane, xa);
     if (D < a.nchunks) {
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the read of qb is done before it is overwritten
@@ -1159,7 +1220,7 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
 }
 
 // The whole pipeline of one wave (W0: wave 0's role), from the first ticket on.
-template <bool W0, int W>
+template <bool W0, int W, bool FEAT>
 __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved &R, CompressShared<W> &sh,
                                           uint32_t *qb, uint32_t *pb, int w)
 {
@@ -1177,7 +1238,7 @@ __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved 
         __builtin_amdgcn_s_waitcnt(0xC07F);
         chunk_fetch<W>(a, B, qb, w, lane);
     }
-    ChunkState ca = compress_rates<W, true>(a, R, A, x, 0, sh);
+    ChunkState ca = compress_rates<W, true, FEAT>(a, R, A, x, 0, sh);
     ChunkState cb = ca;
     uint64_t C = N;
     if (B < N) {
@@ -1190,9 +1251,9 @@ __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved 
     }
     // loop invariant: A rate-passed in x (slot 0), B read into y, C in flight
     for (;;) {
-        const uint64_t D = pipe2_step<W0, W>(a, R, takes, ca, x, 0, B, y, cb, C, qb, pb, sh, w);
+        const uint64_t D = pipe2_step<W0, W, FEAT>(a, R, takes, ca, x, 0, B, y, cb, C, qb, pb, sh, w);
         if (B >= N) return;
-        const uint64_t E = pipe2_step<W0, W>(a, R, takes, cb, y, 1, C, x, ca, D, qb, pb, sh, w);
+        const uint64_t E = pipe2_step<W0, W, FEAT>(a, R, takes, cb, y, 1, C, x, ca, D, qb, pb, sh, w);
         if (C >= N) return;
         B = D;
         C = E;
@@ -1200,8 +1261,8 @@ __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved 
 }
 
 // W waves per workgroup; a chunk is 8 tiles per wave.  a.nchunks must count
-// chunks of that size.
-template <int W>
+// chunks of that size.  FEAT: honour the feature switches in a.features.
+template <int W, bool FEAT = false>
 __global__ __launch_bounds__(W * 64) void compress_pipe2_kernel(CompressArgs a)
 {
     __shared__ CompressShared<W> sh;
@@ -1222,9 +1283,9 @@ __global__ __launch_bounds__(W * 64) void compress_pipe2_kernel(CompressArgs a)
         }
     }
     if (w == 0)
-        pipe2_run<true, W>(a, R, sh, qb, pb, w);
+        pipe2_run<true, W, FEAT>(a, R, sh, qb, pb, w);
     else if (W > 1)
-        pipe2_run<false, W>(a, R, sh, qb, pb, w);
+        pipe2_run<false, W, FEAT>(a, R, sh, qb, pb, w);
 }
 
 // ------------------------------------------------------------------ decompress
@@ -1293,7 +1354,7 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
 // tile mean), x' = (float)q * E.
 template <bool ALIGNED, bool STAGED, int W>
 __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChunk &d, int slot, float E,
-                                           uint64_t total, uint32_t *st, DecompressShared<W> &sh)
+                                           uint64_t total, bool indep, uint32_t *st, DecompressShared<W> &sh)
 {
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -1358,7 +1419,9 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
         acc += ((code[i] >> 1) ^ ns) - ns;
         code[i] = acc;  // first running sum (LZ1 reconstruction / LZ2 first differences)
     }
-    const uint32_t start1 = group_excl_scan(acc, j);
+    // carries from the blocks before in the tile (none when every block
+    // restarts prediction)
+    const uint32_t start1 = indep ? 0u : group_excl_scan(acc, j);
     uint32_t acc2 = 0;
     if (__ballot(d.order2) != 0) {
 #pragma unroll
@@ -1366,7 +1429,7 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
             acc2 += code[i] + start1;
         }
     }
-    const uint32_t start2 = group_excl_scan(acc2, j);
+    const uint32_t start2 = indep ? 0u : group_excl_scan(acc2, j);
     float xo[32];
     {
         const uint32_t om = (uint32_t)-d.order2;
@@ -1431,14 +1494,16 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
 
 // Stream header validation (identical in every workgroup): status, step E
 // and the stream's total size.
-__device__ __forceinline__ int dec_header(const DecompressArgs &a, float &E, uint64_t &total)
+__device__ __forceinline__ int dec_header(const DecompressArgs &a, float &E, uint64_t &total, bool &indep)
 {
     const uint32_t *h = reinterpret_cast<const uint32_t *>(a.cmp);
     E = 1.0f;
     total = 0;
     const uint32_t h1 = h[1];
-    if (h[0] != 0x315A5346u || (h1 & 0xFFFFu) != 1u || ((h1 >> 16) & 0xFFu) > 1u || ((h1 >> 24) & ~1u) != 0u)
+    indep = false;
+    if (h[0] != 0x315A5346u || (h1 & 0xFFFFu) != 1u || ((h1 >> 16) & 0xFFu) > 1u || ((h1 >> 24) & ~3u) != 0u)
         return FSZ_ERR_CORRUPT;
+    indep = ((h1 >> 25) & 1u) != 0;  // flags bit 1: prediction restarts at every block
     if (((uint64_t)h[3] << 32 | h[2]) != a.n) return FSZ_ERR_SIZE_MISMATCH;
     E = __uint_as_float(h[4]);
     total = (uint64_t)h[7] << 32 | h[6];
@@ -1460,7 +1525,8 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
 
     float E;
     uint64_t total;
-    const int hst = dec_header(a, E, total);
+    bool indep;
+    const int hst = dec_header(a, E, total, indep);
     if (hst != FSZ_OK) {
         if (tid == 0 && blockIdx.x == 0) write_final(a.final, 0, hst, a.epoch);
         return;
@@ -1476,7 +1542,7 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
         const uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
         DecChunk dn;
         if (nxt < a.nchunks) dn = dec_sizes<W>(a, nxt, slot ^ 1, sh);
-        dec_decode<ALIGNED, STAGED, W>(a, dc, slot, E, total, st, sh);
+        dec_decode<ALIGNED, STAGED, W>(a, dc, slot, E, total, indep, st, sh);
         if (nxt >= a.nchunks) break;
         dc = dn;
         slot ^= 1;
@@ -1579,6 +1645,7 @@ __global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
         a.stats = b.stats + job;
         a.value = J.value;
         a.mode = J.mode;
+        a.features = kFeaturesAll;
         a.epoch = b.epoch;
         a.flag_epoch = 1;
         a.flags = b.flags + J.chunk_base;
@@ -1602,13 +1669,14 @@ __global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
         a.final = J.final;
         float E;
         uint64_t total;
-        const int hst = dec_header(a, E, total);
+        bool indep;
+        const int hst = dec_header(a, E, total, indep);
         if (hst != FSZ_OK) {
             if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, hst, a.epoch);
             return;
         }
         const DecChunk dc = dec_sizes<W>(a, chunk, 0, sh.d);
-        dec_decode<ALIGNED, true, W>(a, dc, 0, E, total, st, sh.d);
+        dec_decode<ALIGNED, true, W>(a, dc, 0, E, total, indep, st, sh.d);
     }
 }
 
@@ -1674,6 +1742,19 @@ static hipError_t launch_decompress_t(const DecompressArgs &a, hipStream_t s)
 
 hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s)
 {
+    if (a.features != kFeaturesAll) {  // the ablation's feature subsets: 8-wave pipeline or the plain kernel
+        if (in_aligned16) {
+            CompressArgs p = a;
+            p.nchunks = p.ntiles ? ceil_div(p.ntiles, (uint64_t)kTilesPerWave * 8) : 1;
+            static const unsigned cap = persistent_grid(compress_pipe2_kernel<8, true>, ~0ull, 512);
+            hipLaunchKernelGGL((compress_pipe2_kernel<8, true>), dim3((unsigned)(p.nchunks < cap ? p.nchunks : cap)),
+                               dim3(512), 0, s, p);
+        } else {
+            hipLaunchKernelGGL((compress_kernel<false, true, true, true>), dim3((unsigned)a.nchunks), dim3(kThreads), 0,
+                               s, a);
+        }
+        return hipGetLastError();
+    }
     if (in_aligned16 && tuning().pipe_compress) {
         // the arguments count chunks of kTilesPerChunk tiles; the pipeline's
         // chunks are 8 tiles per wave

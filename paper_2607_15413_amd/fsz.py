@@ -41,6 +41,7 @@ EXPORTS = (
     "fsz_decompress",
     "fsz_compress_async",
     "fsz_decompress_async",
+    "fsz_compress_features_async",
     "fsz_batch_async",
     "fsz_autotune",
     "fsz_plan_create",
@@ -55,6 +56,12 @@ EXPORTS = (
     "fsz_server_get_stats",
     "fsz_server_destroy",
 )
+
+# feature switches (fsz_compress_features_async)
+FSZ_FEAT_CROSS_BLOCK = 1
+FSZ_FEAT_CENTERING = 2
+FSZ_FEAT_LZ2 = 4
+FSZ_FEATURES_ALL = 7
 
 FSZ_OP_COMPRESS = 0
 FSZ_OP_DECOMPRESS = 1
@@ -137,6 +144,9 @@ def load_library():
     lib.fsz_decompress.restype = ctypes.c_int
     lib.fsz_compress_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, vp, sz, vp, vp]
     lib.fsz_compress_async.restype = ctypes.c_int
+    lib.fsz_compress_features_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, ctypes.c_uint, vp, sz,
+                                                vp, vp]
+    lib.fsz_compress_features_async.restype = ctypes.c_int
     lib.fsz_decompress_async.argtypes = [vp, sz, vp, sz, vp, vp]
     lib.fsz_decompress_async.restype = ctypes.c_int
     jp, tp = ctypes.POINTER(FszJob), ctypes.POINTER(FszTuning)
@@ -212,6 +222,13 @@ def fsz_compress_async(d_in: int, n: int, mode: int, value: float, d_stats, d_ou
     """Enqueue only; the outcome lands in the device fsz_result at d_result."""
     return load_library().fsz_compress_async(d_in, n, mode, value, d_stats, d_out, out_capacity,
                                              d_result, stream)
+
+
+def fsz_compress_features_async(d_in: int, n: int, mode: int, value: float, d_stats, features: int,
+                                d_out: int, out_capacity: int, d_result: int, stream=None) -> int:
+    """Compression with a subset of the prediction features (enqueue only)."""
+    return load_library().fsz_compress_features_async(d_in, n, mode, value, d_stats, features, d_out,
+                                                      out_capacity, d_result, stream)
 
 
 def fsz_decompress_async(d_cmp: int, cmp_size: int, d_out: int, n: int, d_result: int,
@@ -370,6 +387,27 @@ def compress(x, mode: int, value: float, out=None, check: bool = True):
                             _stream_handle(torch, x.device))
     if check and st != FSZ_OK:
         raise FszError(st, "fsz_compress")
+    return (out[:size] if st == FSZ_OK else out), st
+
+
+def compress_features(x, mode: int, value: float, features: int, out=None, check: bool = True):
+    """Compress a contiguous float32 CUDA tensor with a feature subset; returns
+    (uint8 tensor view, status).  Synchronizes the stream to read the size."""
+    import torch
+    assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+    n = x.numel()
+    if out is None:
+        out = torch.empty(fsz_compressed_bound(n), dtype=torch.uint8, device=x.device)
+    res = torch.zeros(2, dtype=torch.int64, device=x.device)  # fsz_result {u64 size; u32 status, epoch}
+    stream = _stream_handle(torch, x.device)
+    st = fsz_compress_features_async(x.data_ptr(), n, mode, value, None, features, out.data_ptr(),
+                                     out.numel(), res.data_ptr(), stream)
+    if st == FSZ_OK:
+        torch.cuda.current_stream(x.device).synchronize()
+        r = res.cpu()
+        size, st = int(r[0]), int(r[1]) & 0xFFFFFFFF
+    if check and st != FSZ_OK:
+        raise FszError(st, "fsz_compress_features_async")
     return (out[:size] if st == FSZ_OK else out), st
 
 
