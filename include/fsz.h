@@ -160,6 +160,19 @@ fsz_status fsz_compress_features_async(const float *d_in, size_t n, fsz_eb_mode 
                                        const fsz_stats *d_stats, unsigned features, void *d_out,
                                        size_t out_capacity, fsz_result *d_result, void *stream);
 
+/* The naive five-read baseline the paper measures its single-pass evaluation
+ * against (Sec. V-C, Fig. 6): four evaluation passes, one per variant (LZ1,
+ * LZ2, LZ1c, LZ2c), each reading the whole input and writing per-tile costs
+ * and block rates to library-owned device tables (53 bytes per 256-element
+ * tile, grown on demand), then an encode pass that reads the input a fifth
+ * time, selects from the tables and encodes.  The stream is byte-identical
+ * to fsz_compress_async's; it exists to measure what the single pass saves.
+ * Five kernel launches (six with the range pass when d_stats is NULL).
+ * Arguments, ownership and errors as fsz_compress_async. */
+fsz_status fsz_compress_five_read_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                                        const fsz_stats *d_stats, void *d_out, size_t out_capacity,
+                                        fsz_result *d_result, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: many fields of uneven sizes in one launch.
  *

@@ -107,6 +107,9 @@ struct Workspace {
     fsz_stats *b_stats = nullptr;
     uint64_t b_stats_cap = 0;
     unsigned long long *b_ticket = nullptr;
+    // five-read baseline: evaluation tables (53 bytes per tile)
+    uint8_t *d_naive = nullptr;
+    uint64_t naive_cap = 0;
 };
 
 std::mutex g_mu;
@@ -222,6 +225,49 @@ fsz_status enqueue_compress(Workspace *ws, const float *d_in, uint64_t n, int mo
     a.final = d_final;
     if (!ok(launch_compress(a, aligned(d_in, 16), tuning().staged_compress, ws->stream))) return FSZ_ERR_DEVICE;
     *epoch_out = a.epoch;
+    return FSZ_OK;
+}
+
+template <typename T>
+bool grow(T **p, uint64_t *cap, uint64_t want, hipStream_t s);
+
+// The five-read baseline (Sec. V-C, Fig. 6): the same stream as
+// enqueue_compress, from four evaluation passes and one encode pass.
+fsz_status enqueue_compress_naive(Workspace *ws, const float *d_in, uint64_t n, int mode, double value,
+                                  const fsz_stats *d_stats, void *d_out, uint64_t cap, fsz_result *d_final)
+{
+    if (!d_stats) {
+        StatsArgs sa{d_in, n, ws->d_stats, ws->d_partials};
+        if (!ok(launch_stats(sa, ws->stream))) return FSZ_ERR_DEVICE;
+        d_stats = ws->d_stats;
+    }
+    CompressArgs a{};
+    a.x = d_in;
+    a.n = n;
+    a.ntiles = ceil_div(n, kTile);
+    a.nblocks = ceil_div(n, kBlock);
+    a.nchunks = a.ntiles ? ceil_div(a.ntiles, kTilesPerChunk) : 1;
+    a.data0 = kHeaderBytes + pad16(a.nblocks);
+    a.out = static_cast<uint8_t *>(d_out);
+    a.capacity = cap;
+    a.stats = d_stats;
+    a.value = value;
+    a.mode = mode;
+    a.features = kFeaturesAll;
+    const uint64_t nt = std::max<uint64_t>(a.ntiles, 1);
+    const uint64_t off_rates = 16 * nt, off_mu = off_rates + 32 * nt, off_ok = off_mu + 4 * nt;
+    if (!grow(&ws->d_naive, &ws->naive_cap, off_ok + nt, ws->stream)) return FSZ_ERR_DEVICE;
+    NaiveTables t;
+    t.cost = reinterpret_cast<uint32_t *>(ws->d_naive);
+    t.rates = ws->d_naive + off_rates;
+    t.mu = reinterpret_cast<int32_t *>(ws->d_naive + off_mu);
+    t.centre_ok = ws->d_naive + off_ok;
+    if (!ensure_flags(ws, a.nchunks)) return FSZ_ERR_DEVICE;
+    if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
+    a.flags = ws->d_flags;
+    a.ticket = ws->d_ticket;
+    a.final = d_final;
+    if (!ok(launch_compress_naive(a, t, aligned(d_in, 16), ws->stream))) return FSZ_ERR_DEVICE;
     return FSZ_OK;
 }
 
@@ -665,6 +711,19 @@ fsz_status fsz_compress_features_async(const float *d_in, size_t n, fsz_eb_mode 
     std::lock_guard<std::mutex> g(ws->mu);
     uint32_t epoch = 0;
     return enqueue_compress(ws, d_in, n, mode, value, d_stats, d_out, out_capacity, d_result, &epoch, features);
+}
+
+fsz_status fsz_compress_five_read_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                                        const fsz_stats *d_stats, void *d_out, size_t out_capacity,
+                                        fsz_result *d_result, void *stream)
+{
+    if (!d_result) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_compress_args(d_in, n, mode, value, d_out, out_capacity);
+    if (st != FSZ_OK) return st;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    return enqueue_compress_naive(ws, d_in, n, mode, value, d_stats, d_out, out_capacity, d_result);
 }
 
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,

@@ -84,6 +84,16 @@ struct DecompressArgs {
     fsz_result *final;           // written by the workgroup owning the last chunk
 };
 
+// ---- naive five-read baseline (Sec. V-C, Fig. 6): per-tile evaluation tables
+// written by four evaluation passes (one per variant) and read by the encode
+// pass.  Laid out [variant][tile] (cost), [variant][tile][block] (rates).
+struct NaiveTables {
+    uint32_t *cost;      // 4 * ntiles: tile cost C of LZ1, LZ2, LZ1c, LZ2c
+    uint8_t *rates;      // 4 * ntiles * 8: block rates of each variant
+    int32_t *mu;         // ntiles: quantized tile mean (written by the centred passes)
+    uint8_t *centre_ok;  // ntiles: the mean is finite
+};
+
 // ---- batched form: one launch over many jobs (compress or decompress)
 
 constexpr int kSegElems = 32768;  // elements per workgroup of the batched range pass
@@ -132,6 +142,9 @@ hipError_t launch_stats(const StatsArgs &a, hipStream_t s);
 // staged = write outputs through an LDS staging buffer with coalesced stores
 // instead of lane-per-block stores.
 hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged, hipStream_t s);
+// The five-read baseline: four evaluation launches, then the encode launch
+// (a.nchunks counts chunks of kTilesPerChunk tiles).
+hipError_t launch_compress_naive(const CompressArgs &a, const NaiveTables &t, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s);
 // Range pass + flag clear, per-job stats, then the batched kernel.
 hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, const BatchShape &shape,

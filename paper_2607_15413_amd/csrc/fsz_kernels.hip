@@ -1017,6 +1017,200 @@ __global__ __launch_bounds__(kThreads) void compress_kernel(CompressArgs a)
     compress_chunk<ALIGNED, LOAD_STAGED, STORE_STAGED, kWaves, FEAT>(a, chunk, sh, st);
 }
 
+// ------------------------------------------------------------------ naive five-read baseline
+
+// The comparison point of Sec. V-C (Fig. 6): the four variants evaluated in
+// four separate passes over the input, each writing per-tile costs and block
+// rates, then an encode pass that reads the input a fifth time.  It produces
+// the same stream as the single-pass kernels; only the reads differ.
+
+// Evaluation pass of variant v (bit 0: second order, bit 1: centred) over a
+// chunk of kTilesPerChunk tiles per workgroup.
+template <bool ALIGNED>
+__global__ __launch_bounds__(kThreads) void naive_eval_kernel(CompressArgs a, NaiveTables t, int v)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t stage[kWaves * kStageWaveDwords];
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int j = lane & 7;
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status != FSZ_OK) return;  // the encode pass reports the status
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    if (tile0 >= a.ntiles) return;  // wave-uniform; the kernel has no workgroup barrier
+    float f[32];
+    load_blocks_staged<ALIGNED>(a.x, a.n, tile0 * kTile, stage + w * kStageWaveDwords, lane, f);
+    const uint64_t tile = tile0 + (lane >> 3);
+    const bool tile_ok = tile < a.ntiles;
+    const uint64_t eblk = tile * kTile + (uint64_t)j * kBlock;
+    const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
+    const uint32_t vm = cnt >= 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u);
+    const bool full = (tile0 + kTilesPerWave) * kTile <= a.n;
+    const int order2 = v & 1, cen = v >> 1;
+
+    int mu = 0;
+    bool centre_ok = true;
+    if (cen) {  // tile mean, as in the single pass
+        float s16[16];
+#pragma unroll
+        for (int i = 0; i < 16; i++) s16[i] = f[2 * i] + f[2 * i + 1];
+#pragma unroll
+        for (int i = 0; i < 8; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+#pragma unroll
+        for (int i = 0; i < 4; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+#pragma unroll
+        for (int i = 0; i < 2; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+        float ts = s16[0] + s16[1];
+        ts = ts + dppf<kQuadXor1>(ts);
+        ts = ts + dppf<kQuadXor2>(ts);
+        ts = ts + dppf<kRowHalfMirror>(ts);
+        const float mean_q = (ts * 0x1p-8f) * R.inv;
+        centre_ok = __builtin_isfinite(mean_q);
+        mu = centre_ok ? (int)__builtin_rintf(mean_q) : 0;
+    }
+    int x[32];
+#pragma unroll
+    for (int i = 0; i < 32; i++) x[i] = __float_as_int(f[i] * R.inv + kQMagic);
+    const int t0 = dpp<kRowShr1>(x[31]);
+    const int t1 = dpp<kRowShr1>(x[31] - x[30]);
+    const int carry_b = j ? t0 : kQBias;
+    const int carry_l1 = j ? t1 : 0;
+    uint32_t a1, a2;
+    int l2_1;
+    if (full)
+        block_extrema<true>(x, carry_b, carry_l1, j, vm, a1, a2, l2_1);
+    else
+        block_extrema<false>(x, carry_b, carry_l1, j, vm, a1, a2, l2_1);
+    uint32_t r = bitlen(order2 ? a2 : a1);
+    if (j == 0) {  // block 0: the variant's own first residuals
+        const int q0 = x[0] - kQBias;
+        const int f0 = cen ? q0 - mu : q0;
+        const int d1 = cnt >= 2 ? l2_1 : 0;
+        const int f1 = cnt >= 2 ? (cen ? l2_1 + mu : d1) : 0;
+        r = order2 ? bitlen(max(max(uabs(f0), uabs(f1)), a2)) : bitlen(max(uabs(f0), a1));
+    }
+    const uint32_t C = (uint32_t)group_sum((int)block_bytes(r)) + (cen ? 4u : 0u);
+    if (tile_ok) {
+        t.rates[((uint64_t)v * a.ntiles + tile) * kBlocksPerTile + j] = (uint8_t)r;
+        if (j == 0) {
+            t.cost[(uint64_t)v * a.ntiles + tile] = C;
+            if (cen) {
+                t.mu[tile] = mu;
+                t.centre_ok[tile] = centre_ok ? 1 : 0;
+            }
+        }
+    }
+}
+
+// Selection and bookkeeping of the encode pass: the rate pass of the single
+// pass with the evaluation replaced by reads of the tables (same choice,
+// same tie order).  On return x holds the biased quantized values.
+__device__ __forceinline__ ChunkState naive_select(const CompressArgs &a, const Resolved &R, const NaiveTables &t,
+                                                   uint64_t chunk, int (&x)[32], CompressShared<kWaves> &sh)
+{
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int j = lane & 7;
+    const uint64_t tile0 = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    const uint64_t tile = tile0 + (lane >> 3);
+    const bool tile_ok = tile < a.ntiles;
+    const uint64_t eblk = tile * kTile + (uint64_t)j * kBlock;
+    const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
+    ChunkState cs;
+    cs.chunk = chunk;
+    cs.vm = cnt >= 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u);
+#pragma unroll
+    for (int i = 0; i < 32; i++) x[i] = __float_as_int(__int_as_float(x[i]) * R.inv + kQMagic);
+    const int t0 = dpp<kRowShr1>(x[31]);
+    const int t1 = dpp<kRowShr1>(x[31] - x[30]);
+    cs.first = j == 0;
+    cs.carry_b = j ? t0 : kQBias;
+    cs.carry_l1 = j ? t1 : 0;
+
+    int best = 0;
+    uint32_t Z = 0, r = 0;
+    cs.mu = 0;
+    if (tile_ok) {
+        const uint32_t Ca = t.cost[tile], Cb = t.cost[a.ntiles + tile];
+        const uint32_t Cc = t.cost[2 * a.ntiles + tile], Cd = t.cost[3 * a.ntiles + tile];
+        const bool centre_ok = t.centre_ok[tile] != 0;
+        uint32_t C = Ca;
+        if (Cb < C) {
+            best = 1;
+            C = Cb;
+        }
+        if (centre_ok) {
+            if (Cc < C) {
+                best = 2;
+                C = Cc;
+            }
+            if (Cd < C) {
+                best = 3;
+                C = Cd;
+            }
+        }
+        Z = C;
+        r = t.rates[((uint64_t)best * a.ntiles + tile) * kBlocksPerTile + j];
+        if (best >> 1) cs.mu = t.mu[tile];
+    }
+    cs.order2 = best & 1;
+    cs.cent = best >> 1;
+    cs.r = r;
+    cs.rbyte = j == 0 ? (r | (uint32_t)cs.order2 << 7 | (uint32_t)cs.cent << 6) : r;
+    if (cnt > 0) a.out[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)cs.rbyte;
+    const uint32_t S = block_bytes(cs.r);
+    const int incl = wave_incl_scan(j == 0 ? (int)Z : 0);
+    cs.tile_excl = (uint32_t)incl - Z;
+    cs.wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
+    cs.blk_off = cs.tile_excl + group_excl_scan(S, j) + 4u * cs.cent;
+    if (lane == 0) sh.wave_total[0][w] = cs.wave_total;
+    lds_barrier();
+    if (tid == 0) {
+        uint32_t chunk_total = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; k++) chunk_total += sh.wave_total[0][k];
+        publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, false);
+    }
+    return cs;
+}
+
+// Encode pass: one chunk per workgroup from the ticket counter (the fifth
+// read of the input), the tables' choice, lookback, the single pass's encoder.
+template <bool ALIGNED>
+__global__ __launch_bounds__(kThreads) void naive_encode_kernel(CompressArgs a, NaiveTables t)
+{
+    __shared__ CompressShared<kWaves> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t stage[kWaves * kStageWaveDwords];
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    uint32_t *st = stage + w * kStageWaveDwords;
+    int tslot = 0;
+    const uint64_t chunk = next_ticket(a.ticket, a.nchunks, sh, tslot);
+    if (chunk >= a.nchunks) return;
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status != FSZ_OK) {
+        if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
+        return;
+    }
+    const uint64_t tile0 = chunk * kTilesPerChunk + (uint64_t)w * kTilesPerWave;
+    int x[32];
+    {
+        float f[32];
+        if (tile0 < a.ntiles) {
+            load_blocks_staged<ALIGNED>(a.x, a.n, tile0 * kTile, st, lane, f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; i++) f[i] = 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 32; i++) x[i] = __float_as_int(f[i]);
+    }
+    const ChunkState cs = naive_select(a, R, t, chunk, x, sh);
+    compress_encode<true, kWaves>(a, R, cs, x, 0, sh, st);
+}
+
 // ------------------------------------------------------------------ pipelined compress
 //
 // Persistent form of the compression kernel for 16-byte aligned inputs: each
@@ -1796,6 +1990,22 @@ hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged
     }
     if (ls) return staged ? launch_compress_t<false, true, true>(a, s) : launch_compress_t<false, true, false>(a, s);
     return staged ? launch_compress_t<false, false, true>(a, s) : launch_compress_t<false, false, false>(a, s);
+}
+
+hipError_t launch_compress_naive(const CompressArgs &a, const NaiveTables &t, bool in_aligned16, hipStream_t s)
+{
+    const unsigned grid = (unsigned)a.nchunks;
+    for (int v = 0; v < 4; v++) {
+        if (in_aligned16)
+            hipLaunchKernelGGL(naive_eval_kernel<true>, dim3(grid), dim3(kThreads), 0, s, a, t, v);
+        else
+            hipLaunchKernelGGL(naive_eval_kernel<false>, dim3(grid), dim3(kThreads), 0, s, a, t, v);
+    }
+    if (in_aligned16)
+        hipLaunchKernelGGL(naive_encode_kernel<true>, dim3(grid), dim3(kThreads), 0, s, a, t);
+    else
+        hipLaunchKernelGGL(naive_encode_kernel<false>, dim3(grid), dim3(kThreads), 0, s, a, t);
+    return hipGetLastError();
 }
 
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s)

@@ -42,6 +42,7 @@ EXPORTS = (
     "fsz_compress_async",
     "fsz_decompress_async",
     "fsz_compress_features_async",
+    "fsz_compress_five_read_async",
     "fsz_batch_async",
     "fsz_autotune",
     "fsz_plan_create",
@@ -147,6 +148,8 @@ def load_library():
     lib.fsz_compress_features_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, ctypes.c_uint, vp, sz,
                                                 vp, vp]
     lib.fsz_compress_features_async.restype = ctypes.c_int
+    lib.fsz_compress_five_read_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, vp, sz, vp, vp]
+    lib.fsz_compress_five_read_async.restype = ctypes.c_int
     lib.fsz_decompress_async.argtypes = [vp, sz, vp, sz, vp, vp]
     lib.fsz_decompress_async.restype = ctypes.c_int
     jp, tp = ctypes.POINTER(FszJob), ctypes.POINTER(FszTuning)
@@ -229,6 +232,13 @@ def fsz_compress_features_async(d_in: int, n: int, mode: int, value: float, d_st
     """Compression with a subset of the prediction features (enqueue only)."""
     return load_library().fsz_compress_features_async(d_in, n, mode, value, d_stats, features, d_out,
                                                       out_capacity, d_result, stream)
+
+
+def fsz_compress_five_read_async(d_in: int, n: int, mode: int, value: float, d_stats, d_out: int,
+                                 out_capacity: int, d_result: int, stream=None) -> int:
+    """The five-read baseline (enqueue only); same stream as fsz_compress_async."""
+    return load_library().fsz_compress_five_read_async(d_in, n, mode, value, d_stats, d_out, out_capacity,
+                                                       d_result, stream)
 
 
 def fsz_decompress_async(d_cmp: int, cmp_size: int, d_out: int, n: int, d_result: int,

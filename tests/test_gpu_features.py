@@ -1,4 +1,5 @@
-"""GPU parity of the feature switches (the ablation of Sec. VI-B): for every
+"""GPU parity of the feature switches (the ablation of Sec. VI-B) and of the
+five-read baseline (Sec. V-C, Fig. 6).  For every
 subset of {cross-block state, centering, LZ2} the HIP streams equal the
 oracle's byte for byte, through the aligned (pipelined) and the unaligned
 (one chunk per workgroup) kernels, and every decoder path reconstructs them
@@ -96,3 +97,47 @@ def test_ablation_sizes_on_a_grf_slice():
         assert got == exp, first_diff(got, exp)
         sizes[features] = len(got)
     assert sizes[7] <= sizes[3] <= sizes[1]
+
+
+def gpu_compress_five_read(x, mode, value, in_offset=0):
+    n = x.size
+    xd = torch.zeros(n + in_offset + 4, dtype=torch.float32, device=_dev())
+    if n:
+        xd[in_offset:in_offset + n] = torch.from_numpy(x).to(_dev())
+    cap = fsz.fsz_compressed_bound(n)
+    out = torch.zeros(max(cap, 1), dtype=torch.uint8, device=_dev())
+    res = torch.zeros(2, dtype=torch.int64, device=_dev())
+    stream = torch.cuda.current_stream(_dev()).cuda_stream
+    st = fsz.fsz_compress_five_read_async(xd.data_ptr() + 4 * in_offset, n, mode, value, None,
+                                          out.data_ptr(), cap, res.data_ptr(), stream)
+    if st != fsz.FSZ_OK:
+        return st, None
+    torch.cuda.synchronize()
+    r = res.cpu()
+    size, st = int(r[0]), int(r[1]) & 0xFFFFFFFF
+    if st != fsz.FSZ_OK:
+        return st, None
+    return st, out[:size].cpu().numpy().tobytes()
+
+
+def test_five_read_baseline_matches_oracle():
+    """Sec. V-C: the naive five-read evaluation produces the same stream as
+    the single pass."""
+    for name, x in list(_fields()) + [("empty", np.zeros(0, dtype=np.float32))]:
+        for rel in (1e-2, 1e-4):
+            for off in (0, 1):
+                announce(f"five-read {name} REL {rel:g} input offset {off}")
+                st, got = gpu_compress_five_read(x, oracle.REL, rel, in_offset=off)
+                assert st == fsz.FSZ_OK
+                exp = oracle.compress(x, oracle.REL, rel)
+                assert got == exp, first_diff(got, exp)
+
+
+def test_five_read_reports_errors():
+    x = workloads.sinusoid_field(5000, 2)
+    announce("five-read: bound too small, then a NaN")
+    st, _ = gpu_compress_five_read(x, oracle.ABS, 1e-12)
+    assert st == fsz.FSZ_ERR_EB_TOO_SMALL
+    x[77] = np.nan
+    st, _ = gpu_compress_five_read(x, oracle.REL, 1e-3)
+    assert st == fsz.FSZ_ERR_NONFINITE
