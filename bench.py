@@ -376,6 +376,105 @@ def served_benchmark(args):
     print(json.dumps(line), flush=True)
 
 
+ABLATION_COLUMNS = (("base", 0), ("+cross", 1), ("+cent", 3), ("+lz2 (full)", 7))  # feature masks
+
+
+def _timed(torch, stream, fn, reps):
+    fn()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record(stream)
+    for _ in range(reps):
+        fn()
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    return e[0].elapsed_time(e[1]) / reps
+
+
+def ablation_columns(torch, fsz, x, stats, reps: int = 5, reference=None):
+    """The ablation's four columns (Sec. VI-B, Table IV: Base = LZ1 on
+    independent blocks, +Cross, +Cent, +LZ2 = the full method) on one field:
+    CR and compress GB/s (4n / kernel time) per bound.  reference: the
+    default path's streams per bound, which the full column must equal."""
+    stream = torch.cuda.current_stream(x.device)
+    sh = stream.cuda_stream
+    n = x.numel()
+    cap = fsz.fsz_compressed_bound(n)
+    buf = torch.empty(cap, dtype=torch.uint8, device=x.device)
+    res = torch.zeros(4, dtype=torch.int32, device=x.device)
+    rows = []
+    for k, rel in enumerate(RELS):
+        row = {"rel": rel}
+        for name, f in ABLATION_COLUMNS:
+            def run():
+                st = fsz.fsz_compress_features_async(x.data_ptr(), n, fsz.FSZ_REL, rel, stats.data_ptr(), f,
+                                                     buf.data_ptr(), cap, res.data_ptr(), sh)
+                if st != fsz.FSZ_OK:
+                    raise RuntimeError(fsz.fsz_status_string(st))
+            ms = _timed(torch, stream, run, reps)
+            size, st, _ = fsz.read_result(res)
+            if st != fsz.FSZ_OK:
+                raise RuntimeError(f"ablation {name} rel={rel}: {fsz.fsz_status_string(st)}")
+            row[name] = {"cr": round(4 * n / size, 4), "compress_GBps": round(4 * n / ms / 1e6, 1)}
+            if f == fsz.FSZ_FEATURES_ALL and reference is not None:
+                ref = reference[k]
+                row[name]["identical_to_default"] = bool(size == ref.numel() and torch.equal(buf[:size], ref))
+        rows.append(row)
+    del buf
+    return rows
+
+
+def five_read_comparison(torch, fsz, x, stats, outs, sizes, reps: int = 5):
+    """The single pass against the naive five-read evaluation (Sec. V-C,
+    Fig. 6) on the timed field; the streams must be byte-identical."""
+    stream = torch.cuda.current_stream(x.device)
+    sh = stream.cuda_stream
+    n = x.numel()
+    cap = fsz.fsz_compressed_bound(n)
+    buf = torch.empty(cap, dtype=torch.uint8, device=x.device)
+    res = torch.zeros(4, dtype=torch.int32, device=x.device)
+    rows = []
+    for k, rel in enumerate(RELS):
+        def five():
+            st = fsz.fsz_compress_five_read_async(x.data_ptr(), n, fsz.FSZ_REL, rel, stats.data_ptr(),
+                                                  buf.data_ptr(), cap, res.data_ptr(), sh)
+            if st != fsz.FSZ_OK:
+                raise RuntimeError(fsz.fsz_status_string(st))
+        f_ms = _timed(torch, stream, five, reps)
+        size, st, _ = fsz.read_result(res)
+        if st != fsz.FSZ_OK:
+            raise RuntimeError(f"five-read rel={rel}: {fsz.fsz_status_string(st)}")
+
+        def single():
+            st = fsz.fsz_compress_async(x.data_ptr(), n, fsz.FSZ_REL, rel, stats.data_ptr(), outs[k].data_ptr(),
+                                        cap, res.data_ptr(), sh)
+            if st != fsz.FSZ_OK:
+                raise RuntimeError(fsz.fsz_status_string(st))
+        s_ms = _timed(torch, stream, single, reps)
+        rows.append({"rel": rel, "single_pass_ms": round(s_ms, 4), "five_read_ms": round(f_ms, 4),
+                     "speedup": round(f_ms / s_ms, 2),
+                     "identical": bool(size == sizes[k] and torch.equal(buf[:size], outs[k][:size]))})
+    del buf
+    return rows
+
+
+def ablation_benchmark(torch, fsz, workloads, x, stats, outs, sizes):
+    """Ablation columns on the timed k^-3 field and on the 100x500x500
+    piecewise-quadratic field (offsets, zero boxes and quadratic trends), plus
+    the five-read comparison on the timed field."""
+    grf = ablation_columns(torch, fsz, x, stats, reference=[outs[k][:sizes[k]] for k in range(len(RELS))])
+    t0 = time.time()
+    p_np = workloads.piecewise_quadratic((100, 500, 500), 2)
+    print(f"[bench] generated piecewise quadratic in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    p = torch.from_numpy(p_np).to(x.device)
+    pstats = torch.zeros(4, dtype=torch.int32, device=x.device)
+    st = fsz.fsz_field_stats(p.data_ptr(), p.numel(), pstats.data_ptr(), torch.cuda.current_stream(x.device).cuda_stream)
+    if st != fsz.FSZ_OK:
+        raise RuntimeError(fsz.fsz_status_string(st))
+    pwq = ablation_columns(torch, fsz, p, pstats)
+    five = five_read_comparison(torch, fsz, x, stats, outs, sizes)
+    return {"grf 512^3": grf, "piecewise quadratic 100x500x500": pwq}, five
+
+
 def small_configs(torch, fsz, workloads, verify: bool, reps: int = 20):
     """The 2^20 sinusoid field (REL 1e-3; warm and MALL-flushed) and the
     100x500x500 piecewise-quadratic field (REL 1e-2/1e-3/1e-4; flushed: a
@@ -458,6 +557,8 @@ def parse_args():
                     help="skip the batched-form comparison on the 64-field workload and the two small "
                          "configurations (2^20 sinusoid, 100x500x500 piecewise quadratic)")
     ap.add_argument("--batched-reps", type=int, default=10)
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the ablation columns and the five-read comparison")
     ap.add_argument("--served", action="store_true",
                     help="run the served request-loop workload instead of the default one")
     ap.add_argument("--served-loads", type=str, default="0.1,0.3,0.5,0.7,0.9,1.2,1.5")
@@ -656,6 +757,9 @@ def main():
                 "decompress_GBps": round(len(RELS) * 4 * n / t_d / 1e9, 4),
             }
 
+    ablation = five_read = None
+    if not args.no_ablation:
+        ablation, five_read = ablation_benchmark(torch, fsz, workloads, x, stats, outs, sizes)
     others = None
     if not args.no_batched:
         others = small_configs(torch, fsz, workloads, not args.no_verify)
@@ -694,6 +798,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "oracle_identical": verified,
+        "ablation": ablation,
+        "five_read": five_read,
         "batched": batched,
         "other_configs": others,
     }
