@@ -132,6 +132,21 @@ fsz_status fsz_compress_async(const float *d_in, size_t n, fsz_eb_mode mode, dou
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
                                 fsz_result *d_result, void *stream);
 
+/* Random-access decode: elements [begin, end) of the n-element field that
+ * d_cmp[0..cmp_size) holds, into d_out[0 .. end - begin).  Decompression
+ * steps 1-5 of Sec. III-A restricted to the tiles that hold the range: the
+ * byte offset of the first one is a reduction of the block sizes before it
+ * over the rate header (no data bytes before the range are read), then the
+ * offset scan and the decode run over the range's tiles only.  The values
+ * equal the same elements of a whole-field decode bit for bit.  Checks the
+ * header, the range's rate bytes and those before it; unlike a whole-field
+ * decode it does not check that the stream's sizes add up to its total.
+ * Errors: FSZ_ERR_INVALID_ARG for begin > end, end > n, a null or
+ * misaligned pointer, d_result null; then as fsz_decompress_async
+ * (result size = the stream's total bytes). */
+fsz_status fsz_decompress_range_async(const void *d_cmp, size_t cmp_size, size_t n, size_t begin, size_t end,
+                                      float *d_out, fsz_result *d_result, void *stream);
+
 /* ------------------------------------------------------------------------
  * Feature switches (the ablation of Sec. VI-B, Table IV): compression with a
  * subset of the method's three prediction designs.  0 is the base the paper

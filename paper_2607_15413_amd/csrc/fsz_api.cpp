@@ -107,6 +107,8 @@ struct Workspace {
     fsz_stats *b_stats = nullptr;
     uint64_t b_stats_cap = 0;
     unsigned long long *b_ticket = nullptr;
+    // random-access decode: the range's base offset, then the reduction partials
+    unsigned long long *d_range = nullptr;
     // five-read baseline: evaluation tables (53 bytes per tile)
     uint8_t *d_naive = nullptr;
     uint64_t naive_cap = 0;
@@ -283,6 +285,11 @@ fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_siz
     a.nblocks = ceil_div(n, kBlock);
     a.nchunks = a.ntiles ? ceil_div(a.ntiles, kTilesPerChunk) : 1;
     a.data0 = kHeaderBytes + pad16(a.nblocks);
+    a.tile_begin = 0;
+    a.tile_end = a.ntiles;
+    a.elem_begin = 0;
+    a.elem_end = n;
+    a.range_base = nullptr;
     if (!ensure_flags(ws, std::max<uint64_t>(a.nchunks, ceil_div(a.ntiles, kTilesPerWave)))) return FSZ_ERR_DEVICE;
     if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
     a.flags = ws->d_flags;
@@ -290,6 +297,40 @@ fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_siz
     a.final = d_final;
     if (!ok(launch_decompress(a, aligned(d_out, 16), tuning().staged_decompress, ws->stream))) return FSZ_ERR_DEVICE;
     *epoch_out = a.epoch;
+    return FSZ_OK;
+}
+
+// Random-access decode of elements [begin, end): the tiles that hold them,
+// at the offset the rate header gives for the first one.
+fsz_status enqueue_decompress_range(Workspace *ws, const void *d_cmp, uint64_t cmp_size, uint64_t n,
+                                    uint64_t begin, uint64_t end, float *d_out, fsz_result *d_final)
+{
+    DecompressArgs a{};
+    a.cmp = static_cast<const uint8_t *>(d_cmp);
+    a.cmp_size = cmp_size;
+    a.out = d_out;
+    a.n = n;
+    a.ntiles = ceil_div(n, kTile);
+    a.nblocks = ceil_div(n, kBlock);
+    a.data0 = kHeaderBytes + pad16(a.nblocks);
+    a.tile_begin = begin / kTile;
+    a.tile_end = end > begin ? ceil_div(end, kTile) : a.tile_begin;
+    a.elem_begin = begin;
+    a.elem_end = end;
+    const uint64_t tiles = a.tile_end - a.tile_begin;
+    a.nchunks = tiles ? ceil_div(tiles, kTilesPerChunk) : 1;
+    if (!ws->d_range && !ok(hipMalloc(&ws->d_range, (1 + kStatsMaxBlocks) * sizeof(unsigned long long))))
+        return FSZ_ERR_DEVICE;
+    if (!ok(launch_range_base(a, ws->d_range, ws->d_range + 1, ws->stream))) return FSZ_ERR_DEVICE;
+    a.range_base = ws->d_range;
+    if (!ensure_flags(ws, std::max<uint64_t>(a.nchunks, ceil_div(tiles, kTilesPerWave)))) return FSZ_ERR_DEVICE;
+    if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
+    a.flags = ws->d_flags;
+    a.ticket = ws->d_ticket;
+    a.final = d_final;
+    // 16-byte stores need the field's element 0 (d_out - begin) 16-byte aligned
+    const bool al16 = ((reinterpret_cast<uintptr_t>(d_out) - 4 * (uintptr_t)begin) & 15u) == 0;
+    if (!ok(launch_decompress(a, al16, tuning().staged_decompress, ws->stream))) return FSZ_ERR_DEVICE;
     return FSZ_OK;
 }
 
@@ -724,6 +765,18 @@ fsz_status fsz_compress_five_read_async(const float *d_in, size_t n, fsz_eb_mode
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);
     return enqueue_compress_naive(ws, d_in, n, mode, value, d_stats, d_out, out_capacity, d_result);
+}
+
+fsz_status fsz_decompress_range_async(const void *d_cmp, size_t cmp_size, size_t n, size_t begin, size_t end,
+                                      float *d_out, fsz_result *d_result, void *stream)
+{
+    if (!d_result || begin > end || end > n) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_decompress_args(d_cmp, cmp_size, d_out, end - begin);
+    if (st != FSZ_OK) return st;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    return enqueue_decompress_range(ws, d_cmp, cmp_size, n, begin, end, d_out, d_result);
 }
 
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,

@@ -76,8 +76,14 @@ struct CompressArgs {
 struct DecompressArgs {
     const uint8_t *cmp;
     uint64_t cmp_size;
-    float *out;
+    float *out;  // element elem_begin of the field
     uint64_t n, ntiles, nblocks, nchunks, data0;
+    // Decoded range: tiles [tile_begin, tile_end) (chunks count from
+    // tile_begin), elements [elem_begin, elem_end) written.  range_base: the
+    // byte offset of tile_begin's data after data0 (device; null = 0 for a
+    // whole-field decode, which also checks the stream's total and padding).
+    uint64_t tile_begin, tile_end, elem_begin, elem_end;
+    const unsigned long long *range_base;
     uint32_t epoch, flag_epoch;
     unsigned long long *flags;
     unsigned long long *ticket;  // zero between launches (self-resetting)
@@ -146,6 +152,10 @@ hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged
 // (a.nchunks counts chunks of kTilesPerChunk tiles).
 hipError_t launch_compress_naive(const CompressArgs &a, const NaiveTables &t, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s);
+// Byte offset of tile_begin's data: a reduction of the block sizes before it
+// over the rate header into *range_base (partials: kStatsMaxBlocks words).
+hipError_t launch_range_base(const DecompressArgs &a, unsigned long long *range_base, unsigned long long *partials,
+                             hipStream_t s);
 // Range pass + flag clear, per-job stats, then the batched kernel.
 hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, const BatchShape &shape,
                         hipStream_t s);

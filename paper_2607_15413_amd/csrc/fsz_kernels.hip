@@ -1502,7 +1502,9 @@ struct DecompressShared {
 // Decompression steps 1-2 (Sec. III-A): rate bytes and tile metadata ->
 // block and tile sizes -> this chunk's aggregate, published at once so that
 // successors' lookbacks rarely wait.
-template <int W>
+// RANGE: decode the tiles [a.tile_begin, a.tile_end) only (random access);
+// otherwise the whole field (the range fields are not read).
+template <int W, bool RANGE = false>
 __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t chunk, int slot,
                                               DecompressShared<W> &sh)
 {
@@ -1510,10 +1512,11 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
     const int w = tid >> 6;
     const int lane = tid & 63;
     const int j = lane & 7;
-    const uint64_t tile = chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave + (lane >> 3);
-    const bool tile_ok = tile < a.ntiles;
+    const uint64_t tile =
+        (RANGE ? a.tile_begin : 0) + chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave + (lane >> 3);
+    const bool tile_ok = tile < (RANGE ? a.tile_end : a.ntiles);
     const uint64_t gblock = tile * kBlocksPerTile + j;
-    const bool blk_ok = gblock < a.nblocks;
+    const bool blk_ok = (RANGE ? tile_ok : true) && gblock < a.nblocks;
     const uint32_t rb = blk_ok ? a.cmp[kHeaderBytes + gblock] : 0u;
     const bool bad = blk_ok && (j == 0 ? (rb & 0x20u) : (rb & 0xE0u)) != 0;
     const uint32_t head = (uint32_t)group_head((int)rb);
@@ -1546,7 +1549,7 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
 // Decompression steps 3-5: lookback offset, bit-unshuffle, inverse
 // cross-block prediction (one inclusive scan for LZ1, two for LZ2, plus the
 // tile mean), x' = (float)q * E.
-template <bool ALIGNED, bool STAGED, int W>
+template <bool ALIGNED, bool STAGED, int W, bool RANGE = false>
 __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChunk &d, int slot, float E,
                                            uint64_t total, bool indep, uint32_t *st, DecompressShared<W> &sh)
 {
@@ -1561,21 +1564,27 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
         chunk_total += sh.wave_total[slot][k];
     }
     const bool bad = sh.bad[slot] != 0;
+    const uint64_t base0 = RANGE ? *a.range_base : 0;  // data of tiles before the range
     if (w == 0) {
         const Prefix pre = lookback_wait(a.flags, d.chunk, a.flag_epoch, chunk_total, bad);
         if (lane == 0) {
-            sh.base = pre.excl;
+            sh.base = base0 + pre.excl;
             if (d.chunk == a.nchunks - 1) {
-                bool ok = !pre.err && a.data0 + pre.excl + chunk_total == total;
-                for (uint64_t k = kHeaderBytes + a.nblocks; ok && k < a.data0; k++) ok = a.cmp[k] == 0;
+                bool ok;
+                if (RANGE) {  // a range: its data lies inside the stream
+                    ok = !pre.err && a.data0 + base0 + pre.excl + chunk_total <= total;
+                } else {  // the whole field: the sizes add up to the stream's total, padding is zero
+                    ok = !pre.err && a.data0 + pre.excl + chunk_total == total;
+                    for (uint64_t k = kHeaderBytes + a.nblocks; ok && k < a.data0; k++) ok = a.cmp[k] == 0;
+                }
                 write_final(a.final, total, ok ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT, a.epoch);
             }
         }
     }
     lds_barrier();
     const uint64_t base = sh.base;
-    const uint64_t tile0 = d.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
-    if (bad || a.data0 + base + chunk_total > total || tile0 >= a.ntiles) return;
+    const uint64_t tile0 = (RANGE ? a.tile_begin : 0) + d.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
+    if (bad || a.data0 + base + chunk_total > total || tile0 >= (RANGE ? a.tile_end : a.ntiles)) return;
 
     const uint64_t gblock = (tile0 + (lane >> 3)) * kBlocksPerTile + j;
     const bool blk_ok = gblock < a.nblocks;
@@ -1639,15 +1648,17 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
 
     const uint64_t eblk = gblock * kBlock;
     const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
+    // element e of the field goes to a.out[e - eb], for eb <= e < ee
+    const uint64_t eb = RANGE ? a.elem_begin : 0, ee = RANGE ? a.elem_end : a.n;
     if (!STAGED) {  // lane-per-block stores, 8 x 16 B per lane
-        if (ALIGNED && cnt == 32) {
-            f4 *p = reinterpret_cast<f4 *>(a.out + eblk);
+        if (ALIGNED && cnt == 32 && eblk >= eb && eblk + 32 <= ee) {
+            f4 *p = reinterpret_cast<f4 *>(a.out + (eblk - eb));
 #pragma unroll
             for (int k = 0; k < 8; k++) p[k] = f4{xo[4 * k], xo[4 * k + 1], xo[4 * k + 2], xo[4 * k + 3]};
         } else {
 #pragma unroll
             for (int i = 0; i < 32; i++)
-                if (i < cnt) a.out[eblk + i] = xo[i];
+                if (i < cnt && eblk + i >= eb && eblk + i < ee) a.out[eblk + i - eb] = xo[i];
         }
         return;
     }
@@ -1659,19 +1670,20 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const uint64_t e0 = tile0 * kTile;
-    const bool fullw = e0 + 2048 <= a.n;
-    if (ALIGNED) {
+    const bool fullw = e0 >= eb && e0 + 2048 <= ee;  // the wave's 8 tiles lie inside the range
+    if (ALIGNED) {  // 16-byte aligned: a.out - eb (the field's element 0) is
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             const int p = k * 64 + lane;
             const uint64_t e = e0 + 4ull * p;
             const f4 f = *reinterpret_cast<const f4 *>(st + (p >> 3) * kStageRowDwords + (p & 7) * 4);
-            if (fullw || e + 4 <= a.n) {
-                __builtin_nontemporal_store(f, reinterpret_cast<f4 *>(a.out + e));
+            if (fullw || (e >= eb && e + 4 <= ee)) {
+                __builtin_nontemporal_store(f, reinterpret_cast<f4 *>(a.out + (e - eb)));
             } else {
-                if (e + 0 < a.n) a.out[e + 0] = f.x;
-                if (e + 1 < a.n) a.out[e + 1] = f.y;
-                if (e + 2 < a.n) a.out[e + 2] = f.z;
+                if (e + 0 >= eb && e + 0 < ee) a.out[e + 0 - eb] = f.x;
+                if (e + 1 >= eb && e + 1 < ee) a.out[e + 1 - eb] = f.y;
+                if (e + 2 >= eb && e + 2 < ee) a.out[e + 2 - eb] = f.z;
+                if (e + 3 >= eb && e + 3 < ee) a.out[e + 3 - eb] = f.w;
             }
         }
     } else {
@@ -1679,7 +1691,8 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
         for (int k = 0; k < 32; k++) {
             const int p = k * 64 + lane;
             const uint64_t e = e0 + p;
-            if (fullw || e < a.n) a.out[e] = __uint_as_float(st[(p >> 5) * kStageRowDwords + (p & 31)]);
+            if (fullw || (e >= eb && e < ee))
+                a.out[e - eb] = __uint_as_float(st[(p >> 5) * kStageRowDwords + (p & 31)]);
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -1709,7 +1722,7 @@ __device__ __forceinline__ int dec_header(const DecompressArgs &a, float &E, uin
 // publishes its aggregate) runs before the decode of the current one.
 // W waves per workgroup; a chunk is 8 tiles per wave (a.nchunks counts chunks
 // of that size).
-template <bool ALIGNED, bool STAGED, int W>
+template <bool ALIGNED, bool STAGED, int W, bool RANGE = false>
 __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint32_t stage[STAGED ? W * kStageWaveDwords : 4];
@@ -1731,16 +1744,70 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
     uint64_t cur = next_ticket(a.ticket, takes, sh, tslot);
     if (cur >= a.nchunks) return;
     int slot = 0;
-    DecChunk dc = dec_sizes<W>(a, cur, slot, sh);
+    DecChunk dc = dec_sizes<W, RANGE>(a, cur, slot, sh);
     for (;;) {
         const uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
         DecChunk dn;
-        if (nxt < a.nchunks) dn = dec_sizes<W>(a, nxt, slot ^ 1, sh);
-        dec_decode<ALIGNED, STAGED, W>(a, dc, slot, E, total, indep, st, sh);
+        if (nxt < a.nchunks) dn = dec_sizes<W, RANGE>(a, nxt, slot ^ 1, sh);
+        dec_decode<ALIGNED, STAGED, W, RANGE>(a, dc, slot, E, total, indep, st, sh);
         if (nxt >= a.nchunks) break;
         dc = dn;
         slot ^= 1;
     }
+}
+
+// ------------------------------------------------------------------ random-access decode
+
+// Byte offset of a range's first tile, from the rate header alone (the block
+// sizes of decompression step 2, Sec. III-A): each workgroup sums the sizes of
+// a grid-stride share of the blocks before tile_begin; a reserved rate-byte
+// bit sets bit 63 of the partial.
+__global__ __launch_bounds__(kStatsThreads) void range_partial_kernel(DecompressArgs a, unsigned long long *partials)
+{
+    const uint64_t nb = a.tile_begin * kBlocksPerTile;  // every tile before the last is whole
+    unsigned long long sum = 0;
+    uint32_t bad = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
+        const uint32_t rb = a.cmp[kHeaderBytes + b];
+        const bool head = (b & (kBlocksPerTile - 1)) == 0;
+        bad |= head ? (rb & 0x20u) : (rb & 0xE0u);
+        sum += block_bytes(rb & 31u) + ((head && (rb & 0x40u)) ? 4u : 0u);
+    }
+    sum = wave_sum_u64(sum);
+    const bool wbad = __ballot(bad != 0) != 0;
+    __shared__ unsigned long long wsum[kStatsThreads / 64];
+    __shared__ uint32_t wflag[kStatsThreads / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wsum[threadIdx.x >> 6] = sum;
+        wflag[threadIdx.x >> 6] = wbad ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        uint32_t f = 0;
+        for (int k = 0; k < kStatsThreads / 64; k++) {
+            t += wsum[k];
+            f |= wflag[k];
+        }
+        partials[blockIdx.x] = t | ((unsigned long long)f << 63);
+    }
+}
+
+// Folds the partials into *out; a reserved bit anywhere makes the offset
+// 2^62, past any stream, so the decode reports a corrupt stream.
+__global__ __launch_bounds__(64) void range_final_kernel(const unsigned long long *partials, unsigned nparts,
+                                                         unsigned long long *out)
+{
+    unsigned long long t = 0;
+    bool bad = false;
+    for (unsigned i = threadIdx.x; i < nparts; i += 64) {
+        t += partials[i] & ~(1ull << 63);
+        bad = bad || (partials[i] >> 63) != 0;
+    }
+    t = wave_sum_u64(t);
+    bad = __ballot(bad) != 0;
+    if (threadIdx.x == 0) *out = bad ? (1ull << 62) : t;
 }
 
 // ------------------------------------------------------------------ batched form
@@ -1856,6 +1923,11 @@ __global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
         a.nblocks = J.nblocks;
         a.nchunks = J.nchunks;
         a.data0 = J.data0;
+        a.tile_begin = 0;
+        a.tile_end = J.ntiles;
+        a.elem_begin = 0;
+        a.elem_end = J.n;
+        a.range_base = nullptr;
         a.epoch = b.epoch;
         a.flag_epoch = 1;
         a.flags = b.flags + J.chunk_base;
@@ -1912,15 +1984,16 @@ static hipError_t launch_compress_t(const CompressArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool ALIGNED, bool STAGED, int W>
+template <bool ALIGNED, bool STAGED, int W, bool RANGE = false>
 static hipError_t launch_decompress_w(const DecompressArgs &a, hipStream_t s)
 {
     // the arguments count chunks of kTilesPerChunk tiles
     DecompressArgs p = a;
-    p.nchunks = p.ntiles ? ceil_div(p.ntiles, (uint64_t)kTilesPerWave * W) : 1;
-    static const unsigned cap = persistent_grid(decompress_kernel<ALIGNED, STAGED, W>, ~0ull, W * 64);
+    const uint64_t tiles = p.tile_end - p.tile_begin;
+    p.nchunks = tiles ? ceil_div(tiles, (uint64_t)kTilesPerWave * W) : 1;
+    static const unsigned cap = persistent_grid(decompress_kernel<ALIGNED, STAGED, W, RANGE>, ~0ull, W * 64);
     const unsigned grid = (unsigned)(p.nchunks < cap ? p.nchunks : cap);
-    hipLaunchKernelGGL((decompress_kernel<ALIGNED, STAGED, W>), dim3(grid), dim3(W * 64), 0, s, p);
+    hipLaunchKernelGGL((decompress_kernel<ALIGNED, STAGED, W, RANGE>), dim3(grid), dim3(W * 64), 0, s, p);
     return hipGetLastError();
 }
 
@@ -2008,8 +2081,22 @@ hipError_t launch_compress_naive(const CompressArgs &a, const NaiveTables &t, bo
     return hipGetLastError();
 }
 
+hipError_t launch_range_base(const DecompressArgs &a, unsigned long long *range_base, unsigned long long *partials,
+                             hipStream_t s)
+{
+    const uint64_t nb = a.tile_begin * kBlocksPerTile;
+    const uint64_t want = ceil_div(nb, (uint64_t)kStatsThreads * 16);
+    const unsigned grid = (unsigned)(want < 1 ? 1 : (want > kStatsMaxBlocks ? kStatsMaxBlocks : want));
+    hipLaunchKernelGGL(range_partial_kernel, dim3(grid), dim3(kStatsThreads), 0, s, a, partials);
+    hipLaunchKernelGGL(range_final_kernel, dim3(1), dim3(64), 0, s, partials, grid, range_base);
+    return hipGetLastError();
+}
+
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s)
 {
+    if (a.range_base)  // random access: the staged 8-wave decoder with range bookkeeping
+        return out_aligned16 ? launch_decompress_w<true, true, 8, true>(a, s)
+                             : launch_decompress_w<false, true, 8, true>(a, s);
     if (out_aligned16)
         return staged ? launch_decompress_t<true, true>(a, s) : launch_decompress_t<true, false>(a, s);
     return staged ? launch_decompress_t<false, true>(a, s) : launch_decompress_t<false, false>(a, s);

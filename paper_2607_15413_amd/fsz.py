@@ -41,6 +41,7 @@ EXPORTS = (
     "fsz_decompress",
     "fsz_compress_async",
     "fsz_decompress_async",
+    "fsz_decompress_range_async",
     "fsz_compress_features_async",
     "fsz_compress_five_read_async",
     "fsz_batch_async",
@@ -150,6 +151,8 @@ def load_library():
     lib.fsz_compress_features_async.restype = ctypes.c_int
     lib.fsz_compress_five_read_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, vp, sz, vp, vp]
     lib.fsz_compress_five_read_async.restype = ctypes.c_int
+    lib.fsz_decompress_range_async.argtypes = [vp, sz, sz, sz, sz, vp, vp, vp]
+    lib.fsz_decompress_range_async.restype = ctypes.c_int
     lib.fsz_decompress_async.argtypes = [vp, sz, vp, sz, vp, vp]
     lib.fsz_decompress_async.restype = ctypes.c_int
     jp, tp = ctypes.POINTER(FszJob), ctypes.POINTER(FszTuning)
@@ -225,6 +228,12 @@ def fsz_compress_async(d_in: int, n: int, mode: int, value: float, d_stats, d_ou
     """Enqueue only; the outcome lands in the device fsz_result at d_result."""
     return load_library().fsz_compress_async(d_in, n, mode, value, d_stats, d_out, out_capacity,
                                              d_result, stream)
+
+
+def fsz_decompress_range_async(d_cmp: int, cmp_size: int, n: int, begin: int, end: int, d_out: int,
+                               d_result: int, stream=None) -> int:
+    """Elements [begin, end) of the stream's field into d_out (enqueue only)."""
+    return load_library().fsz_decompress_range_async(d_cmp, cmp_size, n, begin, end, d_out, d_result, stream)
 
 
 def fsz_compress_features_async(d_in: int, n: int, mode: int, value: float, d_stats, features: int,

@@ -1,0 +1,85 @@
+"""GPU random-access decode: elements [begin, end) of a stream decoded alone
+equal the same elements of the oracle's whole-field decode bit for bit
+(ranges at the start, the end, across tile and chunk boundaries, empty,
+unaligned outputs, streams with independent blocks), and corrupt rate bytes
+before or inside the range are reported.  Every case prints its name before
+touching the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_15413_amd import fsz, workloads
+from tests.test_gpu_parity import announce
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def gpu_decompress_range(stream_bytes, n, begin, end, out_offset=0):
+    buf = torch.from_numpy(np.frombuffer(stream_bytes, dtype=np.uint8).copy()).to(_dev())
+    m = end - begin
+    guard = 8
+    out = torch.full((m + out_offset + 2 * guard,), float("nan"), dtype=torch.float32, device=_dev())
+    res = torch.zeros(2, dtype=torch.int64, device=_dev())
+    stream = torch.cuda.current_stream(_dev()).cuda_stream
+    st = fsz.fsz_decompress_range_async(buf.data_ptr(), len(stream_bytes), n, begin, end,
+                                        out.data_ptr() + 4 * (guard + out_offset), res.data_ptr(), stream)
+    if st != fsz.FSZ_OK:
+        return st, None
+    torch.cuda.synchronize()
+    st = int(res.cpu()[1]) & 0xFFFFFFFF
+    o = out.cpu().numpy()
+    # nothing outside the requested range was written
+    assert np.all(np.isnan(o[:guard + out_offset])) and np.all(np.isnan(o[guard + out_offset + m:]))
+    return st, o[guard + out_offset:guard + out_offset + m]
+
+
+def _ranges(n):
+    chunk = 64 * 256
+    cand = [(0, n), (0, 1), (n - 1, n), (255, 257), (256, 512), (1000, 70000), (n // 2, n),
+            (chunk - 3, 3 * chunk + 5), (5, 5), (n, n), (n // 3, n // 3 + 100001)]
+    return [(b, e) for b, e in cand if 0 <= b <= e <= n]
+
+
+@pytest.mark.parametrize("features", [fsz.FSZ_FEATURES_ALL, 0])
+def test_range_decode_matches_whole_field(features):
+    for name, x in (("grf 64x64x80", workloads.grf_field((64, 64, 80), 3)),
+                    ("pwq 5x301x181 (ragged)", workloads.piecewise_quadratic((5, 301, 181), 4))):
+        n = x.size
+        s = oracle.compress(x, oracle.REL, 1e-3, features=features)
+        full = oracle.decompress(s, n)
+        for begin, end in _ranges(n):
+            for off in (0, 1):
+                announce(f"range {name} features {features} [{begin}, {end}) output offset {off}")
+                st, y = gpu_decompress_range(s, n, begin, end, out_offset=off)
+                assert st == fsz.FSZ_OK
+                assert np.array_equal(y.view(np.uint32), full[begin:end].view(np.uint32)), (begin, end)
+
+
+def test_range_decode_errors():
+    x = workloads.sinusoid_field(100000, 5)
+    n = x.size
+    s = oracle.compress(x, oracle.REL, 1e-3)
+    announce("range: begin > end, end > n")
+    buf = torch.from_numpy(np.frombuffer(s, dtype=np.uint8).copy()).to(_dev())
+    out = torch.zeros(16, dtype=torch.float32, device=_dev())
+    res = torch.zeros(2, dtype=torch.int64, device=_dev())
+    stream = torch.cuda.current_stream(_dev()).cuda_stream
+    assert fsz.fsz_decompress_range_async(buf.data_ptr(), len(s), n, 10, 5, out.data_ptr(), res.data_ptr(),
+                                          stream) == fsz.FSZ_ERR_INVALID_ARG
+    assert fsz.fsz_decompress_range_async(buf.data_ptr(), len(s), n, 0, n + 1, out.data_ptr(), res.data_ptr(),
+                                          stream) == fsz.FSZ_ERR_INVALID_ARG
+    # a reserved bit (bit 5 of a tile's first rate byte) in a block before the
+    # range (tile 3; the range starts at tile 4), then in one inside it (tile 8)
+    for blk, begin, end, name in ((24, 1024, 3000, "before the range"), (64, 0, 5000, "inside the range")):
+        bad = bytearray(s)
+        bad[32 + blk] |= 0x20
+        announce(f"range: corrupt rate byte {name} (block {blk})")
+        st, _ = gpu_decompress_range(bytes(bad), n, begin, end)
+        assert st == fsz.FSZ_ERR_CORRUPT, name
