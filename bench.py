@@ -457,6 +457,33 @@ def five_read_comparison(torch, fsz, x, stats, outs, sizes, reps: int = 5):
     return rows
 
 
+def random_access(torch, fsz, outs, sizes, n, full_ms, reps: int = 20):
+    """Random-access decode (rate-header prefix + the range's tiles) of ranges
+    in the middle of the REL 1e-3 stream, against the whole-field decode."""
+    dev = outs[0].device
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    k = 1
+    res = torch.zeros(4, dtype=torch.int32, device=dev)
+    rows = []
+    for m in (256, 1 << 18, n // 10):
+        begin = n // 2 - m // 2
+        y = torch.empty(m, dtype=torch.float32, device=dev)
+
+        def run():
+            st = fsz.fsz_decompress_range_async(outs[k].data_ptr(), sizes[k], n, begin, begin + m, y.data_ptr(),
+                                                res.data_ptr(), sh)
+            if st != fsz.FSZ_OK:
+                raise RuntimeError(fsz.fsz_status_string(st))
+        ms = _timed(torch, stream, run, reps)
+        _, st, _ = fsz.read_result(res)
+        if st != fsz.FSZ_OK:
+            raise RuntimeError(f"range decode: {fsz.fsz_status_string(st)}")
+        rows.append({"elements": m, "begin": begin, "ms": round(ms, 4), "whole_field_ms": round(full_ms, 4)})
+        del y
+    return {"rel": RELS[k], "ranges": rows}
+
+
 def ablation_benchmark(torch, fsz, workloads, x, stats, outs, sizes):
     """Ablation columns on the timed k^-3 field and on the 100x500x500
     piecewise-quadratic field (offsets, zero boxes and quadratic trends), plus
@@ -757,9 +784,10 @@ def main():
                 "decompress_GBps": round(len(RELS) * 4 * n / t_d / 1e9, 4),
             }
 
-    ablation = five_read = None
+    ablation = five_read = ranges = None
     if not args.no_ablation:
         ablation, five_read = ablation_benchmark(torch, fsz, workloads, x, stats, outs, sizes)
+        ranges = random_access(torch, fsz, outs, sizes, n, dec_ms[1])
     others = None
     if not args.no_batched:
         others = small_configs(torch, fsz, workloads, not args.no_verify)
@@ -800,6 +828,7 @@ def main():
         "oracle_identical": verified,
         "ablation": ablation,
         "five_read": five_read,
+        "random_access": ranges,
         "batched": batched,
         "other_configs": others,
     }
