@@ -98,6 +98,39 @@ def test_grf_small():
         check_round_trip("grf-64^3", x, fsz.FSZ_REL, rel)
 
 
+def test_grf_512_full_size_bench_launch():
+    """The benchmark's field (512^3 k^-3 GRF, seed 1) at full size, in the
+    benchmark's launch configuration (one range pass, then the asynchronous
+    compress per bound on the persistent pipelined kernel, decompress on the
+    persistent decoder): every byte and every reconstructed value against the
+    oracle."""
+    x = workloads.grf_field((512, 512, 512), 1)
+    n = x.size
+    announce("grf-512^3 full size, bench launch configuration")
+    xd = torch.from_numpy(x).to(_dev())
+    cap = fsz.fsz_compressed_bound(n)
+    out = torch.zeros(cap, dtype=torch.uint8, device=_dev())
+    y = torch.zeros(n, dtype=torch.float32, device=_dev())
+    stats = torch.zeros(4, dtype=torch.int32, device=_dev())
+    r1 = torch.zeros(4, dtype=torch.int32, device=_dev())
+    r2 = torch.zeros(4, dtype=torch.int32, device=_dev())
+    assert fsz.fsz_field_stats(xd.data_ptr(), n, stats.data_ptr(), _stream()) == fsz.FSZ_OK
+    for rel in (1e-2, 1e-3, 1e-4):
+        announce(f"grf-512^3 REL {rel:g}")
+        assert fsz.fsz_compress_async(xd.data_ptr(), n, fsz.FSZ_REL, rel, stats.data_ptr(), out.data_ptr(),
+                                      cap, r1.data_ptr(), _stream()) == fsz.FSZ_OK
+        assert fsz.fsz_decompress_async(out.data_ptr(), cap, y.data_ptr(), n, r2.data_ptr(),
+                                        _stream()) == fsz.FSZ_OK
+        size, st, _ = fsz.read_result(r1)
+        assert st == fsz.FSZ_OK
+        assert fsz.read_result(r2)[1] == fsz.FSZ_OK
+        ref = oracle.compress(x, oracle.REL, rel)
+        got = out[:size].cpu().numpy().tobytes()
+        assert got == ref, f"REL {rel}: {first_diff(got, ref)}"
+        y_ref = oracle.decompress(ref, n)
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), y_ref.view(np.uint32))
+
+
 # ----------------------------------------------------------------- ragged / edge sizes
 
 
