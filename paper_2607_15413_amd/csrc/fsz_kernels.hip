@@ -1870,10 +1870,59 @@ __global__ __launch_bounds__(kStatsThreads) void batch_stats_final_kernel(BatchA
     if (threadIdx.x == 0) b.stats[blockIdx.x] = fsz_stats{p.xmin, p.xmax, p.maxabs, p.flags};
 }
 
-// Batched kernel: one (job, chunk) work item per workgroup, items taken from
-// one ticket counter in job order, so every lookback waits only on chunks of
-// its own job that are already running.  A chunk runs exactly the code of
-// the plain kernels, hence the same output bytes.
+// The arguments of job J's chunks, as the whole-field kernels take them.
+__device__ __forceinline__ CompressArgs batch_compress_args(const BatchArgs &b, uint32_t job, const BatchJob &J)
+{
+    CompressArgs a;
+    a.x = static_cast<const float *>(J.src);
+    a.n = J.n;
+    a.ntiles = J.ntiles;
+    a.nblocks = J.nblocks;
+    a.nchunks = J.nchunks;
+    a.data0 = J.data0;
+    a.out = static_cast<uint8_t *>(J.dst);
+    a.capacity = J.dst_capacity;
+    a.stats = b.stats + job;
+    a.value = J.value;
+    a.mode = J.mode;
+    a.features = kFeaturesAll;
+    a.epoch = b.epoch;
+    a.flag_epoch = 1;
+    a.flags = b.flags + J.chunk_base;
+    a.ticket = nullptr;
+    a.final = J.final;
+    return a;
+}
+
+__device__ __forceinline__ DecompressArgs batch_decompress_args(const BatchArgs &b, const BatchJob &J)
+{
+    DecompressArgs a;
+    a.cmp = static_cast<const uint8_t *>(J.src);
+    a.cmp_size = J.src_size;
+    a.out = static_cast<float *>(J.dst);
+    a.n = J.n;
+    a.ntiles = J.ntiles;
+    a.nblocks = J.nblocks;
+    a.nchunks = J.nchunks;
+    a.data0 = J.data0;
+    a.tile_begin = 0;
+    a.tile_end = J.ntiles;
+    a.elem_begin = 0;
+    a.elem_end = J.n;
+    a.range_base = nullptr;
+    a.epoch = b.epoch;
+    a.flag_epoch = 1;
+    a.flags = b.flags + J.chunk_base;
+    a.ticket = nullptr;
+    a.final = J.final;
+    return a;
+}
+
+// Batched kernel: one (job, chunk) item per workgroup, items from one ticket
+// counter in job order, so every lookback waits only on items already
+// running, and lookback chains stay per job (each job has its own flag
+// range).  The item runs the whole-field per-chunk code, so every job's bytes
+// equal a plain call's.
 template <bool ALIGNED, int W>
 __global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
 {
@@ -1894,45 +1943,9 @@ __global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
     const BatchJob &J = b.jobs[job];
     const uint64_t chunk = t - J.chunk_base;
     if (J.op == FSZ_OP_COMPRESS) {
-        CompressArgs a;
-        a.x = static_cast<const float *>(J.src);
-        a.n = J.n;
-        a.ntiles = J.ntiles;
-        a.nblocks = J.nblocks;
-        a.nchunks = J.nchunks;
-        a.data0 = J.data0;
-        a.out = static_cast<uint8_t *>(J.dst);
-        a.capacity = J.dst_capacity;
-        a.stats = b.stats + job;
-        a.value = J.value;
-        a.mode = J.mode;
-        a.features = kFeaturesAll;
-        a.epoch = b.epoch;
-        a.flag_epoch = 1;
-        a.flags = b.flags + J.chunk_base;
-        a.ticket = nullptr;
-        a.final = J.final;
-        compress_chunk<ALIGNED, true, true, W>(a, chunk, sh.c, st);
+        compress_chunk<ALIGNED, true, true, W>(batch_compress_args(b, job, J), chunk, sh.c, st);
     } else {
-        DecompressArgs a;
-        a.cmp = static_cast<const uint8_t *>(J.src);
-        a.cmp_size = J.src_size;
-        a.out = static_cast<float *>(J.dst);
-        a.n = J.n;
-        a.ntiles = J.ntiles;
-        a.nblocks = J.nblocks;
-        a.nchunks = J.nchunks;
-        a.data0 = J.data0;
-        a.tile_begin = 0;
-        a.tile_end = J.ntiles;
-        a.elem_begin = 0;
-        a.elem_end = J.n;
-        a.range_base = nullptr;
-        a.epoch = b.epoch;
-        a.flag_epoch = 1;
-        a.flags = b.flags + J.chunk_base;
-        a.ticket = nullptr;
-        a.final = J.final;
+        const DecompressArgs a = batch_decompress_args(b, J);
         float E;
         uint64_t total;
         bool indep;
@@ -1943,6 +1956,64 @@ __global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
         }
         const DecChunk dc = dec_sizes<W>(a, chunk, 0, sh.d);
         dec_decode<ALIGNED, true, W>(a, dc, 0, E, total, indep, st, sh.d);
+    }
+}
+
+// Batched decompression when every job decompresses: a persistent grid whose
+// workgroups take items from the ticket counter until one is past the end.
+// The size pass of the next item runs before this item's decode, so its
+// aggregate is out before any lookback waits on it (as in the whole-field
+// decoder); every item publishes its aggregate before its own lookback and
+// tickets are taken in increasing order, so the waits always drain.  Held to
+// 128 VGPRs (4 waves per SIMD), as the whole-field decoder.
+template <bool ALIGNED, int W>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void batch_dec_kernel(BatchArgs b)
+{
+    __shared__ DecompressShared<W> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t stage[W * kStageWaveDwords];
+    const int tid = threadIdx.x;
+    uint32_t *st = stage + (tid >> 6) * kStageWaveDwords;
+    const uint64_t takes = b.total_chunks + gridDim.x;
+    int tslot = 0;
+    uint64_t t = next_ticket(b.ticket, takes, sh, tslot);
+    bool have = false;  // dc holds the size pass of item t (slot `slot`)
+    DecChunk dc;
+    int slot = 0;
+    while (t < b.total_chunks) {
+        const uint32_t job = __builtin_amdgcn_readfirstlane(find_job(b.chunk_end, b.njobs, t));
+        const DecompressArgs a = batch_decompress_args(b, b.jobs[job]);
+        const uint64_t chunk = t - b.jobs[job].chunk_base;
+        const uint64_t nxt = next_ticket(b.ticket, takes, sh, tslot);
+        float E;
+        uint64_t total;
+        bool indep;
+        const int hst = dec_header(a, E, total, indep);
+        if (hst != FSZ_OK) {
+            if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, hst, a.epoch);
+            have = false;
+        } else {
+            if (!have) dc = dec_sizes<W>(a, chunk, slot, sh);
+            bool next_have = false;
+            DecChunk dn;
+            if (nxt < b.total_chunks) {
+                const uint32_t job2 = __builtin_amdgcn_readfirstlane(find_job(b.chunk_end, b.njobs, nxt));
+                const DecompressArgs a2 = batch_decompress_args(b, b.jobs[job2]);
+                float E2;
+                uint64_t total2;
+                bool indep2;
+                if (dec_header(a2, E2, total2, indep2) == FSZ_OK) {
+                    dn = dec_sizes<W>(a2, nxt - b.jobs[job2].chunk_base, slot ^ 1, sh);
+                    next_have = true;
+                }
+            }
+            dec_decode<ALIGNED, true, W>(a, dc, slot, E, total, indep, st, sh);
+            if (next_have) {
+                dc = dn;
+                slot ^= 1;
+            }
+            have = next_have;
+        }
+        t = nxt;
     }
 }
 
@@ -2129,11 +2200,28 @@ static bool batch_lds_pad(K kernel, int groups, size_t *pad)
 }
 
 template <bool ALIGNED, int W>
-static hipError_t launch_batch_t(const BatchArgs &b, int groups, hipStream_t s)
+static hipError_t launch_batch_t(const BatchArgs &b, bool any_compress, int groups, hipStream_t s)
 {
     size_t pad = 0;
-    if (!batch_lds_pad(batch_kernel<ALIGNED, W>, groups, &pad)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((batch_kernel<ALIGNED, W>), dim3((unsigned)b.total_chunks), dim3(W * 64), pad, s, b);
+    if (any_compress) {
+        if (!batch_lds_pad(batch_kernel<ALIGNED, W>, groups, &pad)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((batch_kernel<ALIGNED, W>), dim3((unsigned)b.total_chunks), dim3(W * 64), pad, s, b);
+        return hipGetLastError();
+    }
+    // decompression only: persistent, as many workgroups as fit at this shape
+    if (!batch_lds_pad(batch_dec_kernel<ALIGNED, W>, groups, &pad)) return hipErrorInvalidValue;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_dec_kernel<ALIGNED, W>, W * 64, pad) !=
+            hipSuccess ||
+        cus <= 0 || per_cu <= 0) {
+        cus = 256;
+        per_cu = 1;
+    }
+    const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
+    const unsigned grid = (unsigned)(b.total_chunks < g ? b.total_chunks : g);
+    hipLaunchKernelGGL((batch_dec_kernel<ALIGNED, W>), dim3(grid), dim3(W * 64), pad, s, b);
     return hipGetLastError();
 }
 
@@ -2166,12 +2254,12 @@ hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, c
     if (e != hipSuccess) return e;
     if (b.total_chunks == 0) return hipSuccess;
     switch (shape.waves) {
-    case 2: return aligned16 ? launch_batch_t<true, 2>(b, shape.groups_per_cu, s)
-                             : launch_batch_t<false, 2>(b, shape.groups_per_cu, s);
-    case 4: return aligned16 ? launch_batch_t<true, 4>(b, shape.groups_per_cu, s)
-                             : launch_batch_t<false, 4>(b, shape.groups_per_cu, s);
-    case 8: return aligned16 ? launch_batch_t<true, 8>(b, shape.groups_per_cu, s)
-                             : launch_batch_t<false, 8>(b, shape.groups_per_cu, s);
+    case 2: return aligned16 ? launch_batch_t<true, 2>(b, any_compress, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 2>(b, any_compress, shape.groups_per_cu, s);
+    case 4: return aligned16 ? launch_batch_t<true, 4>(b, any_compress, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 4>(b, any_compress, shape.groups_per_cu, s);
+    case 8: return aligned16 ? launch_batch_t<true, 8>(b, any_compress, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 8>(b, any_compress, shape.groups_per_cu, s);
     default: return hipErrorInvalidValue;
     }
 }

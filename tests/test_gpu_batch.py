@@ -235,6 +235,36 @@ def test_batch_per_job_errors_are_isolated():
     check_against_oracle(b, refs, "errors")
 
 
+def test_batch_decompress_only_persistent():
+    """A batch whose every job decompresses runs the persistent decoder (the
+    next item's size pass ahead of this item's decode): good streams of many
+    sizes interleaved with bad ones (corrupt rate byte, bad magic, element
+    count mismatch, empty field), at every shape and with unaligned pointers."""
+    rng = np.random.default_rng(12)
+    specs = []
+    for k in range(40):
+        n = int(rng.choice([0, 1, 255, 257, 16384, 16385, 70_000, 300_001]))
+        x = workloads.sinusoid_field(n, 700 + k)
+        _, data = oracle.compress_status(x, fsz.FSZ_REL, [1e-2, 1e-3, 1e-4][k % 3])
+        if k % 7 == 3 and n > 300:
+            bad = bytearray(data)
+            bad[32 + 8 * (n // 512)] |= 0x20  # reserved bit in a middle tile
+            data = bytes(bad)
+        elif k % 7 == 5:
+            bad = bytearray(data)
+            bad[0] = ord("G")  # magic
+            data = bytes(bad)
+        specs.append(("d", data, n + 1 if k % 11 == 6 else n))
+    refs = oracle_refs(specs)
+    assert {r[0] for r in refs} >= {fsz.FSZ_OK, fsz.FSZ_ERR_CORRUPT, fsz.FSZ_ERR_SIZE_MISMATCH}
+    for shape in [None, (2, 0), (4, 0), (8, 0), (8, 1)]:
+        for offset in (0, 1):
+            announce(f"batch decompress-only 40 jobs shape {shape} offset {offset}")
+            b = DeviceBatch(specs, offset=offset)
+            b.run(shape)
+            check_against_oracle(b, refs, f"decompress-only shape {shape} offset {offset}")
+
+
 def test_plan_graph_replays():
     fields = small_fields(16, 9)
     specs = [("c", f.data, fsz.FSZ_REL, f.rel) for f in fields]
