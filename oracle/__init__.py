@@ -29,6 +29,10 @@ FEAT_CENTERING = 2
 FEAT_LZ2 = 4
 FEATURES_ALL = 7
 
+# tile configurations (Sec. VI-C, Table V): block size B, blocks per tile T
+DEFAULT_CONFIG = (32, 8)
+CONFIGS = [(32, 4), (32, 8), (32, 16), (64, 4), (64, 8), (64, 16)]
+
 _lib = None
 
 
@@ -57,6 +61,14 @@ def _load():
         lib.fszo_compress_features.restype = ctypes.c_int
         lib.fszo_tile_eval_features.argtypes = [p, ctypes.c_int, ctypes.c_float, ctypes.c_uint32, p, p, p, p, p]
         lib.fszo_tile_eval_features.restype = ctypes.c_int
+        lib.fszo_bound_config.argtypes = [u64, ctypes.c_int, ctypes.c_int]
+        lib.fszo_bound_config.restype = u64
+        lib.fszo_compress_config.argtypes = [p, u64, ctypes.c_int, ctypes.c_double, ctypes.c_uint32,
+                                             ctypes.c_int, ctypes.c_int, p, u64, p]
+        lib.fszo_compress_config.restype = ctypes.c_int
+        lib.fszo_tile_eval_config.argtypes = [p, ctypes.c_int, ctypes.c_float, ctypes.c_uint32, ctypes.c_int,
+                                              ctypes.c_int, p, p, p, p, p]
+        lib.fszo_tile_eval_config.restype = ctypes.c_int
         lib.fszo_decompress.argtypes = [p, u64, p, u64]
         lib.fszo_decompress.restype = ctypes.c_int
         _lib = lib
@@ -71,6 +83,10 @@ def bound(n: int) -> int:
     return int(_load().fszo_bound(n))
 
 
+def bound_config(n: int, block: int, tile_blocks: int) -> int:
+    return int(_load().fszo_bound_config(n, block, tile_blocks))
+
+
 def resolve(x, mode: int, value: float):
     """Return (status, E, inv, flags)."""
     x = _f32(x)
@@ -82,13 +98,19 @@ def resolve(x, mode: int, value: float):
     return st, E.value, inv.value, flags.value
 
 
-def compress_status(x, mode: int, value: float, capacity=None, features: int = FEATURES_ALL):
-    """Return (status, stream bytes or None)."""
+def compress_status(x, mode: int, value: float, capacity=None, features: int = FEATURES_ALL,
+                    config=DEFAULT_CONFIG):
+    """Return (status, stream bytes or None).  config = (B, T)."""
     x = _f32(x)
-    cap = bound(x.size) if capacity is None else capacity
+    B, T = config
+    cap = (bound(x.size) if config == DEFAULT_CONFIG else bound_config(x.size, B, T)) \
+        if capacity is None else capacity
     out = np.zeros(max(cap, 1), dtype=np.uint8)
     size = ctypes.c_uint64()
-    if features == FEATURES_ALL:
+    if tuple(config) != DEFAULT_CONFIG:
+        st = _load().fszo_compress_config(x.ctypes.data, x.size, mode, value, features, B, T,
+                                          out.ctypes.data, cap, ctypes.byref(size))
+    elif features == FEATURES_ALL:
         st = _load().fszo_compress(x.ctypes.data, x.size, mode, value, out.ctypes.data, cap,
                                    ctypes.byref(size))
     else:
@@ -99,8 +121,8 @@ def compress_status(x, mode: int, value: float, capacity=None, features: int = F
     return st, out[: size.value].tobytes()
 
 
-def compress(x, mode: int, value: float, features: int = FEATURES_ALL) -> bytes:
-    st, s = compress_status(x, mode, value, features=features)
+def compress(x, mode: int, value: float, features: int = FEATURES_ALL, config=DEFAULT_CONFIG) -> bytes:
+    st, s = compress_status(x, mode, value, features=features, config=config)
     if st != OK:
         raise OracleError(st, "compress")
     return s
@@ -160,4 +182,21 @@ def tile_eval_features(x, inv: float, features: int):
                                          ctypes.byref(best))
     if st != OK:
         raise OracleError(st, "tile_eval_features")
+    return mu.value, bool(ok.value), cost, rates, best.value
+
+
+def tile_eval_config(x, inv: float, features: int, block: int, tile_blocks: int):
+    """Evaluation of one tile of a (B, T) configuration:
+    (mu, centre_ok, cost[4], rates[4][T], selected variant)."""
+    x = _f32(x)
+    mu = ctypes.c_int32()
+    ok = ctypes.c_int()
+    best = ctypes.c_int()
+    cost = np.zeros(4, dtype=np.uint32)
+    rates = np.zeros((4, tile_blocks), dtype=np.uint32)
+    st = _load().fszo_tile_eval_config(x.ctypes.data, x.size, inv, features, block, tile_blocks,
+                                       ctypes.byref(mu), ctypes.byref(ok), cost.ctypes.data, rates.ctypes.data,
+                                       ctypes.byref(best))
+    if st != OK:
+        raise OracleError(st, "tile_eval_config")
     return mu.value, bool(ok.value), cost, rates, best.value

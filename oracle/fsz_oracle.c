@@ -50,6 +50,16 @@
  * Centering with independent blocks subtracts the tile mean from every
  * value, which changes the first residual of every block (and the second
  * one under LZ2).
+ *
+ * Tile configurations (Sec. VI-C, Table V): the block size B (32 or 64
+ * elements) and the blocks per tile T (4, 8 or 16) are stream parameters,
+ * recorded in header flags bits 2-4 (bit 2: B = 64; bits 3-4: 0 for T = 8,
+ * 1 for T = 4, 2 for T = 16), so the default B = 32, T = 8 keeps those bits
+ * zero.  A block of 64 elements encodes each bit plane (and the sign map) as
+ * one 64-bit word, element i at bit 63 - i, written most-significant byte
+ * first; its cost is 8 + 8r bytes for rate r > 0.  The tile mean is the
+ * pairwise sum of the B*T slots times 1/(B*T), and the prediction state
+ * restarts at every tile start as before.
  */
 #include "fsz_oracle.h"
 
@@ -58,10 +68,14 @@
 #include <stdlib.h>
 #include <string.h>
 
+#define MAX_BLOCK 64
+#define MAX_BLOCKS_PER_TILE 16
+#define MAX_TILE (MAX_BLOCK * MAX_BLOCKS_PER_TILE)
+#define HEADER_BYTES 32
+
+/* the default tile configuration */
 #define BLOCK 32
 #define BLOCKS_PER_TILE 8
-#define TILE (BLOCK * BLOCKS_PER_TILE)
-#define HEADER_BYTES 32
 
 /* ------------------------------------------------------------------ */
 /* small helpers                                                       */
@@ -81,8 +95,23 @@ static uint32_t rate_of(uint32_t v)
     return r;
 }
 
-/* block cost, Eq. (3): nothing for a zero-rate block, else sign map + planes */
-static uint32_t block_cost(uint32_t r) { return r == 0 ? 0 : 4 + 4 * r; }
+/* block cost, Eq. (3): nothing for a zero-rate block, else sign map + r
+ * planes of B bits each */
+static uint32_t block_cost(uint32_t r, int B) { return r == 0 ? 0 : (uint32_t)(B / 8) * (1 + r); }
+
+/* whether (B, T) is a supported tile configuration */
+static int config_ok(int B, int T) { return (B == 32 || B == 64) && (T == 4 || T == 8 || T == 16); }
+
+/* header flags bits 2-4 of a configuration, and back (-1: reserved code) */
+static uint32_t config_flags(int B, int T) { return (B == 64 ? 4u : 0u) | (T == 4 ? 8u : T == 16 ? 16u : 0u); }
+static int config_from_flags(uint32_t flags, int *B, int *T)
+{
+    uint32_t tc = (flags >> 3) & 3u;
+    if (tc == 3) return -1;
+    *B = (flags & 4u) ? 64 : 32;
+    *T = tc == 0 ? 8 : tc == 1 ? 4 : 16;
+    return 0;
+}
 
 static uint32_t magnitude(int32_t v) { return v < 0 ? (uint32_t)0 - (uint32_t)v : (uint32_t)v; }
 
@@ -105,17 +134,16 @@ static uint64_t get_u64(const uint8_t *p)
     for (int k = 7; k >= 0; k--) v = (v << 8) | p[k];
     return v;
 }
-/* bit-shuffled words are stored most-significant byte first */
-static void put_word_msb_first(uint8_t *p, uint32_t w)
+/* bit-shuffled words of B = 32 or 64 bits are stored most-significant byte first */
+static void put_bits_msb_first(uint8_t *p, uint64_t w, int B)
 {
-    p[0] = (uint8_t)(w >> 24);
-    p[1] = (uint8_t)(w >> 16);
-    p[2] = (uint8_t)(w >> 8);
-    p[3] = (uint8_t)w;
+    for (int k = 0; k < B / 8; k++) p[k] = (uint8_t)(w >> (B - 8 - 8 * k));
 }
-static uint32_t get_word_msb_first(const uint8_t *p)
+static uint64_t get_bits_msb_first(const uint8_t *p, int B)
 {
-    return ((uint32_t)p[0] << 24) | ((uint32_t)p[1] << 16) | ((uint32_t)p[2] << 8) | (uint32_t)p[3];
+    uint64_t w = 0;
+    for (int k = 0; k < B / 8; k++) w = (w << 8) | p[k];
+    return w;
 }
 static float bits_to_float(uint32_t u)
 {
@@ -130,12 +158,15 @@ static uint32_t float_to_bits(float f)
     return u;
 }
 
-uint64_t fszo_bound(uint64_t n)
+uint64_t fszo_bound_config(uint64_t n, int B, int T)
 {
-    uint64_t nblocks = ceil_div(n, BLOCK);
-    uint64_t ntiles = ceil_div(n, TILE);
-    return HEADER_BYTES + pad16(nblocks) + 4 * ntiles + (4 + 4 * 31) * nblocks;
+    if (!config_ok(B, T)) return 0;
+    uint64_t nblocks = ceil_div(n, (uint64_t)B);
+    uint64_t ntiles = ceil_div(n, (uint64_t)B * T);
+    return HEADER_BYTES + pad16(nblocks) + 4 * ntiles + block_cost(31, B) * nblocks;
 }
+
+uint64_t fszo_bound(uint64_t n) { return fszo_bound_config(n, BLOCK, BLOCKS_PER_TILE); }
 
 /* ------------------------------------------------------------------ */
 /* error-bound resolution (Sec. V-A and the binary32 reading above)    */
@@ -206,17 +237,18 @@ int fszo_resolve(const float *x, uint64_t n, int mode, double value,
 /* ------------------------------------------------------------------ */
 
 typedef struct {
+    int B, T;                       /* block size, blocks per tile */
     int indep;                      /* prediction restarts at every block */
     int m;                          /* valid elements in the tile */
     int nb;                         /* blocks in the tile */
-    int32_t q[TILE];                /* quantized values */
-    int32_t l1[TILE], l2[TILE];     /* LZ1 / LZ2 residuals, zero state at tile start */
+    int32_t q[MAX_TILE];            /* quantized values */
+    int32_t l1[MAX_TILE], l2[MAX_TILE]; /* LZ1 / LZ2 residuals, zero state at tile start */
     int32_t mu;                     /* quantized tile mean */
     int centre_ok;                  /* mean finite -> centered variants allowed */
     uint32_t cost[4];               /* C of LZ1, LZ2, LZ1c, LZ2c */
-    uint32_t vrate[4][BLOCKS_PER_TILE]; /* per-block rates of each variant */
+    uint32_t vrate[4][MAX_BLOCKS_PER_TILE]; /* per-block rates of each variant */
     int order2, centred;            /* selected variant */
-    uint32_t rate[BLOCKS_PER_TILE]; /* selected per-block rates */
+    uint32_t rate[MAX_BLOCKS_PER_TILE]; /* selected per-block rates */
     uint32_t bytes;                 /* selected tile cost C */
 } tile_t;
 
@@ -228,11 +260,14 @@ static int variant_allowed(int v, uint32_t features, int centre_ok)
     return 1;
 }
 
-static void analyse_tile(const float *x, int m, float inv, uint32_t features, tile_t *t)
+static void analyse_tile(const float *x, int m, float inv, uint32_t features, int B, int T, tile_t *t)
 {
+    const int TILE = B * T;
+    t->B = B;
+    t->T = T;
     t->indep = (features & FSZO_FEAT_CROSS_BLOCK) ? 0 : 1;
     t->m = m;
-    t->nb = (m + BLOCK - 1) / BLOCK;
+    t->nb = (m + B - 1) / B;
 
     /* Quantize + cross-block LZ1/LZ2 residuals in one loop (Sec. IV-A,
      * Eq. (2); Sec. IV-B items 1-2).  The predictor state runs across all
@@ -240,7 +275,7 @@ static void analyse_tile(const float *x, int m, float inv, uint32_t features, ti
      * independent blocks, Eq. (1), every block start has none). */
     int32_t qm1 = 0, qm2 = 0;
     for (int i = 0; i < TILE; i++) {
-        if (t->indep && i % BLOCK == 0) qm1 = qm2 = 0;
+        if (t->indep && i % B == 0) qm1 = qm2 = 0;
         if (i < m) {
             float y = x[i] * inv;
             int32_t q = (int32_t)rintf(y);
@@ -258,12 +293,13 @@ static void analyse_tile(const float *x, int m, float inv, uint32_t features, ti
     }
 
     /* Tile mean (Sec. IV-B item 3): index-order pairwise binary32 sum of
-     * the 256 slots, then divided by 256 and quantized. */
-    float s[TILE];
+     * the B*T slots (256 by default), then divided by B*T (a power of two,
+     * so the division is exact) and quantized. */
+    float s[MAX_TILE];
     for (int i = 0; i < TILE; i++) s[i] = i < m ? x[i] : 0.0f;
     for (int w = 1; w < TILE; w *= 2)
         for (int i = 0; i < TILE; i += 2 * w) s[i] = s[i] + s[i + w];
-    float mean_q = (s[0] * 0.00390625f) * inv;
+    float mean_q = (s[0] * (1.0f / (float)TILE)) * inv;
     t->centre_ok = isfinite(mean_q) ? 1 : 0;
     t->mu = t->centre_ok ? (int32_t)rintf(mean_q) : 0;
 
@@ -275,15 +311,15 @@ static void analyse_tile(const float *x, int m, float inv, uint32_t features, ti
      * first residuals: l[0] = q0 (or q0 - mu), LZ2 l[1] = q1 - 2 q0 (or
      * q1 - 2 q0 + mu), absent when the block holds fewer than 2 values. */
     for (int v = 0; v < 4; v++) t->cost[v] = (v >> 1) ? 4 : 0;
-    for (int b = 0; b < BLOCKS_PER_TILE; b++) {
+    for (int b = 0; b < T; b++) {
         if (b >= t->nb) {
             for (int v = 0; v < 4; v++) t->vrate[v][b] = 0;
             continue;
         }
         int restart = (b == 0 || t->indep);
-        int s0 = b * BLOCK;
+        int s0 = b * B;
         uint32_t a1 = 0, a2 = 0;
-        for (int i = s0; i < s0 + BLOCK; i++) {
+        for (int i = s0; i < s0 + B; i++) {
             uint32_t m1 = magnitude(t->l1[i]), m2 = magnitude(t->l2[i]);
             if (!restart || i >= s0 + 1) a1 = m1 > a1 ? m1 : a1;
             if (!restart || i >= s0 + 2) a2 = m2 > a2 ? m2 : a2;
@@ -292,7 +328,7 @@ static void analyse_tile(const float *x, int m, float inv, uint32_t features, ti
             int ord2 = v & 1, cen = v >> 1;
             uint32_t a = ord2 ? a2 : a1;
             if (restart) {
-                int mb = m - s0 < BLOCK ? m - s0 : BLOCK;
+                int mb = m - s0 < B ? m - s0 : B;
                 int32_t q0 = t->q[s0];
                 int32_t d1 = mb >= 2 ? t->l2[s0 + 1] : 0;
                 int32_t f0 = cen ? q0 - t->mu : q0;
@@ -301,7 +337,7 @@ static void analyse_tile(const float *x, int m, float inv, uint32_t features, ti
                 if (ord2 && magnitude(f1) > a) a = magnitude(f1);
             }
             t->vrate[v][b] = rate_of(a);
-            t->cost[v] += block_cost(t->vrate[v][b]);
+            t->cost[v] += block_cost(t->vrate[v][b], B);
         }
     }
 
@@ -314,23 +350,33 @@ static void analyse_tile(const float *x, int m, float inv, uint32_t features, ti
     t->order2 = best & 1;
     t->centred = best >> 1;
     t->bytes = t->cost[best];
-    for (int b = 0; b < BLOCKS_PER_TILE; b++) t->rate[b] = t->vrate[best][b];
+    for (int b = 0; b < T; b++) t->rate[b] = t->vrate[best][b];
+}
+
+int fszo_tile_eval_config(const float *x, int m, float inv, uint32_t features, int B, int T, int32_t *mu,
+                          int *centre_ok, uint32_t *cost4, uint32_t *rates, int *best)
+{
+    if (!config_ok(B, T) || m < 1 || m > B * T || (features & ~(uint32_t)FSZO_FEATURES_ALL))
+        return FSZO_ERR_INVALID_ARG;
+    tile_t *t = (tile_t *)malloc(sizeof(tile_t));
+    if (!t) return FSZO_ERR_INVALID_ARG;
+    analyse_tile(x, m, inv, features, B, T, t);
+    *best = t->order2 | (t->centred << 1);
+    *mu = t->mu;
+    *centre_ok = t->centre_ok;
+    for (int v = 0; v < 4; v++) {
+        cost4[v] = t->cost[v];
+        for (int b = 0; b < T; b++) rates[v * T + b] = t->vrate[v][b];
+    }
+    free(t);
+    return FSZO_OK;
 }
 
 int fszo_tile_eval_features(const float *x, int m, float inv, uint32_t features, int32_t *mu,
                             int *centre_ok, uint32_t *cost4, uint32_t *rates4x8, int *best)
 {
-    if (m < 1 || m > TILE || (features & ~(uint32_t)FSZO_FEATURES_ALL)) return FSZO_ERR_INVALID_ARG;
-    tile_t t;
-    analyse_tile(x, m, inv, features, &t);
-    *best = t.order2 | (t.centred << 1);
-    *mu = t.mu;
-    *centre_ok = t.centre_ok;
-    for (int v = 0; v < 4; v++) {
-        cost4[v] = t.cost[v];
-        for (int b = 0; b < BLOCKS_PER_TILE; b++) rates4x8[v * BLOCKS_PER_TILE + b] = t.vrate[v][b];
-    }
-    return FSZO_OK;
+    return fszo_tile_eval_config(x, m, inv, features, BLOCK, BLOCKS_PER_TILE, mu, centre_ok, cost4, rates4x8,
+                                 best);
 }
 
 int fszo_tile_eval(const float *x, int m, float inv, int32_t *mu, int *centre_ok,
@@ -346,74 +392,87 @@ static int32_t selected_residual(const tile_t *t, int i)
     if (i >= t->m) return 0;
     int32_t e = t->order2 ? t->l2[i] : t->l1[i];
     if (t->centred) {
-        int s0 = t->indep ? i / BLOCK * BLOCK : 0; /* start of the prediction run */
+        int s0 = t->indep ? i / t->B * t->B : 0; /* start of the prediction run */
         if (i == s0) e = t->q[i] - t->mu;
         else if (i == s0 + 1 && t->order2) e = t->l2[i] + t->mu;
     }
     return e;
 }
 
-/* Fixed-length encoding + bit-shuffle of one block (Sec. IV-C). */
+/* Fixed-length encoding + bit-shuffle of one block (Sec. IV-C): the sign
+ * map, then planes 0..r-1, each one B-bit word with element j at bit
+ * B - 1 - j. */
 static uint8_t *encode_block(const tile_t *t, int b, uint8_t *p)
 {
+    const int B = t->B;
     uint32_t r = t->rate[b];
     if (r == 0) return p;
-    uint32_t mag[BLOCK];
-    uint32_t sign = 0;
-    for (int j = 0; j < BLOCK; j++) {
-        int32_t e = selected_residual(t, b * BLOCK + j);
+    uint32_t mag[MAX_BLOCK];
+    uint64_t sign = 0;
+    for (int j = 0; j < B; j++) {
+        int32_t e = selected_residual(t, b * B + j);
         mag[j] = magnitude(e);
-        if (e < 0) sign |= 1u << (31 - j);
+        if (e < 0) sign |= 1ull << (B - 1 - j);
     }
-    put_word_msb_first(p, sign);
-    p += 4;
+    put_bits_msb_first(p, sign, B);
+    p += B / 8;
     for (uint32_t plane = 0; plane < r; plane++) {
-        uint32_t w = 0;
-        for (int j = 0; j < BLOCK; j++) w |= ((mag[j] >> plane) & 1u) << (31 - j);
-        put_word_msb_first(p, w);
-        p += 4;
+        uint64_t w = 0;
+        for (int j = 0; j < B; j++) w |= (uint64_t)((mag[j] >> plane) & 1u) << (B - 1 - j);
+        put_bits_msb_first(p, w, B);
+        p += B / 8;
     }
     return p;
 }
 
-int fszo_compress_features(const float *x, uint64_t n, int mode, double value, uint32_t features,
-                           uint8_t *out, uint64_t cap, uint64_t *out_size)
+int fszo_compress_config(const float *x, uint64_t n, int mode, double value, uint32_t features, int B, int T,
+                         uint8_t *out, uint64_t cap, uint64_t *out_size)
 {
-    if (features & ~(uint32_t)FSZO_FEATURES_ALL) return FSZO_ERR_INVALID_ARG;
+    if ((features & ~(uint32_t)FSZO_FEATURES_ALL) || !config_ok(B, T)) return FSZO_ERR_INVALID_ARG;
     float E, inv;
     uint32_t flags;
     int st = fszo_resolve(x, n, mode, value, &E, &inv, &flags);
     if (st != FSZO_OK) return st;
 
-    uint64_t nblocks = ceil_div(n, BLOCK);
+    const uint64_t TILE = (uint64_t)B * T;
+    uint64_t nblocks = ceil_div(n, (uint64_t)B);
     uint64_t ntiles = ceil_div(n, TILE);
     uint64_t data0 = HEADER_BYTES + pad16(nblocks);
 
-    /* Pass 1: per-tile analysis, rate header and tile sizes. */
-    tile_t *tiles = (tile_t *)malloc(sizeof(tile_t) * (ntiles ? ntiles : 1));
+    /* Pass 1: per-tile analysis -> rate bytes and tile sizes. */
+    tile_t *tl = (tile_t *)malloc(sizeof(tile_t));
+    uint8_t *rates = (uint8_t *)malloc(nblocks ? nblocks : 1);
     uint64_t *offset = (uint64_t *)malloc(sizeof(uint64_t) * (ntiles + 1));
-    if (!tiles || !offset) {
-        free(tiles);
+    if (!tl || !rates || !offset) {
+        free(tl);
+        free(rates);
         free(offset);
         return FSZO_ERR_INVALID_ARG;
     }
     for (uint64_t t = 0; t < ntiles; t++) {
         uint64_t start = t * TILE;
         int m = (int)(n - start < TILE ? n - start : TILE);
-        analyse_tile(x + start, m, inv, features, &tiles[t]);
+        analyse_tile(x + start, m, inv, features, B, T, tl);
+        for (int b = 0; b < tl->nb; b++) {
+            uint8_t byte = (uint8_t)tl->rate[b];
+            if (b == 0) byte |= (uint8_t)((tl->order2 << 7) | (tl->centred << 6)); /* Sec. III-A */
+            rates[t * (uint64_t)T + b] = byte;
+        }
+        offset[t + 1] = tl->bytes;
     }
 
     /* Pass 2: exclusive prefix sum of tile sizes (Sec. IV-D). */
     offset[0] = 0;
-    for (uint64_t t = 0; t < ntiles; t++) offset[t + 1] = offset[t] + tiles[t].bytes;
+    for (uint64_t t = 0; t < ntiles; t++) offset[t + 1] += offset[t];
     uint64_t total = data0 + offset[ntiles];
     if (total > cap) {
-        free(tiles);
+        free(tl);
+        free(rates);
         free(offset);
         return FSZO_ERR_CAPACITY;
     }
 
-    /* Header (32 bytes). */
+    /* Header (32 bytes), then the rate header: one byte per block. */
     memset(out, 0, data0);
     out[0] = 'F';
     out[1] = 'S';
@@ -421,25 +480,19 @@ int fszo_compress_features(const float *x, uint64_t n, int mode, double value, u
     out[3] = '1';
     put_u16(out + 4, 1);
     out[6] = (uint8_t)mode;
-    out[7] = (uint8_t)(flags | ((features & FSZO_FEAT_CROSS_BLOCK) ? 0u : 2u));
+    out[7] = (uint8_t)(flags | ((features & FSZO_FEAT_CROSS_BLOCK) ? 0u : 2u) | config_flags(B, T));
     put_u64(out + 8, n);
     put_u32(out + 16, float_to_bits(E));
     put_u32(out + 20, float_to_bits((float)value));
     put_u64(out + 24, total);
+    memcpy(out + HEADER_BYTES, rates, nblocks);
 
-    /* Rate header: one byte per block (Sec. III-A). */
+    /* Pass 3: encode every tile at its offset (the analysis is repeated,
+     * as the paper's encoder re-reads its input). */
     for (uint64_t t = 0; t < ntiles; t++) {
-        const tile_t *tl = &tiles[t];
-        for (int b = 0; b < tl->nb; b++) {
-            uint8_t byte = (uint8_t)tl->rate[b];
-            if (b == 0) byte |= (uint8_t)((tl->order2 << 7) | (tl->centred << 6));
-            out[HEADER_BYTES + t * BLOCKS_PER_TILE + b] = byte;
-        }
-    }
-
-    /* Pass 3: encode every tile at its offset. */
-    for (uint64_t t = 0; t < ntiles; t++) {
-        const tile_t *tl = &tiles[t];
+        uint64_t start = t * TILE;
+        int m = (int)(n - start < TILE ? n - start : TILE);
+        analyse_tile(x + start, m, inv, features, B, T, tl);
         uint8_t *p = out + data0 + offset[t];
         if (tl->centred) {
             put_u32(p, (uint32_t)tl->mu);
@@ -448,10 +501,17 @@ int fszo_compress_features(const float *x, uint64_t n, int mode, double value, u
         for (int b = 0; b < tl->nb; b++) p = encode_block(tl, b, p);
     }
 
-    free(tiles);
+    free(tl);
+    free(rates);
     free(offset);
     *out_size = total;
     return FSZO_OK;
+}
+
+int fszo_compress_features(const float *x, uint64_t n, int mode, double value, uint32_t features,
+                           uint8_t *out, uint64_t cap, uint64_t *out_size)
+{
+    return fszo_compress_config(x, n, mode, value, features, BLOCK, BLOCKS_PER_TILE, out, cap, out_size);
 }
 
 int fszo_compress(const float *x, uint64_t n, int mode, double value,
@@ -469,15 +529,18 @@ int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t 
     if (cmp_size < HEADER_BYTES) return FSZO_ERR_CORRUPT;
     if (cmp[0] != 'F' || cmp[1] != 'S' || cmp[2] != 'Z' || cmp[3] != '1') return FSZO_ERR_CORRUPT;
     if ((cmp[4] | (cmp[5] << 8)) != 1) return FSZO_ERR_CORRUPT;
-    if (cmp[6] > 1 || (cmp[7] & ~3u) != 0) return FSZO_ERR_CORRUPT;
+    if (cmp[6] > 1 || (cmp[7] & ~0x1Fu) != 0) return FSZO_ERR_CORRUPT;
     int indep = (cmp[7] >> 1) & 1; /* independent blocks: sums restart per block */
+    int B, T;
+    if (config_from_flags(cmp[7], &B, &T) != 0) return FSZO_ERR_CORRUPT;
+    const uint64_t TILE = (uint64_t)B * T;
     uint64_t hn = get_u64(cmp + 8);
     if (hn != n) return FSZO_ERR_SIZE_MISMATCH;
     float E = bits_to_float(get_u32(cmp + 16));
     if (!isfinite(E) || !(E > 0.0f)) return FSZO_ERR_CORRUPT;
     uint64_t total = get_u64(cmp + 24);
 
-    uint64_t nblocks = ceil_div(n, BLOCK);
+    uint64_t nblocks = ceil_div(n, (uint64_t)B);
     uint64_t ntiles = ceil_div(n, TILE);
     uint64_t data0 = HEADER_BYTES + pad16(nblocks);
     if (total > cmp_size || total < data0) return FSZO_ERR_CORRUPT;
@@ -490,16 +553,16 @@ int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t 
     if (!offset) return FSZO_ERR_INVALID_ARG;
     offset[0] = 0;
     for (uint64_t t = 0; t < ntiles; t++) {
-        uint64_t nb = nblocks - t * BLOCKS_PER_TILE;
-        if (nb > BLOCKS_PER_TILE) nb = BLOCKS_PER_TILE;
+        uint64_t nb = nblocks - t * T;
+        if (nb > (uint64_t)T) nb = T;
         uint64_t bytes = 0;
         for (uint64_t b = 0; b < nb; b++) {
-            uint8_t byte = rates[t * BLOCKS_PER_TILE + b];
+            uint8_t byte = rates[t * T + b];
             if (b == 0 ? (byte & 0x20) != 0 : (byte & 0xE0) != 0) {
                 free(offset);
                 return FSZO_ERR_CORRUPT;
             }
-            bytes += block_cost(byte & 0x1F);
+            bytes += block_cost(byte & 0x1F, B);
             if (b == 0 && (byte & 0x40)) bytes += 4;
         }
         offset[t + 1] = offset[t] + bytes;
@@ -513,8 +576,8 @@ int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t 
     for (uint64_t t = 0; t < ntiles; t++) {
         uint64_t start = t * TILE;
         int m = (int)(n - start < TILE ? n - start : TILE);
-        int nb = (m + BLOCK - 1) / BLOCK;
-        uint8_t head = rates[t * BLOCKS_PER_TILE];
+        int nb = (m + B - 1) / B;
+        uint8_t head = rates[t * T];
         int order2 = (head >> 7) & 1, centred = (head >> 6) & 1;
         const uint8_t *p = cmp + data0 + offset[t];
         int32_t mu = 0;
@@ -522,26 +585,26 @@ int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t 
             mu = (int32_t)get_u32(p);
             p += 4;
         }
-        uint32_t e[TILE];
+        uint32_t e[MAX_TILE];
         for (int b = 0; b < nb; b++) {
-            uint32_t r = rates[t * BLOCKS_PER_TILE + b] & 0x1F;
-            for (int j = 0; j < BLOCK; j++) e[b * BLOCK + j] = 0;
+            uint32_t r = rates[t * T + b] & 0x1F;
+            for (int j = 0; j < B; j++) e[b * B + j] = 0;
             if (r == 0) continue;
-            uint32_t sign = get_word_msb_first(p);
-            p += 4;
+            uint64_t sign = get_bits_msb_first(p, B);
+            p += B / 8;
             for (uint32_t plane = 0; plane < r; plane++) {
-                uint32_t w = get_word_msb_first(p);
-                p += 4;
-                for (int j = 0; j < BLOCK; j++) e[b * BLOCK + j] |= ((w >> (31 - j)) & 1u) << plane;
+                uint64_t w = get_bits_msb_first(p, B);
+                p += B / 8;
+                for (int j = 0; j < B; j++) e[b * B + j] |= (uint32_t)((w >> (B - 1 - j)) & 1u) << plane;
             }
-            for (int j = 0; j < BLOCK; j++)
-                if ((sign >> (31 - j)) & 1u) e[b * BLOCK + j] = (uint32_t)0 - e[b * BLOCK + j];
+            for (int j = 0; j < B; j++)
+                if ((sign >> (B - 1 - j)) & 1u) e[b * B + j] = (uint32_t)0 - e[b * B + j];
         }
         /* inverse Lorenzo: one running sum for LZ1, two for LZ2 (wrapping
          * 32-bit arithmetic, so corrupt streams cannot overflow) */
         uint32_t acc1 = 0, acc2 = 0;
         for (int i = 0; i < m; i++) {
-            if (indep && i % BLOCK == 0) acc1 = acc2 = 0;
+            if (indep && i % B == 0) acc1 = acc2 = 0;
             acc1 += e[i];
             uint32_t qhat;
             if (order2) {

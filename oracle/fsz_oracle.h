@@ -66,7 +66,20 @@ int fszo_tile_eval(const float *x, int m, float inv, int32_t *mu, int *centre_ok
 int fszo_tile_eval_features(const float *x, int m, float inv, uint32_t features, int32_t *mu,
                             int *centre_ok, uint32_t *cost4, uint32_t *rates4x8, int *best);
 
-/* Full decompression of a stream of cmp_size bytes into n floats. */
+/* Tile configurations (Sec. VI-C, Table V): block size B in {32, 64}
+ * elements, T in {4, 8, 16} blocks per tile; B = 32, T = 8 is the default
+ * and the only one the calls above produce.  The stream records B and T in
+ * header flags bits 2-4.  Invalid (B, T): FSZO_ERR_INVALID_ARG (bound: 0). */
+uint64_t fszo_bound_config(uint64_t n, int B, int T);
+int fszo_compress_config(const float *x, uint64_t n, int mode, double value, uint32_t features, int B, int T,
+                         uint8_t *out, uint64_t cap, uint64_t *out_size);
+/* Four-way evaluation of one tile of m (1..B*T) floats; rates holds 4 x T
+ * per-block rates (row per variant). */
+int fszo_tile_eval_config(const float *x, int m, float inv, uint32_t features, int B, int T, int32_t *mu,
+                          int *centre_ok, uint32_t *cost4, uint32_t *rates, int *best);
+
+/* Full decompression of a stream of cmp_size bytes into n floats (any tile
+ * configuration, read from the header). */
 int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t n);
 
 #ifdef __cplusplus

@@ -10,6 +10,11 @@ block (Sec. III-A) zero-padded to 16 bytes, then per 256-element tile its
 optional int32 mean and, per block with rate r > 0, a sign word and r
 bit-plane words, element j of the block at bit 31 - j, words written
 most-significant byte first (Sec. IV-C).
+
+Tile configurations (Sec. VI-C, Table V): every helper takes the block size
+B (32 or 64) and the blocks per tile T (4, 8, 16); header flags bits 2-4 hold
+them (bit 2: B = 64; bits 3-4: 0 -> T = 8, 1 -> T = 4, 2 -> T = 16).  A
+64-element block's sign map and planes are 64-bit big-endian words.
 """
 import struct
 
@@ -28,8 +33,20 @@ def pad16(a):
     return (a + 15) // 16 * 16
 
 
-def data_start(n):
-    return HEADER + pad16(ceil_div(n, BLOCK))
+def data_start(n, B=BLOCK):
+    return HEADER + pad16(ceil_div(n, B))
+
+
+def config_flags(B=BLOCK, T=8):
+    return (4 if B == 64 else 0) | {8: 0, 4: 8, 16: 16}[T]
+
+
+def header_config(flags):
+    """(B, T) from header flags, or None for the reserved T code."""
+    tc = (flags >> 3) & 3
+    if tc == 3:
+        return None
+    return (64 if flags & 4 else 32), {0: 8, 1: 4, 2: 16}[tc]
 
 
 def parse_header(s: bytes) -> dict:
@@ -38,32 +55,33 @@ def parse_header(s: bytes) -> dict:
                 total=total)
 
 
-def rate_bytes(s: bytes, n: int) -> np.ndarray:
-    return np.frombuffer(s, dtype=np.uint8, count=ceil_div(n, BLOCK), offset=HEADER)
+def rate_bytes(s: bytes, n: int, B=BLOCK) -> np.ndarray:
+    return np.frombuffer(s, dtype=np.uint8, count=ceil_div(n, B), offset=HEADER)
 
 
 def bitlen(v: int) -> int:
     return int(v).bit_length()
 
 
-def block_cost(r: int) -> int:
-    return 0 if r == 0 else 4 + 4 * r
+def block_cost(r: int, B=BLOCK) -> int:
+    """Sign map + r planes of B bits each (Eq. 3 for B = 32)."""
+    return 0 if r == 0 else (B // 8) * (1 + r)
 
 
-def tile_choices(s: bytes, n: int):
-    """Per tile: (order2, centred, [8 rates]) read from the rate header
+def tile_choices(s: bytes, n: int, B=BLOCK, T=8):
+    """Per tile: (order2, centred, [T rates]) read from the rate header
     (blocks past the end of a ragged last tile read as rate 0)."""
-    rb = rate_bytes(s, n)
+    rb = rate_bytes(s, n, B)
     out = []
-    for t in range(ceil_div(n, TILE)):
-        blk = rb[t * 8:(t + 1) * 8]
-        rates = [int(b) & 0x1F for b in blk] + [0] * (8 - blk.size)
+    for t in range(ceil_div(n, B * T)):
+        blk = rb[t * T:(t + 1) * T]
+        rates = [int(b) & 0x1F for b in blk] + [0] * (T - blk.size)
         out.append((int(blk[0] >> 7) & 1, int(blk[0] >> 6) & 1, rates))
     return out
 
 
-def tile_sizes(s: bytes, n: int):
-    return [sum(block_cost(r) for r in rates) + 4 * c for (_, c, rates) in tile_choices(s, n)]
+def tile_sizes(s: bytes, n: int, B=BLOCK, T=8):
+    return [sum(block_cost(r, B) for r in rates) + 4 * c for (_, c, rates) in tile_choices(s, n, B, T)]
 
 
 def quantize(x: np.ndarray, inv: float) -> np.ndarray:
@@ -78,26 +96,27 @@ def closed_form(x: np.ndarray, E: float, inv: float) -> np.ndarray:
     return (q.astype(np.float32) * np.float32(E)).astype(np.float32)
 
 
-def pairwise_mean(xt: np.ndarray, inv: float):
-    """(finite, mu): index-order pairwise binary32 sum of 256 slots (+0 padded)."""
-    s = np.zeros(TILE, dtype=np.float32)
+def pairwise_mean(xt: np.ndarray, inv: float, tile=TILE):
+    """(finite, mu): index-order pairwise binary32 sum of `tile` slots (+0
+    padded), times 1/tile (exact: a power of two)."""
+    s = np.zeros(tile, dtype=np.float32)
     s[:xt.size] = xt
     with np.errstate(over="ignore", invalid="ignore"):
         while s.size > 1:
             s = (s[0::2] + s[1::2]).astype(np.float32)
-        v = np.float32(np.float32(s[0] * np.float32(0.00390625)) * np.float32(inv))
+        v = np.float32(np.float32(s[0] * np.float32(1.0 / tile)) * np.float32(inv))
     if not np.isfinite(v):
         return False, 0
     return True, int(np.rint(v))
 
 
-def residuals(q: np.ndarray, order2: int, mu: int, independent: bool = False) -> np.ndarray:
+def residuals(q: np.ndarray, order2: int, mu: int, independent: bool = False, B=BLOCK) -> np.ndarray:
     """Lorenzo residuals of q - mu with zero state before the tile start
     (independent: before every block start)."""
     qc = np.asarray(q, dtype=np.int64) - mu
     if independent:
-        return np.concatenate([residuals(qc[b:b + BLOCK], order2, 0)
-                               for b in range(0, qc.size, BLOCK)]).astype(np.int64)
+        return np.concatenate([residuals(qc[b:b + B], order2, 0)
+                               for b in range(0, qc.size, B)]).astype(np.int64)
     p1 = np.concatenate([[0], qc[:-1]])
     if not order2:
         return qc - p1
@@ -117,22 +136,22 @@ def allowed(v: int, features: int, centre_ok: bool) -> bool:
     return True
 
 
-def brute_force_tile(xt: np.ndarray, inv: float, features: int = ALL):
-    """Four separate full passes; returns (mu, centre_ok, costs[4], rates[4][8], best)."""
+def brute_force_tile(xt: np.ndarray, inv: float, features: int = ALL, B=BLOCK, T=8):
+    """Four separate full passes; returns (mu, centre_ok, costs[4], rates[4][T], best)."""
     m = xt.size
-    nb = ceil_div(m, BLOCK)
+    nb = ceil_div(m, B)
     q = quantize(xt, inv)
-    ok, mu = pairwise_mean(xt, inv)
+    ok, mu = pairwise_mean(xt, inv, B * T)
     indep = not features & CROSS_BLOCK
     costs, rates = [], []
     for v in range(4):
         order2, cen = v & 1, v >> 1
-        res = np.zeros(TILE, dtype=np.int64)
-        res[:m] = residuals(q, order2, mu if cen else 0, indep)
-        rv = [bitlen(int(np.abs(res[b * BLOCK:(b + 1) * BLOCK]).max())) if b < nb else 0
-              for b in range(8)]
+        res = np.zeros(B * T, dtype=np.int64)
+        res[:m] = residuals(q, order2, mu if cen else 0, indep, B)
+        rv = [bitlen(int(np.abs(res[b * B:(b + 1) * B]).max())) if b < nb else 0
+              for b in range(T)]
         rates.append(rv)
-        costs.append(sum(block_cost(r) for r in rv) + (4 if cen else 0))
+        costs.append(sum(block_cost(r, B) for r in rv) + (4 if cen else 0))
     best = 0
     for v in (1, 2, 3):
         if allowed(v, features, ok) and costs[v] < costs[best]:
@@ -140,48 +159,51 @@ def brute_force_tile(xt: np.ndarray, inv: float, features: int = ALL):
     return mu, ok, costs, rates, best
 
 
-def _word_bytes(w: int) -> bytes:
-    return struct.pack(">I", w)
+def _word_bytes(w: int, B=BLOCK) -> bytes:
+    return struct.pack(">I" if B == 32 else ">Q", w)
 
 
 def encode_stream(x: np.ndarray, E: float, inv: float, mode: int, value: float, flags: int,
-                  choices) -> bytes:
+                  choices, B=BLOCK, T=8) -> bytes:
     """Encode x with the given per-tile (order2, centred, mu) choices
-    (flags bit 1: independent blocks)."""
+    (flags bit 1: independent blocks; the configuration bits of (B, T) are
+    added here)."""
     x = np.asarray(x, dtype=np.float32).reshape(-1)
     n = x.size
     q = quantize(x, inv)
-    nblocks = ceil_div(n, BLOCK)
+    nblocks = ceil_div(n, B)
+    tile = B * T
+    flags |= config_flags(B, T)
     rate_hdr = bytearray(pad16(nblocks))
     body = bytearray()
-    for t in range(ceil_div(n, TILE)):
-        qt = q[t * TILE:(t + 1) * TILE]
+    for t in range(ceil_div(n, tile)):
+        qt = q[t * tile:(t + 1) * tile]
         m = qt.size
         order2, cen, mu = choices[t]
-        res = np.zeros(TILE, dtype=np.int64)
-        res[:m] = residuals(qt, order2, mu if cen else 0, bool(flags & 2))
+        res = np.zeros(tile, dtype=np.int64)
+        res[:m] = residuals(qt, order2, mu if cen else 0, bool(flags & 2), B)
         if cen:
             body += struct.pack("<i", mu)
-        for b in range(ceil_div(m, BLOCK)):
-            blk = res[b * BLOCK:(b + 1) * BLOCK]
+        for b in range(ceil_div(m, B)):
+            blk = res[b * B:(b + 1) * B]
             r = bitlen(int(np.abs(blk).max()))
             byte = r
             if b == 0:
                 byte |= (order2 << 7) | (cen << 6)
-            rate_hdr[t * 8 + b] = byte
+            rate_hdr[t * T + b] = byte
             if r == 0:
                 continue
             sign = 0
-            for j in range(BLOCK):
+            for j in range(B):
                 if blk[j] < 0:
-                    sign |= 1 << (31 - j)
-            body += _word_bytes(sign)
+                    sign |= 1 << (B - 1 - j)
+            body += _word_bytes(sign, B)
             mag = np.abs(blk)
             for p in range(r):
                 w = 0
-                for j in range(BLOCK):
-                    w |= ((int(mag[j]) >> p) & 1) << (31 - j)
-                body += _word_bytes(w)
+                for j in range(B):
+                    w |= ((int(mag[j]) >> p) & 1) << (B - 1 - j)
+                body += _word_bytes(w, B)
     total = HEADER + len(rate_hdr) + len(body)
     hdr = struct.pack("<4sHBBQffQ", b"FSZ1", 1, mode, flags, n, E, value, total)
     return bytes(hdr) + bytes(rate_hdr) + bytes(body)

@@ -383,7 +383,8 @@ def _mutations(s, n):
     yield "magic", m(lambda c: c.__setitem__(0, ord("G"))), oracle.ERR_CORRUPT
     yield "version", m(lambda c: c.__setitem__(4, 2)), oracle.ERR_CORRUPT
     yield "mode", m(lambda c: c.__setitem__(6, 2)), oracle.ERR_CORRUPT
-    yield "flags", m(lambda c: c.__setitem__(7, 4)), oracle.ERR_CORRUPT
+    yield "flags", m(lambda c: c.__setitem__(7, 0x20)), oracle.ERR_CORRUPT
+    yield "tile code", m(lambda c: c.__setitem__(7, 0x18)), oracle.ERR_CORRUPT
     yield "n", m(lambda c: struct.pack_into("<Q", c, 8, n + 1)), oracle.ERR_SIZE_MISMATCH
     yield "E nan", m(lambda c: struct.pack_into("<f", c, 16, float("nan"))), oracle.ERR_CORRUPT
     yield "E zero", m(lambda c: struct.pack_into("<f", c, 16, 0.0)), oracle.ERR_CORRUPT
