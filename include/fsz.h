@@ -189,6 +189,45 @@ fsz_status fsz_compress_five_read_async(const float *d_in, size_t n, fsz_eb_mode
                                         fsz_result *d_result, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Tile configurations (the sweep of Sec. VI-C, Table V): block size
+ * `block` in {32, 64} elements and `tile_blocks` in {4, 8, 16} blocks per
+ * tile (a tile of block * tile_blocks elements).  32 / 8 is the default, the
+ * only configuration the other entry points use.  The full method (all three
+ * features) with the tile geometry changed:
+ *   - one rate byte per block; the cross-block prediction chain, the tile
+ *     mean (pairwise binary32 sum of the block * tile_blocks slots times
+ *     1 / (block * tile_blocks)) and the four-way selection span the tile;
+ *   - a 64-element block stores its sign map and each bit plane as one
+ *     64-bit word, element i at bit 63 - i, most-significant byte first
+ *     (block cost 8 + 8r bytes for rate r > 0);
+ *   - the stream header records the configuration in flags bits 2-4 (bit 2:
+ *     block 64; bits 3-4: 0 for 8 blocks per tile, 1 for 4, 2 for 16), which
+ *     are zero for 32 / 8, so the default configuration gives exactly the
+ *     stream of fsz_compress_async.
+ * The reconstruction x' = q E does not depend on the configuration.  These
+ * calls run the generic kernels (a lane per 32 elements, one chunk of 8192
+ * elements per workgroup) for every configuration, 32 / 8 included.
+ *
+ * fsz_compressed_bound_config: worst-case stream size (every block at rate
+ *   31); 0 for an unsupported configuration.
+ * fsz_compress_config_async: arguments, ownership and errors as
+ *   fsz_compress_async, plus FSZ_ERR_INVALID_ARG for an unsupported
+ *   configuration; FSZ_ERR_CAPACITY for out_capacity below the header and
+ *   rate bytes (32 + ceil(n / block) rounded up to 16).
+ * fsz_decompress_config_async: decodes a stream of that configuration;
+ *   arguments and errors as fsz_decompress_async.  A stream whose header
+ *   names another configuration is FSZ_ERR_CORRUPT, as is a configuration
+ *   stream handed to fsz_decompress / fsz_decompress_async. */
+size_t fsz_compressed_bound_config(size_t n, int block, int tile_blocks);
+
+fsz_status fsz_compress_config_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                                     const fsz_stats *d_stats, int block, int tile_blocks, void *d_out,
+                                     size_t out_capacity, fsz_result *d_result, void *stream);
+
+fsz_status fsz_decompress_config_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n, int block,
+                                       int tile_blocks, fsz_result *d_result, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: many fields of uneven sizes in one launch.
  *
  * Every job produces exactly the bytes (compress) or floats (decompress)

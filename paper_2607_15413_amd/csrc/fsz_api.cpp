@@ -300,6 +300,67 @@ fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_siz
     return FSZ_OK;
 }
 
+// Tile configurations (Sec. VI-C, Table V): the generic lane-per-segment
+// kernels, one chunk of kCfgChunkSegs 32-element segments per workgroup.
+fsz_status enqueue_compress_config(Workspace *ws, const float *d_in, uint64_t n, int mode, double value,
+                                   const fsz_stats *d_stats, int block, int tile_blocks, void *d_out, uint64_t cap,
+                                   fsz_result *d_final)
+{
+    if (!d_stats) {
+        StatsArgs sa{d_in, n, ws->d_stats, ws->d_partials};
+        if (!ok(launch_stats(sa, ws->stream))) return FSZ_ERR_DEVICE;
+        d_stats = ws->d_stats;
+    }
+    CompressArgs a{};
+    a.x = d_in;
+    a.n = n;
+    a.ntiles = ceil_div(n, (uint64_t)block * tile_blocks);
+    a.nblocks = ceil_div(n, (uint64_t)block);
+    a.nchunks = n ? ceil_div(ceil_div(n, kBlock), kCfgChunkSegs) : 1;
+    a.data0 = kHeaderBytes + pad16(a.nblocks);
+    a.out = static_cast<uint8_t *>(d_out);
+    a.capacity = cap;
+    a.stats = d_stats;
+    a.value = value;
+    a.mode = mode;
+    a.features = kFeaturesAll;
+    a.cfg_flags = cfg_flag_bits(block, tile_blocks);
+    if (!ensure_flags(ws, a.nchunks)) return FSZ_ERR_DEVICE;
+    if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
+    a.flags = ws->d_flags;
+    a.ticket = ws->d_ticket;
+    a.final = d_final;
+    if (!ok(launch_compress_cfg(a, block, tile_blocks, aligned(d_in, 16), ws->stream))) return FSZ_ERR_DEVICE;
+    return FSZ_OK;
+}
+
+fsz_status enqueue_decompress_config(Workspace *ws, const void *d_cmp, uint64_t cmp_size, float *d_out, uint64_t n,
+                                     int block, int tile_blocks, fsz_result *d_final)
+{
+    DecompressArgs a{};
+    a.cmp = static_cast<const uint8_t *>(d_cmp);
+    a.cmp_size = cmp_size;
+    a.out = d_out;
+    a.n = n;
+    a.ntiles = ceil_div(n, (uint64_t)block * tile_blocks);
+    a.nblocks = ceil_div(n, (uint64_t)block);
+    a.nchunks = n ? ceil_div(ceil_div(n, kBlock), kCfgChunkSegs) : 1;
+    a.data0 = kHeaderBytes + pad16(a.nblocks);
+    a.tile_begin = 0;
+    a.tile_end = a.ntiles;
+    a.elem_begin = 0;
+    a.elem_end = n;
+    a.range_base = nullptr;
+    a.cfg_flags = cfg_flag_bits(block, tile_blocks);
+    if (!ensure_flags(ws, a.nchunks)) return FSZ_ERR_DEVICE;
+    if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
+    a.flags = ws->d_flags;
+    a.ticket = ws->d_ticket;
+    a.final = d_final;
+    if (!ok(launch_decompress_cfg(a, block, tile_blocks, aligned(d_out, 16), ws->stream))) return FSZ_ERR_DEVICE;
+    return FSZ_OK;
+}
+
 // Random-access decode of elements [begin, end): the tiles that hold them,
 // at the offset the rate header gives for the first one.
 fsz_status enqueue_decompress_range(Workspace *ws, const void *d_cmp, uint64_t cmp_size, uint64_t n,
@@ -664,6 +725,14 @@ size_t fsz_compressed_bound(size_t n)
     return (size_t)(kHeaderBytes + pad16(nblocks) + 4 * ntiles + (4 + 4 * 31) * nblocks);
 }
 
+size_t fsz_compressed_bound_config(size_t n, int block, int tile_blocks)
+{
+    if (!cfg_supported(block, tile_blocks)) return 0;
+    const uint64_t nblocks = ceil_div(n, (uint64_t)block);
+    const uint64_t ntiles = ceil_div(n, (uint64_t)block * tile_blocks);
+    return (size_t)(kHeaderBytes + pad16(nblocks) + 4 * ntiles + (uint64_t)(block / 8) * 32 * nblocks);
+}
+
 const char *fsz_status_string(int s)
 {
     switch (s) {
@@ -777,6 +846,34 @@ fsz_status fsz_decompress_range_async(const void *d_cmp, size_t cmp_size, size_t
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);
     return enqueue_decompress_range(ws, d_cmp, cmp_size, n, begin, end, d_out, d_result);
+}
+
+fsz_status fsz_compress_config_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                                     const fsz_stats *d_stats, int block, int tile_blocks, void *d_out,
+                                     size_t out_capacity, fsz_result *d_result, void *stream)
+{
+    if (!d_result || !cfg_supported(block, tile_blocks) || !valid_bound(mode, value) || !d_out ||
+        (n > 0 && !d_in) || !aligned(d_in, 4) || !aligned(d_out, 4))
+        return FSZ_ERR_INVALID_ARG;
+    if (out_capacity < kHeaderBytes + pad16(ceil_div(n, (uint64_t)block))) return FSZ_ERR_CAPACITY;
+    fsz_status st = FSZ_OK;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    return enqueue_compress_config(ws, d_in, n, mode, value, d_stats, block, tile_blocks, d_out, out_capacity,
+                                   d_result);
+}
+
+fsz_status fsz_decompress_config_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n, int block,
+                                       int tile_blocks, fsz_result *d_result, void *stream)
+{
+    if (!d_result || !cfg_supported(block, tile_blocks)) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_decompress_args(d_cmp, cmp_size, d_out, n);
+    if (st != FSZ_OK) return st;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    return enqueue_decompress_config(ws, d_cmp, cmp_size, d_out, n, block, tile_blocks, d_result);
 }
 
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,

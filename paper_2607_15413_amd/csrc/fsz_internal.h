@@ -66,6 +66,7 @@ struct CompressArgs {
     double value;
     int mode;
     uint32_t features;    // FSZ_FEAT_* switches (kFeaturesAll = the full method)
+    uint32_t cfg_flags;   // header flags bits 2-4: tile configuration (0 = B 32, T 8)
     uint32_t epoch;       // 32-bit call epoch (result words)
     uint32_t flag_epoch;  // 18-bit nonzero epoch (chunk flags)
     unsigned long long *flags;
@@ -84,6 +85,7 @@ struct DecompressArgs {
     // whole-field decode, which also checks the stream's total and padding).
     uint64_t tile_begin, tile_end, elem_begin, elem_end;
     const unsigned long long *range_base;
+    uint32_t cfg_flags;  // tile-configuration decoders: the header flags bits 2-4 required
     uint32_t epoch, flag_epoch;
     unsigned long long *flags;
     unsigned long long *ticket;  // zero between launches (self-resetting)
@@ -152,6 +154,22 @@ hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged
 // (a.nchunks counts chunks of kTilesPerChunk tiles).
 hipError_t launch_compress_naive(const CompressArgs &a, const NaiveTables &t, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s);
+// Tile configurations (Sec. VI-C): one chunk of 4 x 64 32-element segments per
+// workgroup (a.nchunks counts those), block in {32, 64}, tile_blocks in {4, 8, 16}.
+hipError_t launch_compress_cfg(const CompressArgs &a, int block, int tile_blocks, bool in_aligned16, hipStream_t s);
+hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
+                                 hipStream_t s);
+constexpr int kCfgWaves = 4;
+constexpr int kCfgChunkSegs = kCfgWaves * 64;
+// header flags bits 2-4 of a tile configuration (0 for B 32, T 8)
+inline uint32_t cfg_flag_bits(int block, int tile_blocks)
+{
+    return (block == 64 ? 4u : 0u) | (tile_blocks == 4 ? 8u : tile_blocks == 16 ? 16u : 0u);
+}
+inline bool cfg_supported(int block, int tile_blocks)
+{
+    return (block == 32 || block == 64) && (tile_blocks == 4 || tile_blocks == 8 || tile_blocks == 16);
+}
 // Byte offset of tile_begin's data: a reduction of the block sizes before it
 // over the rate header into *range_base (partials: kStatsMaxBlocks words).
 hipError_t launch_range_base(const DecompressArgs &a, unsigned long long *range_base, unsigned long long *partials,

@@ -870,7 +870,8 @@ __device__ __forceinline__ void finish_stream(const CompressArgs &a, const Resol
     if (status == FSZ_OK) {
         uint32_t *h = reinterpret_cast<uint32_t *>(a.out);
         h[0] = 0x315A5346u;  // "FSZ1"
-        const uint32_t hflags = R.flags | ((a.features & FSZ_FEAT_CROSS_BLOCK) ? 0u : 2u);  // bit 1: independent blocks
+        // bit 1: independent blocks; bits 2-4: tile configuration (0 = B 32, T 8)
+        const uint32_t hflags = R.flags | ((a.features & FSZ_FEAT_CROSS_BLOCK) ? 0u : 2u) | a.cfg_flags;
         h[1] = 1u | ((uint32_t)a.mode << 16) | (hflags << 24);
         h[2] = (uint32_t)a.n;
         h[3] = (uint32_t)(a.n >> 32);
@@ -1886,6 +1887,7 @@ __device__ __forceinline__ CompressArgs batch_compress_args(const BatchArgs &b, 
     a.value = J.value;
     a.mode = J.mode;
     a.features = kFeaturesAll;
+    a.cfg_flags = 0;
     a.epoch = b.epoch;
     a.flag_epoch = 1;
     a.flags = b.flags + J.chunk_base;
@@ -1910,6 +1912,7 @@ __device__ __forceinline__ DecompressArgs batch_decompress_args(const BatchArgs 
     a.elem_begin = 0;
     a.elem_end = J.n;
     a.range_base = nullptr;
+    a.cfg_flags = 0;
     a.epoch = b.epoch;
     a.flag_epoch = 1;
     a.flags = b.flags + J.chunk_base;
@@ -2029,6 +2032,357 @@ hipError_t launch_stats(const StatsArgs &a, hipStream_t s)
         hipLaunchKernelGGL(stats_partial_kernel<false>, dim3(grid), dim3(kStatsThreads), 0, s, a);
     hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kStatsThreads), 0, s, a, grid);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ tile configurations
+//
+// The tile-configuration sweep of Sec. VI-C (Table V): blocks of B = 32 HB
+// elements (HB = 1 or 2) and tiles of T blocks, recorded in header flags bits
+// 2-4.  As in the default kernels a lane holds one 32-element segment; a block
+// spans HB lanes and a tile L = HB T lanes (4 to 32), so the cross-block chain
+// runs over L lanes.  A 64-element block's words (sign map, planes) are 64
+// bits with element i at bit 63 - i, written most-significant byte first:
+// the stored words of its two halves side by side, so the lane of half h
+// writes its word k at byte 8k + 4h of the block.  One chunk of kCfgWaves
+// waves per workgroup, chunk ids from the ticket counter (as compress_kernel).
+
+constexpr int kCfgStageDwords = 2064;  // a wave's largest output: 64 x 128 B + 16 tile means
+
+// Sum over aligned groups of L lanes, in every lane of the group.  For binary32
+// values the butterfly adds the groups' halves in index order at each level,
+// so it reproduces the pairwise tree bit for bit (addition is commutative).
+template <int L, typename V>
+__device__ __forceinline__ V lane_group_sum(V v)
+{
+#pragma unroll
+    for (int k = 1; k < L; k <<= 1) v = v + __shfl_xor(v, k);
+    return v;
+}
+
+// Inclusive prefix sum over aligned runs of `run` lanes (a power of two, at
+// most L); pos = the lane's index inside its group of L lanes.
+template <int L>
+__device__ __forceinline__ uint32_t lane_run_incl_scan(uint32_t v, int pos, int run)
+{
+#pragma unroll
+    for (int k = 1; k < L; k <<= 1) {
+        const uint32_t t = __shfl_up(v, k);
+        if (k < run && (pos & (run - 1)) >= k) v += t;
+    }
+    return v;
+}
+
+template <bool ALIGNED, int HB, int L>
+__global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressArgs a)
+{
+    __shared__ CompressShared<kCfgWaves> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t stage[kCfgWaves * kCfgStageDwords];
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int tl = lane % L;  // lane inside the tile
+    const int h = tl % HB;    // half of a 64-element block
+    uint32_t *st = stage + w * kCfgStageDwords;
+    int tslot = 0;
+    const uint64_t chunk = next_ticket(a.ticket, a.nchunks, sh, tslot);
+    if (chunk >= a.nchunks) return;  // inconsistent ticket counter: never index past the flags
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status != FSZ_OK) {
+        if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
+        return;
+    }
+    const uint64_t seg0 = (chunk * kCfgWaves + w) * 64;  // the wave's first segment
+    const uint64_t seg = seg0 + lane;
+    const uint64_t e0 = seg * 32;
+    const int cnt = e0 >= a.n ? 0 : (a.n - e0 >= 32 ? 32 : (int)(a.n - e0));
+    const bool tile_ok = seg / L < a.ntiles;
+    const bool full = (seg0 + 64) * 32 <= a.n;  // wave-uniform
+    const uint32_t vm = cnt >= 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u);
+    int x[32];
+    {
+        float f[32];
+        load_block<ALIGNED>(a.x, e0, cnt, f);
+#pragma unroll
+        for (int i = 0; i < 32; i++) x[i] = __float_as_int(f[i]);
+    }
+
+    // ---- tile mean: pairwise binary32 tree over the B T slots, times 1/(B T)
+    float s16[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) s16[i] = __int_as_float(x[2 * i]) + __int_as_float(x[2 * i + 1]);
+#pragma unroll
+    for (int i = 0; i < 8; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+#pragma unroll
+    for (int i = 0; i < 4; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+#pragma unroll
+    for (int i = 0; i < 2; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+    const float ts = lane_group_sum<L>(s16[0] + s16[1]);
+    const float mean_q = (ts * (1.0f / (float)(32 * L))) * R.inv;
+    const bool centre_ok = __builtin_isfinite(mean_q);
+    const int mu = centre_ok ? (int)__builtin_rintf(mean_q) : 0;
+
+    // ---- quantize (biased), cross-block state from the previous lane of the tile
+#pragma unroll
+    for (int i = 0; i < 32; i++) x[i] = __float_as_int(__int_as_float(x[i]) * R.inv + kQMagic);
+    const int p31 = __shfl_up(x[31], 1);
+    const int p30 = __shfl_up(x[30], 1);
+    const bool first = tl == 0;  // the tile start: the prediction restarts
+    const int carry_b = first ? kQBias : p31;
+    const int carry_l1 = first ? 0 : p31 - p30;
+    uint32_t a1, a2;
+    int l2_1;
+    if (full)
+        block_extrema<true>(x, carry_b, carry_l1, first ? 0 : 1, vm, a1, a2, l2_1);
+    else
+        block_extrema<false>(x, carry_b, carry_l1, first ? 0 : 1, vm, a1, a2, l2_1);
+
+    // ---- four-way evaluation (Eq. (3)-(4)): block magnitude maxima per
+    // variant, the tile start re-rated per variant
+    uint32_t m0 = a1, m1 = a2, m2 = a1, m3 = a2;
+    if (first) {
+        const int q0 = x[0] - kQBias;
+        const int d1 = cnt >= 2 ? l2_1 : 0;  // q1 - 2 q0
+        const int c0 = q0 - mu;
+        const int c1 = cnt >= 2 ? l2_1 + mu : 0;
+        m0 = max(uabs(q0), a1);
+        m1 = max(max(uabs(q0), uabs(d1)), a2);
+        m2 = max(uabs(c0), a1);
+        m3 = max(max(uabs(c0), uabs(c1)), a2);
+    }
+    if (cnt == 0) m0 = m1 = m2 = m3 = 0;  // segments past the end of the field
+    if (HB == 2) {
+        m0 = max(m0, (uint32_t)__shfl_xor((int)m0, 1));
+        m1 = max(m1, (uint32_t)__shfl_xor((int)m1, 1));
+        m2 = max(m2, (uint32_t)__shfl_xor((int)m2, 1));
+        m3 = max(m3, (uint32_t)__shfl_xor((int)m3, 1));
+    }
+    const uint32_t r0 = bitlen(m0), r1 = bitlen(m1), r2 = bitlen(m2), r3 = bitlen(m3);
+    // block costs (B/8 bytes per word, sign map + r planes), counted once per block
+    const uint32_t Ca = lane_group_sum<L>(h == 0 ? (uint32_t)HB * block_bytes(r0) : 0u);
+    const uint32_t Cb = lane_group_sum<L>(h == 0 ? (uint32_t)HB * block_bytes(r1) : 0u);
+    const uint32_t Cc = lane_group_sum<L>(h == 0 ? (uint32_t)HB * block_bytes(r2) : 0u) + 4u;
+    const uint32_t Cd = lane_group_sum<L>(h == 0 ? (uint32_t)HB * block_bytes(r3) : 0u) + 4u;
+    int best = 0;
+    uint32_t C = Ca, r = r0;
+    if (Cb < C) {
+        best = 1;
+        C = Cb;
+        r = r1;
+    }
+    if (centre_ok) {
+        if (Cc < C) {
+            best = 2;
+            C = Cc;
+            r = r2;
+        }
+        if (Cd < C) {
+            best = 3;
+            C = Cd;
+            r = r3;
+        }
+    }
+    if (!tile_ok) {
+        best = 0;
+        C = 0;
+        r = 0;
+    }
+    const int order2 = best & 1, cent = best >> 1;
+    if (h == 0 && cnt > 0)  // the block's rate byte (Sec. III-A)
+        a.out[kHeaderBytes + seg / HB] = (uint8_t)(first ? (r | (uint32_t)order2 << 7 | (uint32_t)cent << 6) : r);
+
+    // ---- offsets: the lane's block inside the tile, the tile inside the wave
+    const uint32_t S = block_bytes(r);  // this lane's words: 4 (1 + r) bytes
+    const uint32_t pre = lane_run_incl_scan<L>(S, tl, L) - S;
+    const uint32_t blk_rel = 4u * (uint32_t)cent + pre - (uint32_t)h * S;
+    const int incl = wave_incl_scan(first ? (int)C : 0);
+    const uint32_t tile_excl = (uint32_t)incl - C;
+    const uint32_t wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
+    if (lane == 0) sh.wave_total[0][w] = wave_total;
+    lds_barrier();
+    uint32_t chunk_total = 0, wave_base = 0;
+#pragma unroll
+    for (int k = 0; k < kCfgWaves; k++) {
+        if (k < w) wave_base += sh.wave_total[0][k];
+        chunk_total += sh.wave_total[0][k];
+    }
+    if (tid == 0) publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, false);
+    if (w == 0) {  // decoupled lookback (Sec. IV-D)
+        const Prefix pre_c = lookback_wait(a.flags, chunk, a.flag_epoch, chunk_total, false);
+        if (lane == 0) {
+            sh.base = pre_c.excl;
+            if (chunk == a.nchunks - 1) finish_stream(a, R, pre_c, chunk_total);
+        }
+    }
+    lds_barrier();
+    const uint64_t base = sh.base;
+    if (a.data0 + base + chunk_total > a.capacity || seg0 / L >= a.ntiles) return;
+
+    // ---- encode (Sec. IV-C) into the wave's staging area, then one copy
+    if (first && cent && tile_ok) st[tile_excl >> 2] = (uint32_t)mu;
+    block_codes<0>(x, carry_b, carry_l1, first ? 0 : 1, order2, cent, mu);
+    const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(vm));
+    const uint32_t nwords = r ? r + 1 : 0;
+    uint32_t *words = st + ((tile_excl + blk_rel) >> 2) + h;
+    for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
+        uint32_t Rg[8];
+#pragma unroll
+        for (int rho = 0; rho < 8; rho++)
+            Rg[rho] = pack_byte_g((uint32_t)x[7 - rho], (uint32_t)x[15 - rho], (uint32_t)x[23 - rho],
+                                  (uint32_t)x[31 - rho], g);
+        transpose8(Rg);
+#pragma unroll
+        for (int p = 0; p < 8; p++)
+            if (8 * g + p < nwords) words[HB * (8 * g + p)] = Rg[p] & keep;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    wave_store_staged(reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base), st, wave_total >> 2, lane);
+}
+
+template <bool ALIGNED, int HB, int L>
+__global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(DecompressArgs a)
+{
+    __shared__ DecompressShared<kCfgWaves> sh;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int tl = lane % L;
+    const int h = tl % HB;
+
+    // ---- header: as dec_header, with the configuration bits of this kernel
+    const uint32_t *hw = reinterpret_cast<const uint32_t *>(a.cmp);
+    const uint32_t h1 = hw[1];
+    int hst = FSZ_OK;
+    if (hw[0] != 0x315A5346u || (h1 & 0xFFFFu) != 1u || ((h1 >> 16) & 0xFFu) > 1u || ((h1 >> 24) & ~0x1Fu) != 0u ||
+        ((h1 >> 24) & 0x1Cu) != a.cfg_flags)
+        hst = FSZ_ERR_CORRUPT;
+    else if (((uint64_t)hw[3] << 32 | hw[2]) != a.n)
+        hst = FSZ_ERR_SIZE_MISMATCH;
+    const bool indep = ((h1 >> 25) & 1u) != 0;  // flags bit 1: prediction restarts at every block
+    const float E = __uint_as_float(hw[4]);
+    const uint64_t total = (uint64_t)hw[7] << 32 | hw[6];
+    if (hst == FSZ_OK && (!__builtin_isfinite(E) || !(E > 0.0f) || total > a.cmp_size || total < a.data0))
+        hst = FSZ_ERR_CORRUPT;
+    if (hst != FSZ_OK) {
+        if (tid == 0 && blockIdx.x == 0) write_final(a.final, 0, hst, a.epoch);
+        return;
+    }
+    int tslot = 0;
+    const uint64_t chunk = next_ticket(a.ticket, a.nchunks, sh, tslot);
+    if (chunk >= a.nchunks) return;
+
+    // ---- steps 1-2: rate bytes -> block, tile and wave sizes
+    const uint64_t seg0 = (chunk * kCfgWaves + w) * 64;
+    const uint64_t seg = seg0 + lane;
+    const uint64_t e0 = seg * 32;
+    const int cnt = e0 >= a.n ? 0 : (a.n - e0 >= 32 ? 32 : (int)(a.n - e0));
+    const bool tile_ok = seg / L < a.ntiles;
+    const uint64_t blk = seg / HB;
+    const bool blk_ok = tile_ok && blk < a.nblocks;
+    const bool first = tl == 0;
+    const uint32_t rb = blk_ok ? a.cmp[kHeaderBytes + blk] : 0u;
+    const bool bad = blk_ok && h == 0 && (first ? (rb & 0x20u) : (rb & 0xE0u)) != 0;
+    const uint32_t head = (uint32_t)__shfl((int)rb, lane - tl);  // the tile's first rate byte
+    const int order2 = tile_ok ? (int)((head >> 7) & 1u) : 0;
+    const int cent = tile_ok ? (int)((head >> 6) & 1u) : 0;
+    const uint32_t r = rb & 31u;
+    const uint32_t S = block_bytes(r);  // this lane's words
+    const uint32_t Z = lane_group_sum<L>(S) + 4u * (uint32_t)cent;
+    const uint32_t pre = lane_run_incl_scan<L>(S, tl, L) - S;
+    const uint32_t blk_rel = 4u * (uint32_t)cent + pre - (uint32_t)h * S;
+    const int incl = wave_incl_scan(first ? (int)Z : 0);
+    const uint32_t tile_excl = (uint32_t)incl - Z;
+    const uint32_t wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
+    const bool wave_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+        sh.wave_total[0][w] = wave_total;
+        sh.wave_total[1][w] = wave_bad ? 1u : 0u;
+    }
+    lds_barrier();
+    uint32_t chunk_total = 0, wave_base = 0;
+    bool any_bad = false;
+#pragma unroll
+    for (int k = 0; k < kCfgWaves; k++) {
+        if (k < w) wave_base += sh.wave_total[0][k];
+        chunk_total += sh.wave_total[0][k];
+        any_bad = any_bad || sh.wave_total[1][k] != 0;
+    }
+    if (tid == 0) publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, any_bad);
+    if (w == 0) {
+        const Prefix pre_c = lookback_wait(a.flags, chunk, a.flag_epoch, chunk_total, any_bad);
+        if (lane == 0) {
+            sh.base = pre_c.excl;
+            if (chunk == a.nchunks - 1) {  // the sizes add up to the stream's total, padding is zero
+                bool good = !pre_c.err && a.data0 + pre_c.excl + chunk_total == total;
+                for (uint64_t k = kHeaderBytes + a.nblocks; good && k < a.data0; k++) good = a.cmp[k] == 0;
+                write_final(a.final, total, good ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT, a.epoch);
+            }
+        }
+    }
+    lds_barrier();
+    const uint64_t base = sh.base;
+    if (any_bad || a.data0 + base + chunk_total > total || seg0 / L >= a.ntiles) return;
+
+    // ---- steps 3-5: bit-unshuffle, inverse prediction, x' = (float)q * E
+    const uint8_t *wave_data = a.cmp + a.data0 + base + wave_base;
+    int mu = 0;
+    if (cent) mu = (int)*reinterpret_cast<const uint32_t *>(wave_data + tile_excl);
+    uint32_t code[32];
+#pragma unroll
+    for (int i = 0; i < 32; i++) code[i] = 0;
+    const uint32_t nwords = (blk_ok && r) ? r + 1 : 0;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(wave_data + tile_excl + blk_rel) + h;
+    for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
+        uint32_t Rg[8];
+#pragma unroll
+        for (int p = 0; p < 8; p++) Rg[p] = 8 * g + p < nwords ? words[HB * (8 * g + p)] : 0u;
+        transpose8(Rg);
+        // Rg[rho] byte k = byte g of code 8k + 7 - rho
+#pragma unroll
+        for (int rho = 0; rho < 8; rho++) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t sel = (0x03020100u & ~(0xFFu << (8 * g))) | ((4u + k) << (8 * g));
+                code[8 * k + 7 - rho] = __builtin_amdgcn_perm(Rg[rho], code[8 * k + 7 - rho], sel);
+            }
+        }
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        const uint32_t ns = (uint32_t)-(int)(code[i] & 1u);
+        acc += ((code[i] >> 1) ^ ns) - ns;
+        code[i] = acc;  // first running sum inside the segment
+    }
+    // carries from the earlier lanes of the prediction run (the tile, or the
+    // block when every block restarts)
+    const int run = indep ? HB : L;
+    const uint32_t start1 = lane_run_incl_scan<L>(acc, tl, run) - acc;
+    uint32_t acc2 = 0;
+#pragma unroll
+    for (int i = 0; i < 32; i++) acc2 += code[i] + start1;
+    const uint32_t start2 = lane_run_incl_scan<L>(acc2, tl, run) - acc2;
+    float xo[32];
+    {
+        const uint32_t om = (uint32_t)-order2;
+        uint32_t run2 = start2;
+#pragma unroll
+        for (int i = 0; i < 32; i++) {
+            const uint32_t d1 = code[i] + start1;  // first running sum with the carry
+            run2 += d1;                            // second running sum
+            const uint32_t qh = (run2 & om) | (d1 & ~om);
+            xo[i] = (float)(int)(qh + (uint32_t)mu) * E;
+        }
+    }
+    if (ALIGNED && cnt == 32) {
+        f4 *p = reinterpret_cast<f4 *>(a.out + e0);
+#pragma unroll
+        for (int k = 0; k < 8; k++) p[k] = f4{xo[4 * k], xo[4 * k + 1], xo[4 * k + 2], xo[4 * k + 3]};
+    } else {
+#pragma unroll
+        for (int i = 0; i < 32; i++)
+            if (i < cnt) a.out[e0 + i] = xo[i];
+    }
 }
 
 // Workgroups of a persistent grid: enough to fill every CU at the kernel's
@@ -2171,6 +2525,54 @@ hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool s
     if (out_aligned16)
         return staged ? launch_decompress_t<true, true>(a, s) : launch_decompress_t<true, false>(a, s);
     return staged ? launch_decompress_t<false, true>(a, s) : launch_decompress_t<false, false>(a, s);
+}
+
+// Tile configurations (Sec. VI-C): (B, T) -> (HB, L) = (B / 32, T B / 32).
+template <bool ALIGNED>
+static hipError_t launch_compress_cfg_t(const CompressArgs &a, int block, int tile_blocks, hipStream_t s)
+{
+    const dim3 grid((unsigned)a.nchunks), threads(kCfgWaves * 64);
+    const int key = block * 100 + tile_blocks;
+    switch (key) {
+    case 3204: hipLaunchKernelGGL((compress_cfg_kernel<ALIGNED, 1, 4>), grid, threads, 0, s, a); break;
+    case 3208: hipLaunchKernelGGL((compress_cfg_kernel<ALIGNED, 1, 8>), grid, threads, 0, s, a); break;
+    case 3216: hipLaunchKernelGGL((compress_cfg_kernel<ALIGNED, 1, 16>), grid, threads, 0, s, a); break;
+    case 6404: hipLaunchKernelGGL((compress_cfg_kernel<ALIGNED, 2, 8>), grid, threads, 0, s, a); break;
+    case 6408: hipLaunchKernelGGL((compress_cfg_kernel<ALIGNED, 2, 16>), grid, threads, 0, s, a); break;
+    case 6416: hipLaunchKernelGGL((compress_cfg_kernel<ALIGNED, 2, 32>), grid, threads, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <bool ALIGNED>
+static hipError_t launch_decompress_cfg_t(const DecompressArgs &a, int block, int tile_blocks, hipStream_t s)
+{
+    const dim3 grid((unsigned)a.nchunks), threads(kCfgWaves * 64);
+    const int key = block * 100 + tile_blocks;
+    switch (key) {
+    case 3204: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 4>), grid, threads, 0, s, a); break;
+    case 3208: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 8>), grid, threads, 0, s, a); break;
+    case 3216: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 16>), grid, threads, 0, s, a); break;
+    case 6404: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 8>), grid, threads, 0, s, a); break;
+    case 6408: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 16>), grid, threads, 0, s, a); break;
+    case 6416: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 32>), grid, threads, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_cfg(const CompressArgs &a, int block, int tile_blocks, bool in_aligned16, hipStream_t s)
+{
+    return in_aligned16 ? launch_compress_cfg_t<true>(a, block, tile_blocks, s)
+                        : launch_compress_cfg_t<false>(a, block, tile_blocks, s);
+}
+
+hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
+                                 hipStream_t s)
+{
+    return out_aligned16 ? launch_decompress_cfg_t<true>(a, block, tile_blocks, s)
+                         : launch_decompress_cfg_t<false>(a, block, tile_blocks, s);
 }
 
 constexpr size_t kLdsPerCu = 160 * 1024;

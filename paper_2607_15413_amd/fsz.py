@@ -44,6 +44,9 @@ EXPORTS = (
     "fsz_decompress_range_async",
     "fsz_compress_features_async",
     "fsz_compress_five_read_async",
+    "fsz_compressed_bound_config",
+    "fsz_compress_config_async",
+    "fsz_decompress_config_async",
     "fsz_batch_async",
     "fsz_autotune",
     "fsz_plan_create",
@@ -153,6 +156,13 @@ def load_library():
     lib.fsz_compress_five_read_async.restype = ctypes.c_int
     lib.fsz_decompress_range_async.argtypes = [vp, sz, sz, sz, sz, vp, vp, vp]
     lib.fsz_decompress_range_async.restype = ctypes.c_int
+    lib.fsz_compressed_bound_config.argtypes = [sz, ctypes.c_int, ctypes.c_int]
+    lib.fsz_compressed_bound_config.restype = sz
+    lib.fsz_compress_config_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, ctypes.c_int,
+                                              ctypes.c_int, vp, sz, vp, vp]
+    lib.fsz_compress_config_async.restype = ctypes.c_int
+    lib.fsz_decompress_config_async.argtypes = [vp, sz, vp, sz, ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.fsz_decompress_config_async.restype = ctypes.c_int
     lib.fsz_decompress_async.argtypes = [vp, sz, vp, sz, vp, vp]
     lib.fsz_decompress_async.restype = ctypes.c_int
     jp, tp = ctypes.POINTER(FszJob), ctypes.POINTER(FszTuning)
@@ -248,6 +258,24 @@ def fsz_compress_five_read_async(d_in: int, n: int, mode: int, value: float, d_s
     """The five-read baseline (enqueue only); same stream as fsz_compress_async."""
     return load_library().fsz_compress_five_read_async(d_in, n, mode, value, d_stats, d_out, out_capacity,
                                                        d_result, stream)
+
+
+def fsz_compressed_bound_config(n: int, block: int, tile_blocks: int) -> int:
+    return int(load_library().fsz_compressed_bound_config(n, block, tile_blocks))
+
+
+def fsz_compress_config_async(d_in: int, n: int, mode: int, value: float, d_stats, block: int,
+                              tile_blocks: int, d_out: int, out_capacity: int, d_result: int, stream=None) -> int:
+    """Compression with a (block, tile_blocks) tile configuration (enqueue only)."""
+    return load_library().fsz_compress_config_async(d_in, n, mode, value, d_stats, block, tile_blocks, d_out,
+                                                    out_capacity, d_result, stream)
+
+
+def fsz_decompress_config_async(d_cmp: int, cmp_size: int, d_out: int, n: int, block: int, tile_blocks: int,
+                                d_result: int, stream=None) -> int:
+    """Decode a stream of a (block, tile_blocks) tile configuration (enqueue only)."""
+    return load_library().fsz_decompress_config_async(d_cmp, cmp_size, d_out, n, block, tile_blocks, d_result,
+                                                      stream)
 
 
 def fsz_decompress_async(d_cmp: int, cmp_size: int, d_out: int, n: int, d_result: int,
