@@ -502,6 +502,94 @@ def ablation_benchmark(torch, fsz, workloads, x, stats, outs, sizes):
     return {"grf 512^3": grf, "piecewise quadratic 100x500x500": pwq}, five
 
 
+TILE_CONFIGS = ((32, 4), (32, 8), (32, 16), (64, 4), (64, 8), (64, 16))  # (B, T); the paper sweeps all but 64/16
+
+
+def tile_sweep(torch, fsz, workloads, x, stats, outs, sizes, reps: int = 5):
+    """The tile-configuration sweep (Sec. VI-C, Table V, Fig. 9): block size B
+    and blocks per tile T.  On the timed field: CR and compress / decompress
+    GB/s (4n / kernel time) of every configuration through the generic
+    configuration kernels, the 32 / 8 stream checked against the default
+    path's.  On a set of synthetic fields x 3 bounds: per configuration the
+    tests won / tied / lost against 32 / 8 (win = CR more than 2% higher) and
+    the mean CR ratio, as Table V counts them."""
+    dev = x.device
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    n = x.numel()
+    cap = max(fsz.fsz_compressed_bound_config(n, B, T) for B, T in TILE_CONFIGS)
+    buf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    res = torch.zeros(4, dtype=torch.int32, device=dev)
+
+    def compress_cfg(xt, st_t, rel, B, T):
+        st = fsz.fsz_compress_config_async(xt.data_ptr(), xt.numel(), fsz.FSZ_REL, rel, st_t.data_ptr(), B, T,
+                                           buf.data_ptr(), cap, res.data_ptr(), sh)
+        if st != fsz.FSZ_OK:
+            raise RuntimeError(fsz.fsz_status_string(st))
+
+    rows = []
+    identical = True
+    for k, rel in enumerate(RELS):
+        for B, T in TILE_CONFIGS:
+            c_ms = _timed(torch, stream, lambda: compress_cfg(x, stats, rel, B, T), reps)
+            size, st, _ = fsz.read_result(res)
+            if st != fsz.FSZ_OK:
+                raise RuntimeError(f"tile sweep B={B} T={T} rel={rel}: {fsz.fsz_status_string(st)}")
+            if (B, T) == (32, 8):
+                identical = identical and size == sizes[k] and torch.equal(buf[:size], outs[k][:size])
+
+            def dec():
+                st = fsz.fsz_decompress_config_async(buf.data_ptr(), size, y.data_ptr(), n, B, T, res.data_ptr(), sh)
+                if st != fsz.FSZ_OK:
+                    raise RuntimeError(fsz.fsz_status_string(st))
+            d_ms = _timed(torch, stream, dec, reps)
+            _, st, _ = fsz.read_result(res)
+            if st != fsz.FSZ_OK:
+                raise RuntimeError(f"tile sweep decode B={B} T={T} rel={rel}: {fsz.fsz_status_string(st)}")
+            rows.append({"B": B, "T": T, "rel": rel, "cr": round(4 * n / size, 4),
+                         "compress_GBps": round(4 * n / c_ms / 1e6, 1),
+                         "decompress_GBps": round(4 * n / d_ms / 1e6, 1)})
+    del y
+
+    # win / tie / loss against 32 / 8 over synthetic fields x bounds
+    fields = [("grf k^-3 512^3 (timed field)", None),
+              ("grf k^-2 256^3", lambda: workloads.grf_field((256, 256, 256), 11, slope=-2.0)),
+              ("grf k^-4 256^3", lambda: workloads.grf_field((256, 256, 256), 12, slope=-4.0)),
+              ("piecewise quadratic 100x500x500", lambda: workloads.piecewise_quadratic((100, 500, 500), 2)),
+              ("sinusoid 2^24", lambda: workloads.sinusoid_field(1 << 24, 5)),
+              ("sinusoid 2^22 noise-free", lambda: workloads.sinusoid_field(1 << 22, 6, noise_sigma=0.0))]
+    crs = {}  # (field, rel) -> {(B, T): cr}
+    for name, gen in fields:
+        if gen is None:
+            xt, st_t = x, stats
+        else:
+            xt = torch.from_numpy(gen()).to(dev)
+            st_t = torch.zeros(4, dtype=torch.int32, device=dev)
+            st = fsz.fsz_field_stats(xt.data_ptr(), xt.numel(), st_t.data_ptr(), sh)
+            if st != fsz.FSZ_OK:
+                raise RuntimeError(fsz.fsz_status_string(st))
+        for rel in RELS:
+            for B, T in TILE_CONFIGS:
+                compress_cfg(xt, st_t, rel, B, T)
+                size, st, _ = fsz.read_result(res)
+                if st != fsz.FSZ_OK:
+                    raise RuntimeError(f"tile sweep {name} B={B} T={T}: {fsz.fsz_status_string(st)}")
+                crs.setdefault((name, rel), {})[(B, T)] = 4 * xt.numel() / size
+        del xt
+    table = []
+    for B, T in TILE_CONFIGS:
+        if (B, T) == (32, 8):
+            continue
+        ratios = [c[(B, T)] / c[(32, 8)] for c in crs.values()]
+        table.append({"B": B, "T": T, "tile": B * T, "win": sum(r > 1.02 for r in ratios),
+                      "tie": sum(0.98 <= r <= 1.02 for r in ratios), "loss": sum(r < 0.98 for r in ratios),
+                      "cr_ratio": round(float(np.mean(ratios)), 4)})
+    del buf
+    return {"timed_field": rows, "default_identical": bool(identical), "vs_default": table,
+            "tests": len(crs), "fields": [f for f, _ in fields]}
+
+
 def small_configs(torch, fsz, workloads, verify: bool, reps: int = 20):
     """The 2^20 sinusoid field (REL 1e-3; warm and MALL-flushed) and the
     100x500x500 piecewise-quadratic field (REL 1e-2/1e-3/1e-4; flushed: a
@@ -784,10 +872,11 @@ def main():
                 "decompress_GBps": round(len(RELS) * 4 * n / t_d / 1e9, 4),
             }
 
-    ablation = five_read = ranges = None
+    ablation = five_read = ranges = sweep = None
     if not args.no_ablation:
         ablation, five_read = ablation_benchmark(torch, fsz, workloads, x, stats, outs, sizes)
         ranges = random_access(torch, fsz, outs, sizes, n, dec_ms[1])
+        sweep = tile_sweep(torch, fsz, workloads, x, stats, outs, sizes)
     others = None
     if not args.no_batched:
         others = small_configs(torch, fsz, workloads, not args.no_verify)
@@ -829,6 +918,7 @@ def main():
         "ablation": ablation,
         "five_read": five_read,
         "random_access": ranges,
+        "tile_sweep": sweep,
         "batched": batched,
         "other_configs": others,
     }
