@@ -2046,7 +2046,9 @@ hipError_t launch_stats(const StatsArgs &a, hipStream_t s)
 // writes its word k at byte 8k + 4h of the block.  One chunk of kCfgWaves
 // waves per workgroup, chunk ids from the ticket counter (as compress_kernel).
 
-constexpr int kCfgStageDwords = 2064;  // a wave's largest output: 64 x 128 B + 16 tile means
+// a wave's staging area: the padded input rows (64 x 36 dwords), reused for
+// its output (at most 64 x 128 B + 16 tile means = 2064 dwords)
+constexpr int kCfgStageDwords = 64 * kStageRowDwords;
 
 // Sum over aligned groups of L lanes, in every lane of the group.  For binary32
 // values the butterfly adds the groups' halves in index order at each level,
@@ -2101,7 +2103,12 @@ __global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressAr
     int x[32];
     {
         float f[32];
-        load_block<ALIGNED>(a.x, e0, cnt, f);
+        if (seg0 * 32 < a.n) {  // coalesced loads of the wave's 2048 elements through LDS
+            load_blocks_staged<ALIGNED>(a.x, a.n, seg0 * 32, st, lane, f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; i++) f[i] = 0.0f;
+        }
 #pragma unroll
         for (int i = 0; i < 32; i++) x[i] = __float_as_int(f[i]);
     }
@@ -2243,6 +2250,7 @@ template <bool ALIGNED, int HB, int L>
 __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(DecompressArgs a)
 {
     __shared__ DecompressShared<kCfgWaves> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t stage[kCfgWaves * kCfgStageDwords];
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
@@ -2274,8 +2282,6 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
     // ---- steps 1-2: rate bytes -> block, tile and wave sizes
     const uint64_t seg0 = (chunk * kCfgWaves + w) * 64;
     const uint64_t seg = seg0 + lane;
-    const uint64_t e0 = seg * 32;
-    const int cnt = e0 >= a.n ? 0 : (a.n - e0 >= 32 ? 32 : (int)(a.n - e0));
     const bool tile_ok = seg / L < a.ntiles;
     const uint64_t blk = seg / HB;
     const bool blk_ok = tile_ok && blk < a.nblocks;
@@ -2374,14 +2380,38 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
             xo[i] = (float)(int)(qh + (uint32_t)mu) * E;
         }
     }
-    if (ALIGNED && cnt == 32) {
-        f4 *p = reinterpret_cast<f4 *>(a.out + e0);
+    // ---- write back through LDS with coalesced stores (the wave's 2048 elements)
+    uint32_t *st = stage + w * kCfgStageDwords;
 #pragma unroll
-        for (int k = 0; k < 8; k++) p[k] = f4{xo[4 * k], xo[4 * k + 1], xo[4 * k + 2], xo[4 * k + 3]};
+    for (int k = 0; k < 8; k++)
+        *reinterpret_cast<float4 *>(st + lane * kStageRowDwords + 4 * k) =
+            make_float4(xo[4 * k], xo[4 * k + 1], xo[4 * k + 2], xo[4 * k + 3]);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const uint64_t w0 = seg0 * 32;
+    const bool fullw = w0 + 2048 <= a.n;
+    if (ALIGNED) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int p = k * 64 + lane;
+            const uint64_t e = w0 + 4ull * p;
+            const f4 f = *reinterpret_cast<const f4 *>(st + (p >> 3) * kStageRowDwords + (p & 7) * 4);
+            if (fullw || e + 4 <= a.n) {
+                __builtin_nontemporal_store(f, reinterpret_cast<f4 *>(a.out + e));
+            } else {
+                if (e + 0 < a.n) a.out[e + 0] = f.x;
+                if (e + 1 < a.n) a.out[e + 1] = f.y;
+                if (e + 2 < a.n) a.out[e + 2] = f.z;
+                if (e + 3 < a.n) a.out[e + 3] = f.w;
+            }
+        }
     } else {
-#pragma unroll
-        for (int i = 0; i < 32; i++)
-            if (i < cnt) a.out[e0 + i] = xo[i];
+#pragma unroll 8
+        for (int k = 0; k < 32; k++) {
+            const int p = k * 64 + lane;
+            const uint64_t e = w0 + p;
+            if (fullw || e < a.n) a.out[e] = __uint_as_float(st[(p >> 5) * kStageRowDwords + (p & 31)]);
+        }
     }
 }
 
