@@ -506,7 +506,7 @@ TILE_CONFIGS = ((32, 4), (32, 8), (32, 16), (64, 4), (64, 8), (64, 16))  # (B, T
 
 
 def tile_sweep(torch, fsz, workloads, x, stats, outs, sizes, reps: int = 5):
-    """The tile-configuration sweep (Sec. VI-C, Table V, Fig. 9): block size B
+    """The tile-configuration sweep (Sec. VI-C, Table V, Fig. 10): block size B
     and blocks per tile T.  On the timed field: CR and compress / decompress
     GB/s (4n / kernel time) of every configuration through the generic
     configuration kernels, the 32 / 8 stream checked against the default
