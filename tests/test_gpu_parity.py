@@ -131,6 +131,58 @@ def test_grf_512_full_size_bench_launch():
         assert np.array_equal(y.cpu().numpy().view(np.uint32), y_ref.view(np.uint32))
 
 
+@pytest.mark.timeout(600)
+def test_stream_beyond_4gib():
+    """64-bit sizes and offsets: 2^31 + 4099 uniform values at REL 1e-6 give
+    an input of 8 GiB and a stream of about 5.7 GB, so tile offsets, the
+    lookback sums and the header's total pass 2^32 bytes.  Every byte
+    against the oracle; the decode against the closed form fl(rint(fl(x *
+    inv)) * E) computed with plain torch operations on the device."""
+    n = (1 << 31) + 4099
+    rng = np.random.default_rng(17)
+    x = rng.random(n, dtype=np.float32)
+    x *= 2
+    x -= 1
+    rel = 1e-6
+    announce(f"stream beyond 4 GiB: uniform n={n} REL {rel:g}")
+    xd = torch.from_numpy(x).to(_dev())
+    cap = fsz.fsz_compressed_bound(n)
+    out = torch.zeros(cap, dtype=torch.uint8, device=_dev())
+    r1 = torch.zeros(4, dtype=torch.int32, device=_dev())
+    assert fsz.fsz_compress_async(xd.data_ptr(), n, fsz.FSZ_REL, rel, None, out.data_ptr(), cap, r1.data_ptr(),
+                                  _stream()) == fsz.FSZ_OK
+    size, st, _ = fsz.read_result(r1)
+    assert st == fsz.FSZ_OK and size > (1 << 32)
+    ref = oracle.compress(x, oracle.REL, rel)
+    assert size == len(ref)
+    got = out[:size].cpu().numpy()
+    assert np.array_equal(got, np.frombuffer(ref, dtype=np.uint8))
+    E = np.float32(fmt.parse_header(ref)["E"])
+    del ref, got
+    announce(f"stream beyond 4 GiB: decode of {size} bytes")
+    y = torch.empty(n, dtype=torch.float32, device=_dev())
+    r2 = torch.zeros(4, dtype=torch.int32, device=_dev())
+    assert fsz.fsz_decompress_async(out.data_ptr(), size, y.data_ptr(), n, r2.data_ptr(), _stream()) == fsz.FSZ_OK
+    assert fsz.read_result(r2)[1] == fsz.FSZ_OK
+    del out
+    inv = np.float32(1) / E
+    # binary32 product, round half to even, then the integer q (|q| < 2^22:
+    # exact), whose zero is +0 whatever the sign of the product
+    q = torch.round(xd * float(inv)).to(torch.int32)
+    del xd
+    expect = q.to(torch.float32) * float(E)
+    del q
+    step = 1 << 28  # compared slice by slice, so a mismatch names its position
+    for k in range(0, n, step):
+        a = y[k:k + step].view(torch.int32)
+        b = expect[k:k + step].view(torch.int32)
+        bad = (a != b).nonzero()
+        if bad.numel():
+            i = k + int(bad[0])
+            raise AssertionError(f"{bad.numel()} of the elements [{k}, {k + a.numel()}) differ; first at {i}: "
+                                 f"decoded {float(y[i])} expected {float(expect[i])} (x = {float(x[i])})")
+
+
 # ----------------------------------------------------------------- ragged / edge sizes
 
 
