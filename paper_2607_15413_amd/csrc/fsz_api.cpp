@@ -654,7 +654,7 @@ fsz_status enqueue_batch(Workspace *ws, const fsz_job *jobs, size_t njobs, const
     if (!ok(hipMemcpyAsync(slot.d, slot.h, bytes, hipMemcpyHostToDevice, ws->stream))) return FSZ_ERR_DEVICE;
     if (++ws->call == 0) ++ws->call;
     const BatchArgs b = batch_args(L, slot.d, ws->call, ws->b_flags, ws->b_ticket, ws->b_stats, ws->b_partials);
-    if (!ok(launch_batch(b, L.aligned16, L.any_compress, shape, ws->stream))) return FSZ_ERR_DEVICE;
+    if (!ok(launch_batch(b, L.aligned16, L.any_compress, L.any_decompress, shape, ws->stream))) return FSZ_ERR_DEVICE;
     if (!ok(hipEventRecord(slot.ev, ws->stream))) return FSZ_ERR_DEVICE;
     slot.used = true;
     return FSZ_OK;
@@ -984,7 +984,8 @@ fsz_status fsz_plan_create(const fsz_job *jobs, size_t njobs, const fsz_tuning *
                                            p->d_partials);
             good = ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             if (good) {
-                const bool launched = ok(launch_batch(b, L.aligned16, L.any_compress, to_shape(t), cs));
+                const bool launched =
+                    ok(launch_batch(b, L.aligned16, L.any_compress, L.any_decompress, to_shape(t), cs));
                 const bool ended = ok(hipStreamEndCapture(cs, &p->graph));
                 good = launched && ended && ok(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
             }

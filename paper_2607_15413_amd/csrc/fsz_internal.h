@@ -175,8 +175,11 @@ inline bool cfg_supported(int block, int tile_blocks)
 hipError_t launch_range_base(const DecompressArgs &a, unsigned long long *range_base, unsigned long long *partials,
                              hipStream_t s);
 // Range pass + flag clear, per-job stats, then the batched kernel.
-hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, const BatchShape &shape,
-                        hipStream_t s);
+// Compress-only batches with 16-byte aligned inputs run a persistent
+// pipelined kernel, decompress-only batches a persistent decoder, mixed
+// batches one work item per workgroup.
+hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, bool any_decompress,
+                        const BatchShape &shape, hipStream_t s);
 bool batch_shape_supported(const BatchShape &shape);
 
 // Host-side argument checks shared by every entry point (fsz_api.cpp).

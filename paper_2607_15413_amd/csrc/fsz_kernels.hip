@@ -2034,6 +2034,210 @@ hipError_t launch_stats(const StatsArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ batched pipelined compression
+//
+// Compress-only batches with 16-byte aligned inputs: the pipeline of
+// compress_pipe2_kernel over the batch's work items.  Tickets are global item
+// ids in job order; every item in flight carries its job, whose arguments
+// (input, output, flag range, bound) come from the job table where they are
+// needed, so one pipeline runs across job boundaries.  Items of a job whose
+// bound does not resolve stay in the pipeline as empty items (no flags, no
+// stores); the job's last item reports its status.  Each job's bytes equal a
+// plain call's.
+
+struct BItem {
+    uint64_t t;    // global item id (>= total_chunks: none)
+    uint32_t job;  // job index (njobs: none)
+    uint64_t c;    // chunk index inside the job
+};
+
+__device__ __forceinline__ BItem batch_item(const BatchArgs &b, uint64_t t, uint32_t job)
+{
+    BItem it;
+    it.t = t;
+    it.job = t < b.total_chunks && job < b.njobs ? job : b.njobs;
+    it.c = it.job < b.njobs ? t - b.jobs[it.job].chunk_base : 0;
+    return it;
+}
+
+__device__ __forceinline__ BItem batch_item_of(const BatchArgs &b, uint64_t t)
+{
+    const uint32_t job = t < b.total_chunks ? __builtin_amdgcn_readfirstlane(find_job(b.chunk_end, b.njobs, t))
+                                            : b.njobs;
+    return batch_item(b, t, job);
+}
+
+template <int W>
+__device__ __forceinline__ void batch_fetch(const BatchArgs &b, const BItem &it, uint32_t *qb, int w, int lane)
+{
+    const BatchJob &J = b.jobs[it.job];
+    chunk_fetch<W>(batch_compress_args(b, it.job, J), it.c, qb, w, lane);
+}
+
+// Rate pass of item B (as compress_rates with DEFER), or an empty state and
+// the same barrier for an item whose job has no valid bound.
+template <int W>
+__device__ __forceinline__ ChunkState batch_rates(const BatchArgs &b, const BItem &it, int (&x)[32], int slot,
+                                                  CompressShared<W> &sh)
+{
+    const BatchJob &J = b.jobs[it.job];
+    const CompressArgs a = batch_compress_args(b, it.job, J);
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status == FSZ_OK) {
+        ChunkState cs = compress_rates<W, true>(a, R, it.c, x, slot, sh);
+        cs.chunk = it.c;
+        return cs;
+    }
+    ChunkState cs{};
+    cs.chunk = it.c;
+    if ((threadIdx.x & 63) == 0) sh.wave_total[slot][threadIdx.x >> 6] = 0;
+    lds_barrier();
+    return cs;
+}
+
+// One step of the batched pipeline: as pipe2_step, with A, B, C and the new
+// item each in its own job.
+template <bool W0, int W>
+__device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, uint64_t takes, const BItem &iA,
+                                                 const ChunkState &ca, int (&xa)[32], int sa, const BItem &iB,
+                                                 int (&yb)[32], ChunkState &cb, const BItem &iC, uint32_t *qb,
+                                                 uint32_t *pb, CompressShared<W> &sh, uint32_t &s_job, int w)
+{
+    const uint64_t N = b.total_chunks;
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 7;
+    const bool take = iC.t < N;
+    const BatchJob &JA = b.jobs[iA.job];
+    const CompressArgs aA = batch_compress_args(b, iA.job, JA);
+    const Resolved RA = resolve_bound(aA.stats, aA.mode, aA.value, aA.n);
+    const bool liveA = RA.status == FSZ_OK;
+    unsigned long long traw = 0, probe = 0;
+    if (W0) {
+        if (take && lane == 0) traw = atomicAdd(b.ticket, 1ull);
+        if (liveA) probe = lookback_probe(aA.flags, iA.c, aA.flag_epoch);
+    }
+    if (iB.t < N) cb = batch_rates<W>(b, iB, yb, sa ^ 1, sh);
+
+    // ---- lookback of A (wave 0), the new ticket and its job
+    uint32_t chunk_total = 0, wave_base = 0;
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+        if (k < w) wave_base += sh.wave_total[sa][k];
+        chunk_total += sh.wave_total[sa][k];
+    }
+    if (W0) {
+        const unsigned long long tk =
+            take ? ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(traw >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)traw)
+                 : N;
+        // the new item's job: the first window of job ends is loaded before
+        // the lookback waits, so its latency hides behind them
+        const uint32_t nj = b.njobs;
+        const uint64_t jend = tk < N ? b.chunk_end[min((uint32_t)lane, nj - 1)] : 0;
+        Prefix pre{0, false};
+        asm volatile("; probe %0" ::"v"(probe));
+        if (liveA) pre = lookback_wait(aA.flags, iA.c, aA.flag_epoch, chunk_total, false, true, probe);
+        uint32_t jobD = nj;
+        if (tk < N) {
+            const unsigned long long m = __ballot((uint32_t)lane < nj && jend <= tk);
+            jobD = m != ~0ull ? (uint32_t)__builtin_popcountll(m) : find_job(b.chunk_end, nj, tk);
+        }
+        if (lane == 0) {
+            if (take && tk == takes - 1)
+                __hip_atomic_store(b.ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh.base = pre.excl;
+            sh.ticket[0] = tk;
+            s_job = jobD;
+            if (iA.c == aA.nchunks - 1) {
+                if (liveA)
+                    finish_stream(aA, RA, pre, chunk_total);
+                else
+                    write_final(aA.final, 0, (uint32_t)RA.status, aA.epoch);
+            }
+        }
+    }
+    lds_barrier();
+    const uint64_t base = sh.base;
+    const BItem iD = batch_item(b, sh.ticket[0], s_job);
+
+    const uint64_t tile0 = iA.c * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
+    const bool ok = liveA && aA.data0 + base + chunk_total <= aA.capacity && tile0 < aA.ntiles;
+    if (ok) pipe2_stage<false>(ca, xa, pb);
+    if (iC.t < N) chunk_read(qb, lane, xa);
+    if (iD.t < N) {
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the read of qb is done before it is overwritten
+        batch_fetch<W>(b, iD, qb, w, lane);
+    }
+    if (liveA && ca.vm != 0)
+        aA.out[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
+    if (ok) {
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        wave_store_staged(reinterpret_cast<uint32_t *>(aA.out + aA.data0 + base + wave_base), pb,
+                          ca.wave_total >> 2, lane);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    return iD;
+}
+
+template <bool W0, int W>
+__device__ __forceinline__ void batch_pipe_run(const BatchArgs &b, CompressShared<W> &sh, uint32_t &s_job,
+                                               uint32_t *qb, uint32_t *pb, int w)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t N = b.total_chunks;
+    const uint64_t takes = N + gridDim.x;
+    int tslot = 0;
+    BItem iA = batch_item_of(b, next_ticket(b.ticket, takes, sh, tslot));
+    if (iA.t >= N) return;
+    batch_fetch<W>(b, iA, qb, w, lane);
+    BItem iB = batch_item_of(b, next_ticket(b.ticket, takes, sh, tslot));
+    int x[32], y[32];
+    chunk_read(qb, lane, x);
+    if (iB.t < N) {
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        batch_fetch<W>(b, iB, qb, w, lane);
+    }
+    ChunkState ca = batch_rates<W>(b, iA, x, 0, sh);
+    ChunkState cb = ca;
+    BItem iC = batch_item(b, N, b.njobs);
+    if (iB.t < N) {
+        iC = batch_item_of(b, next_ticket(b.ticket, takes, sh, tslot));
+        chunk_read(qb, lane, y);
+        if (iC.t < N) {
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            batch_fetch<W>(b, iC, qb, w, lane);
+        }
+    }
+    // loop invariant: A rate-passed in x (slot 0), B read into y, C in flight
+    for (;;) {
+        const BItem iD = batch_pipe_step<W0, W>(b, takes, iA, ca, x, 0, iB, y, cb, iC, qb, pb, sh, s_job, w);
+        if (iB.t >= N) return;
+        const BItem iE = batch_pipe_step<W0, W>(b, takes, iB, cb, y, 1, iC, x, ca, iD, qb, pb, sh, s_job, w);
+        if (iC.t >= N) return;
+        iA = iC;
+        iB = iD;
+        iC = iE;
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(W * 64) void batch_pipe_kernel(BatchArgs b)
+{
+    __shared__ CompressShared<W> sh;
+    __shared__ uint32_t s_job;
+    __shared__ __attribute__((aligned(16))) uint32_t inbuf[W * kPipeWaveDwords];
+    __shared__ __attribute__((aligned(16))) uint32_t stbuf[W * kPipeWaveDwords];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    uint32_t *qb = inbuf + w * kPipeWaveDwords;
+    uint32_t *pb = stbuf + w * kPipeWaveDwords;
+    if (w == 0)
+        batch_pipe_run<true, W>(b, sh, s_job, qb, pb, w);
+    else if (W > 1)
+        batch_pipe_run<false, W>(b, sh, s_job, qb, pb, w);
+}
+
 // ------------------------------------------------------------------ tile configurations
 //
 // The tile-configuration sweep of Sec. VI-C (Table V): blocks of B = 32 HB
@@ -2632,9 +2836,32 @@ static bool batch_lds_pad(K kernel, int groups, size_t *pad)
 }
 
 template <bool ALIGNED, int W>
-static hipError_t launch_batch_t(const BatchArgs &b, bool any_compress, int groups, hipStream_t s)
+static hipError_t launch_batch_t(const BatchArgs &b, bool any_compress, bool any_decompress, int groups,
+                                 hipStream_t s)
 {
     size_t pad = 0;
+    if (ALIGNED && any_compress && !any_decompress) {
+        // compression only, 16-byte aligned inputs: the persistent pipeline,
+        // one workgroup per CU at most (its LDS); a cap of 1 needs no pad
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_pipe_kernel<W>, W * 64, 0) != hipSuccess ||
+            cus <= 0 || per_cu <= 0) {
+            cus = 256;
+            per_cu = 1;
+        }
+        if (groups > 0 && groups < per_cu) {  // the cap is a hint: dropped where no pad can set it
+            if (batch_lds_pad(batch_pipe_kernel<W>, groups, &pad))
+                per_cu = groups;
+            else
+                pad = 0;
+        }
+        const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
+        const unsigned grid = (unsigned)(b.total_chunks < g ? b.total_chunks : g);
+        hipLaunchKernelGGL((batch_pipe_kernel<W>), dim3(grid), dim3(W * 64), pad, s, b);
+        return hipGetLastError();
+    }
     if (any_compress) {
         if (!batch_lds_pad(batch_kernel<ALIGNED, W>, groups, &pad)) return hipErrorInvalidValue;
         hipLaunchKernelGGL((batch_kernel<ALIGNED, W>), dim3((unsigned)b.total_chunks), dim3(W * 64), pad, s, b);
@@ -2669,8 +2896,8 @@ bool batch_shape_supported(const BatchShape &shape)
     }
 }
 
-hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, const BatchShape &shape,
-                        hipStream_t s)
+hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, bool any_decompress,
+                        const BatchShape &shape, hipStream_t s)
 {
     uint64_t grid = b.total_segs;
     const uint64_t clear = ceil_div(b.nflags, kStatsThreads);
@@ -2686,12 +2913,12 @@ hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, c
     if (e != hipSuccess) return e;
     if (b.total_chunks == 0) return hipSuccess;
     switch (shape.waves) {
-    case 2: return aligned16 ? launch_batch_t<true, 2>(b, any_compress, shape.groups_per_cu, s)
-                             : launch_batch_t<false, 2>(b, any_compress, shape.groups_per_cu, s);
-    case 4: return aligned16 ? launch_batch_t<true, 4>(b, any_compress, shape.groups_per_cu, s)
-                             : launch_batch_t<false, 4>(b, any_compress, shape.groups_per_cu, s);
-    case 8: return aligned16 ? launch_batch_t<true, 8>(b, any_compress, shape.groups_per_cu, s)
-                             : launch_batch_t<false, 8>(b, any_compress, shape.groups_per_cu, s);
+    case 2: return aligned16 ? launch_batch_t<true, 2>(b, any_compress, any_decompress, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 2>(b, any_compress, any_decompress, shape.groups_per_cu, s);
+    case 4: return aligned16 ? launch_batch_t<true, 4>(b, any_compress, any_decompress, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 4>(b, any_compress, any_decompress, shape.groups_per_cu, s);
+    case 8: return aligned16 ? launch_batch_t<true, 8>(b, any_compress, any_decompress, shape.groups_per_cu, s)
+                             : launch_batch_t<false, 8>(b, any_compress, any_decompress, shape.groups_per_cu, s);
     default: return hipErrorInvalidValue;
     }
 }

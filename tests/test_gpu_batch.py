@@ -235,6 +235,36 @@ def test_batch_per_job_errors_are_isolated():
     check_against_oracle(b, refs, "errors")
 
 
+def test_batch_compress_only_pipeline_errors():
+    """A batch whose every job compresses (16-byte aligned) runs the persistent
+    pipeline across job boundaries: jobs whose bound does not resolve pass
+    through it as empty items and report their status, jobs that run out of
+    capacity report it, and every other job's stream equals the oracle's."""
+    good = workloads.sinusoid_field(300_000, 31)
+    nan = good.copy()
+    nan[777] = np.nan
+    header_cap = 32 + (-(-good.size // 32) + 15) // 16 * 16
+    specs = [
+        ("c", good, fsz.FSZ_REL, 1e-3),
+        ("c", nan, fsz.FSZ_REL, 1e-3),
+        ("c", workloads.sinusoid_field(70_001, 32), fsz.FSZ_REL, 1e-2),
+        ("c", good, fsz.FSZ_ABS, 1e-12),             # bound below 8 ulp(max|x|)
+        ("c", np.zeros(0, np.float32), fsz.FSZ_REL, 1e-3),
+        ("c", good, fsz.FSZ_REL, 1e-4, header_cap),  # capacity: rate header only
+        ("c", workloads.grf_field((64, 64, 80), 33), fsz.FSZ_REL, 1e-4),
+        ("c", np.full(5000, 3.0, np.float32), fsz.FSZ_REL, 1e-3),
+        ("c", nan[:20000], fsz.FSZ_ABS, 1e-3),
+        ("c", good[:16385], fsz.FSZ_ABS, 1e-4),
+    ]
+    refs = oracle_refs(specs)
+    assert [r[0] for r in refs] == [0, 2, 0, 3, 0, 4, 0, 0, 2, 0]
+    for shape in [(2, 0), (4, 0), (8, 0), (8, 1), (4, 1)]:
+        announce(f"compress-only batch with per-job errors, shape {shape}")
+        b = DeviceBatch(specs)
+        b.run(shape)
+        check_against_oracle(b, refs, f"compress-only errors {shape}")
+
+
 def test_batch_decompress_only_persistent():
     """A batch whose every job decompresses runs the persistent decoder (the
     next item's size pass ahead of this item's decode): good streams of many
@@ -289,6 +319,31 @@ def test_plan_graph_replays():
             check_against_oracle(b, refs, f"replay {rep}")
         st, t = fsz.fsz_plan_get_tuning(plan)
         assert st == fsz.FSZ_OK and t == (4, 0)
+    finally:
+        fsz.fsz_plan_destroy(plan)
+
+
+def test_plan_graph_replays_compress_only():
+    """A captured compress-only batch (the persistent pipeline) replays
+    correctly, with eager work between the replays."""
+    fields = small_fields(10, 19)
+    specs = [("c", f.data, fsz.FSZ_REL, f.rel) for f in fields]
+    announce("plan: compress-only batch, graph capture + 3 replays")
+    refs = oracle_refs(specs)
+    b = DeviceBatch(specs)
+    st, plan = fsz.fsz_plan_create(b.jobs, (8, 0))
+    assert st == fsz.FSZ_OK, fsz.fsz_status_string(st)
+    try:
+        other = torch.from_numpy(workloads.sinusoid_field(100_000, 4)).to(_dev())
+        for rep in range(3):
+            b.clear_outputs()
+            out = torch.empty(fsz.fsz_compressed_bound(other.numel()), dtype=torch.uint8, device=_dev())
+            st_p, _ = fsz.fsz_compress(other.data_ptr(), other.numel(), fsz.FSZ_REL, 1e-3, out.data_ptr(),
+                                       out.numel(), _stream())
+            assert st_p == fsz.FSZ_OK
+            assert fsz.fsz_plan_launch(plan, _stream()) == fsz.FSZ_OK
+            torch.cuda.synchronize()
+            check_against_oracle(b, refs, f"compress-only replay {rep}")
     finally:
         fsz.fsz_plan_destroy(plan)
 
