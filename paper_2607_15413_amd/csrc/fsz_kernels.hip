@@ -2051,38 +2051,55 @@ struct BItem {
     uint64_t c;    // chunk index inside the job
 };
 
-__device__ __forceinline__ BItem batch_item(const BatchArgs &b, uint64_t t, uint32_t job)
+// Up to kPipeLdsJobs job records and their resolved bounds are copied to LDS
+// when the kernel starts, so that no step waits on global memory for its
+// items' arguments; larger batches read the job table and resolve per use.
+constexpr uint32_t kPipeLdsJobs = 96;
+
+struct JobView {
+    const BatchJob *jobs;  // LDS copy or the global table
+    const Resolved *bound; // LDS (null: resolve from the job's stats)
+};
+
+__device__ __forceinline__ Resolved job_bound(const BatchArgs &b, const JobView &v, uint32_t job, const BatchJob &J)
+{
+    if (v.bound) return v.bound[job];
+    return resolve_bound(b.stats + job, J.mode, J.value, J.n);
+}
+
+__device__ __forceinline__ BItem batch_item(const BatchArgs &b, const JobView &v, uint64_t t, uint32_t job)
 {
     BItem it;
     it.t = t;
     it.job = t < b.total_chunks && job < b.njobs ? job : b.njobs;
-    it.c = it.job < b.njobs ? t - b.jobs[it.job].chunk_base : 0;
+    it.c = it.job < b.njobs ? t - v.jobs[it.job].chunk_base : 0;
     return it;
 }
 
-__device__ __forceinline__ BItem batch_item_of(const BatchArgs &b, uint64_t t)
+__device__ __forceinline__ BItem batch_item_of(const BatchArgs &b, const JobView &v, uint64_t t)
 {
     const uint32_t job = t < b.total_chunks ? __builtin_amdgcn_readfirstlane(find_job(b.chunk_end, b.njobs, t))
                                             : b.njobs;
-    return batch_item(b, t, job);
+    return batch_item(b, v, t, job);
 }
 
 template <int W>
-__device__ __forceinline__ void batch_fetch(const BatchArgs &b, const BItem &it, uint32_t *qb, int w, int lane)
+__device__ __forceinline__ void batch_fetch(const BatchArgs &b, const JobView &v, const BItem &it, uint32_t *qb,
+                                            int w, int lane)
 {
-    const BatchJob &J = b.jobs[it.job];
+    const BatchJob &J = v.jobs[it.job];
     chunk_fetch<W>(batch_compress_args(b, it.job, J), it.c, qb, w, lane);
 }
 
 // Rate pass of item B (as compress_rates with DEFER), or an empty state and
 // the same barrier for an item whose job has no valid bound.
 template <int W>
-__device__ __forceinline__ ChunkState batch_rates(const BatchArgs &b, const BItem &it, int (&x)[32], int slot,
-                                                  CompressShared<W> &sh)
+__device__ __forceinline__ ChunkState batch_rates(const BatchArgs &b, const JobView &v, const BItem &it,
+                                                  int (&x)[32], int slot, CompressShared<W> &sh)
 {
-    const BatchJob &J = b.jobs[it.job];
+    const BatchJob &J = v.jobs[it.job];
     const CompressArgs a = batch_compress_args(b, it.job, J);
-    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    const Resolved R = job_bound(b, v, it.job, J);
     if (R.status == FSZ_OK) {
         ChunkState cs = compress_rates<W, true>(a, R, it.c, x, slot, sh);
         cs.chunk = it.c;
@@ -2098,25 +2115,26 @@ __device__ __forceinline__ ChunkState batch_rates(const BatchArgs &b, const BIte
 // One step of the batched pipeline: as pipe2_step, with A, B, C and the new
 // item each in its own job.
 template <bool W0, int W>
-__device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, uint64_t takes, const BItem &iA,
-                                                 const ChunkState &ca, int (&xa)[32], int sa, const BItem &iB,
-                                                 int (&yb)[32], ChunkState &cb, const BItem &iC, uint32_t *qb,
-                                                 uint32_t *pb, CompressShared<W> &sh, uint32_t &s_job, int w)
+__device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, const JobView &v, uint64_t takes,
+                                                 const BItem &iA, const ChunkState &ca, int (&xa)[32], int sa,
+                                                 const BItem &iB, int (&yb)[32], ChunkState &cb, const BItem &iC,
+                                                 uint32_t *qb, uint32_t *pb, CompressShared<W> &sh,
+                                                 uint32_t &s_job, int w)
 {
     const uint64_t N = b.total_chunks;
     const int lane = threadIdx.x & 63;
     const int j = lane & 7;
     const bool take = iC.t < N;
-    const BatchJob &JA = b.jobs[iA.job];
+    const BatchJob &JA = v.jobs[iA.job];
     const CompressArgs aA = batch_compress_args(b, iA.job, JA);
-    const Resolved RA = resolve_bound(aA.stats, aA.mode, aA.value, aA.n);
+    const Resolved RA = job_bound(b, v, iA.job, JA);
     const bool liveA = RA.status == FSZ_OK;
     unsigned long long traw = 0, probe = 0;
     if (W0) {
         if (take && lane == 0) traw = atomicAdd(b.ticket, 1ull);
         if (liveA) probe = lookback_probe(aA.flags, iA.c, aA.flag_epoch);
     }
-    if (iB.t < N) cb = batch_rates<W>(b, iB, yb, sa ^ 1, sh);
+    if (iB.t < N) cb = batch_rates<W>(b, v, iB, yb, sa ^ 1, sh);
 
     // ---- lookback of A (wave 0), the new ticket and its job
     uint32_t chunk_total = 0, wave_base = 0;
@@ -2158,7 +2176,7 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, uint64_t ta
     }
     lds_barrier();
     const uint64_t base = sh.base;
-    const BItem iD = batch_item(b, sh.ticket[0], s_job);
+    const BItem iD = batch_item(b, v, sh.ticket[0], s_job);
 
     const uint64_t tile0 = iA.c * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     const bool ok = liveA && aA.data0 + base + chunk_total <= aA.capacity && tile0 < aA.ntiles;
@@ -2166,7 +2184,7 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, uint64_t ta
     if (iC.t < N) chunk_read(qb, lane, xa);
     if (iD.t < N) {
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the read of qb is done before it is overwritten
-        batch_fetch<W>(b, iD, qb, w, lane);
+        batch_fetch<W>(b, v, iD, qb, w, lane);
     }
     if (liveA && ca.vm != 0)
         aA.out[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
@@ -2182,39 +2200,39 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, uint64_t ta
 }
 
 template <bool W0, int W>
-__device__ __forceinline__ void batch_pipe_run(const BatchArgs &b, CompressShared<W> &sh, uint32_t &s_job,
-                                               uint32_t *qb, uint32_t *pb, int w)
+__device__ __forceinline__ void batch_pipe_run(const BatchArgs &b, const JobView &v, CompressShared<W> &sh,
+                                               uint32_t &s_job, uint32_t *qb, uint32_t *pb, int w)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t N = b.total_chunks;
     const uint64_t takes = N + gridDim.x;
     int tslot = 0;
-    BItem iA = batch_item_of(b, next_ticket(b.ticket, takes, sh, tslot));
+    BItem iA = batch_item_of(b, v, next_ticket(b.ticket, takes, sh, tslot));
     if (iA.t >= N) return;
-    batch_fetch<W>(b, iA, qb, w, lane);
-    BItem iB = batch_item_of(b, next_ticket(b.ticket, takes, sh, tslot));
+    batch_fetch<W>(b, v, iA, qb, w, lane);
+    BItem iB = batch_item_of(b, v, next_ticket(b.ticket, takes, sh, tslot));
     int x[32], y[32];
     chunk_read(qb, lane, x);
     if (iB.t < N) {
         __builtin_amdgcn_s_waitcnt(0xC07F);
-        batch_fetch<W>(b, iB, qb, w, lane);
+        batch_fetch<W>(b, v, iB, qb, w, lane);
     }
-    ChunkState ca = batch_rates<W>(b, iA, x, 0, sh);
+    ChunkState ca = batch_rates<W>(b, v, iA, x, 0, sh);
     ChunkState cb = ca;
-    BItem iC = batch_item(b, N, b.njobs);
+    BItem iC = batch_item(b, v, N, b.njobs);
     if (iB.t < N) {
-        iC = batch_item_of(b, next_ticket(b.ticket, takes, sh, tslot));
+        iC = batch_item_of(b, v, next_ticket(b.ticket, takes, sh, tslot));
         chunk_read(qb, lane, y);
         if (iC.t < N) {
             __builtin_amdgcn_s_waitcnt(0xC07F);
-            batch_fetch<W>(b, iC, qb, w, lane);
+            batch_fetch<W>(b, v, iC, qb, w, lane);
         }
     }
     // loop invariant: A rate-passed in x (slot 0), B read into y, C in flight
     for (;;) {
-        const BItem iD = batch_pipe_step<W0, W>(b, takes, iA, ca, x, 0, iB, y, cb, iC, qb, pb, sh, s_job, w);
+        const BItem iD = batch_pipe_step<W0, W>(b, v, takes, iA, ca, x, 0, iB, y, cb, iC, qb, pb, sh, s_job, w);
         if (iB.t >= N) return;
-        const BItem iE = batch_pipe_step<W0, W>(b, takes, iB, cb, y, 1, iC, x, ca, iD, qb, pb, sh, s_job, w);
+        const BItem iE = batch_pipe_step<W0, W>(b, v, takes, iB, cb, y, 1, iC, x, ca, iD, qb, pb, sh, s_job, w);
         if (iC.t >= N) return;
         iA = iC;
         iB = iD;
@@ -2229,13 +2247,27 @@ __global__ __launch_bounds__(W * 64) void batch_pipe_kernel(BatchArgs b)
     __shared__ uint32_t s_job;
     __shared__ __attribute__((aligned(16))) uint32_t inbuf[W * kPipeWaveDwords];
     __shared__ __attribute__((aligned(16))) uint32_t stbuf[W * kPipeWaveDwords];
+    __shared__ __attribute__((aligned(16))) BatchJob ljobs[kPipeLdsJobs];
+    __shared__ Resolved lbound[kPipeLdsJobs];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     uint32_t *qb = inbuf + w * kPipeWaveDwords;
     uint32_t *pb = stbuf + w * kPipeWaveDwords;
+    JobView v{b.jobs, nullptr};
+    if (b.njobs <= kPipeLdsJobs) {  // job records and resolved bounds to LDS
+        for (uint32_t k = threadIdx.x; k < b.njobs * (uint32_t)(sizeof(BatchJob) / 16); k += blockDim.x)
+            reinterpret_cast<u32x4 *>(ljobs)[k] = reinterpret_cast<const u32x4 *>(b.jobs)[k];
+        for (uint32_t k = threadIdx.x; k < b.njobs; k += blockDim.x) {
+            const BatchJob &J = b.jobs[k];
+            lbound[k] = J.op == FSZ_OP_COMPRESS ? resolve_bound(b.stats + k, J.mode, J.value, J.n)
+                                                : Resolved{1.0f, 1.0f, 0u, FSZ_ERR_INVALID_ARG};
+        }
+        v = JobView{ljobs, lbound};
+        lds_barrier();
+    }
     if (w == 0)
-        batch_pipe_run<true, W>(b, sh, s_job, qb, pb, w);
+        batch_pipe_run<true, W>(b, v, sh, s_job, qb, pb, w);
     else if (W > 1)
-        batch_pipe_run<false, W>(b, sh, s_job, qb, pb, w);
+        batch_pipe_run<false, W>(b, v, sh, s_job, qb, pb, w);
 }
 
 // ------------------------------------------------------------------ tile configurations
