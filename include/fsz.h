@@ -234,10 +234,13 @@ fsz_status fsz_decompress_config_async(const void *d_cmp, size_t cmp_size, float
  * that the plain call with the same arguments produces; only the launch
  * differs.  A batch runs as three kernels on the stream: a segmented
  * value-range pass over all compress jobs, a per-job fold of that pass, and
- * one kernel whose workgroups take (job, chunk) work items from a single
- * ticket counter in job order, each chunk following Sec. III-A steps 1-5
- * (compress) or decompression steps 1-5, with one decoupled-lookback chain
- * (Sec. IV-D) per job.
+ * one kernel that takes (job, chunk) work items from a single ticket counter
+ * in job order, each chunk following Sec. III-A steps 1-5 (compress) or
+ * decompression steps 1-5, with one decoupled-lookback chain (Sec. IV-D) per
+ * job.  That kernel is a persistent pipeline (the single-field kernels'
+ * prefetch and overlap, across job boundaries) when every job compresses
+ * from a 16-byte aligned input or every job decompresses, and one work item
+ * per workgroup otherwise.
  *
  * Jobs of one batch must not write memory that another job of the same batch
  * reads or writes.  Per-job errors (non-finite input, bound too small,
@@ -263,7 +266,9 @@ typedef struct {
  * workgroup owns 8 tiles per wave); groups_per_cu caps resident workgroups
  * per CU through extra LDS (0 = no cap, else 1..8; a cap that the kernel's
  * own LDS or the device's per-workgroup LDS limit makes void or impossible
- * is rejected as FSZ_ERR_INVALID_ARG).  Neither changes any output byte. */
+ * is rejected as FSZ_ERR_INVALID_ARG; the pipelined compress-only kernel,
+ * whose own LDS already allows few workgroups per CU, treats such a cap as
+ * no cap).  Neither changes any output byte. */
 typedef struct {
     int waves_per_group;
     int groups_per_cu;
