@@ -154,12 +154,12 @@ hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged
 // (a.nchunks counts chunks of kTilesPerChunk tiles).
 hipError_t launch_compress_naive(const CompressArgs &a, const NaiveTables &t, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s);
-// Tile configurations (Sec. VI-C): one chunk of 4 x 64 32-element segments per
+// Tile configurations (Sec. VI-C): one chunk of kCfgWaves x 64 32-element segments per
 // workgroup (a.nchunks counts those), block in {32, 64}, tile_blocks in {4, 8, 16}.
 hipError_t launch_compress_cfg(const CompressArgs &a, int block, int tile_blocks, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
                                  hipStream_t s);
-constexpr int kCfgWaves = 4;
+constexpr int kCfgWaves = 16;
 constexpr int kCfgChunkSegs = kCfgWaves * 64;
 // header flags bits 2-4 of a tile configuration (0 for B 32, T 8)
 inline uint32_t cfg_flag_bits(int block, int tile_blocks)
