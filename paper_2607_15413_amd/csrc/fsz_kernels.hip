@@ -141,6 +141,23 @@ __device__ __forceinline__ void wave_store_staged(uint32_t *g, const uint32_t *s
     if ((uint32_t)lane < nw - t0) g[t0 + lane] = st[t0 + lane];
 }
 
+// As wave_store_staged, for a staging area laid out at the same 16-byte
+// phase as g (st + head is 16-byte aligned): the body is read with one
+// 16-byte LDS read per lane (consecutive lanes, consecutive 16 bytes), free of
+// bank conflicts.
+__device__ __forceinline__ void wave_store_staged_phased(uint32_t *g, const uint32_t *st, uint32_t nw, int lane)
+{
+    const uint32_t head = min(nw, ((16u - ((uint32_t)(uintptr_t)g & 15u)) & 15u) >> 2);
+    if ((uint32_t)lane < head) g[lane] = st[lane];
+    const uint32_t nq = (nw - head) >> 2;
+    for (uint32_t q = lane; q < nq; q += 64) {
+        const uint32_t o = head + 4 * q;
+        *reinterpret_cast<u32x4 *>(g + o) = *reinterpret_cast<const u32x4 *>(st + o);
+    }
+    const uint32_t t0 = head + 4 * nq;
+    if ((uint32_t)lane < nw - t0) g[t0 + lane] = st[t0 + lane];
+}
+
 __device__ __forceinline__ uint32_t uabs(int v) { return v < 0 ? 0u - (uint32_t)v : (uint32_t)v; }
 
 // number of significant bits = ceil(log2(v + 1)) (the rate of Sec. IV-A)
@@ -1223,7 +1240,7 @@ __global__ __launch_bounds__(kThreads) void naive_encode_kernel(CompressArgs a, 
 // lane-per-block reads (lane b reads piece m at step m) are free of bank
 // conflicts.
 
-constexpr int kPipeWaveDwords = 2056;  // 8 tiles of input, or the wave's output (<= 8 x 1028 B)
+constexpr int kPipeWaveDwords = 2060;  // 8 tiles of input, or the wave's output (<= 8 x 1028 B) at a 16-byte phase
 typedef __attribute__((address_space(3))) void lds_void;
 
 // Input of the wave's 8 tiles (element e0 onward, all in bounds) -> LDS.
@@ -1395,7 +1412,9 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
     }
     const uint64_t tile0 = ca.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     const bool ok = a.data0 + base + chunk_total <= a.capacity && tile0 < a.ntiles;
-    if (ok) pipe2_stage<FEAT>(ca, xa, pb);
+    uint32_t *wave_out = reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base);
+    uint32_t *ps = pb + (((uint32_t)(uintptr_t)wave_out >> 2) & 3u);  // staging at the output's 16-byte phase
+    if (ok) pipe2_stage<FEAT>(ca, xa, ps);
     if (C < a.nchunks) chunk_read(qb, lane, xa);
     if (D < a.nchunks) {
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the read of qb is done before it is overwritten
@@ -1406,8 +1425,7 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
     if (ok) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        wave_store_staged(reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base), pb, ca.wave_total >> 2,
-                          lane);
+        wave_store_staged_phased(wave_out, ps, ca.wave_total >> 2, lane);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
@@ -2180,7 +2198,9 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, const JobVi
 
     const uint64_t tile0 = iA.c * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
     const bool ok = liveA && aA.data0 + base + chunk_total <= aA.capacity && tile0 < aA.ntiles;
-    if (ok) pipe2_stage<false>(ca, xa, pb);
+    uint32_t *wave_out = reinterpret_cast<uint32_t *>(aA.out + aA.data0 + base + wave_base);
+    uint32_t *ps = pb + (((uint32_t)(uintptr_t)wave_out >> 2) & 3u);  // staging at the output's 16-byte phase
+    if (ok) pipe2_stage<false>(ca, xa, ps);
     if (iC.t < N) chunk_read(qb, lane, xa);
     if (iD.t < N) {
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the read of qb is done before it is overwritten
@@ -2191,8 +2211,7 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, const JobVi
     if (ok) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        wave_store_staged(reinterpret_cast<uint32_t *>(aA.out + aA.data0 + base + wave_base), pb,
-                          ca.wave_total >> 2, lane);
+        wave_store_staged_phased(wave_out, ps, ca.wave_total >> 2, lane);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
