@@ -694,8 +694,8 @@ def parse_args():
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in the design notes but not launched.",
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is a design only, never launched.",
               file=sys.stderr, flush=True)
         sys.exit(2)
     if args.served:
