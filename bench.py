@@ -791,6 +791,26 @@ def main():
         check(st, f"decompress result rel={RELS[k]}")
         sizes.append(int(size))
 
+    # cold decompress: the 256 MB MALL refilled by a read of a 1 GiB buffer
+    # (clean lines, nothing to write back) before each timed call, so the
+    # stream is read from HBM (in the step, decompression follows the
+    # compression that wrote the stream, which may still be cached)
+    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dec_cold_ms = []
+    for k in range(len(RELS)):
+        t = []
+        for _ in range(3):
+            flush.sum()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record(stream)
+            check(fsz.fsz_decompress_async(outs[k].data_ptr(), sizes[k], y.data_ptr(), n, dres[k].data_ptr(), sh),
+                  "decompress")
+            e[1].record(stream)
+            torch.cuda.synchronize()
+            t.append(e[0].elapsed_time(e[1]))
+        dec_cold_ms.append(float(np.median(t)))
+    del flush
+
     # pointwise error of every bound's reconstruction, relative to eb
     st_np = stats.cpu().numpy().view(np.float32)
     span = float(st_np[1]) - float(st_np[0])
@@ -815,6 +835,8 @@ def main():
             "decompress_ms": round(dec_ms[k], 4),
             "compress_hbm_frac": round(alg / comp_ms[k] / 1e6 / HBM_PEAK_GBPS, 4),
             "decompress_hbm_frac": round(alg / dec_ms[k] / 1e6 / HBM_PEAK_GBPS, 4),
+            "decompress_cold_ms": round(dec_cold_ms[k], 4),
+            "decompress_cold_GBps": round(4 * n / dec_cold_ms[k] / 1e6, 1),
         })
         comp_bytes += alg
         dec_bytes += alg

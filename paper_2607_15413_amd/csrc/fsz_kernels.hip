@@ -1240,10 +1240,13 @@ __global__ __launch_bounds__(kThreads) void naive_encode_kernel(CompressArgs a, 
 // lane-per-block reads (lane b reads piece m at step m) are free of bank
 // conflicts.
 
+constexpr int kCachePolicyNT = 2;  // cache-policy operand of the LDS copies: nontemporal
 constexpr int kPipeWaveDwords = 2060;  // 8 tiles of input, or the wave's output (<= 8 x 1028 B) at a 16-byte phase
 typedef __attribute__((address_space(3))) void lds_void;
 
 // Input of the wave's 8 tiles (element e0 onward, all in bounds) -> LDS.
+// The copies carry the nontemporal hint: the input is read once, and without
+// the hint it displaces cached data, among it the stream just written.
 __device__ __forceinline__ void chunk_copy_async(const float *__restrict__ x, uint64_t e0, uint32_t *wbuf, int lane)
 {
 #pragma unroll
@@ -1251,7 +1254,7 @@ __device__ __forceinline__ void chunk_copy_async(const float *__restrict__ x, ui
         const int b = 8 * k + (lane >> 3);
         const int m = ((lane & 7) - b) & 7;
         __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(x + e0 + 32 * b + 4 * m),
-                                         (lds_void *)(wbuf + 256 * k), 16, 0, 0);
+                                         (lds_void *)(wbuf + 256 * k), 16, 0, kCachePolicyNT);
     }
 }
 
