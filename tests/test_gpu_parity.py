@@ -28,19 +28,21 @@ def announce(name):
     print(f"\n[case] {name}", flush=True)
 
 
-def gpu_compress(x, mode, value, capacity=None, in_offset=0):
-    """Compress numpy float32 x on the GPU; returns (status, bytes or None)."""
+def gpu_compress(x, mode, value, capacity=None, in_offset=0, out_offset=0):
+    """Compress numpy float32 x on the GPU; returns (status, bytes or None).
+    in_offset / out_offset shift the input / output pointers by that many
+    4-byte words from a 256-byte aligned allocation."""
     n = x.size
     xd = torch.zeros(n + in_offset + 4, dtype=torch.float32, device=_dev())
     if n:
         xd[in_offset:in_offset + n] = torch.from_numpy(x).to(_dev())
     cap = fsz.fsz_compressed_bound(n) if capacity is None else capacity
-    out = torch.zeros(max(cap, 1), dtype=torch.uint8, device=_dev())
-    st, size = fsz.fsz_compress(xd.data_ptr() + 4 * in_offset, n, mode, value, out.data_ptr(), cap,
-                                _stream())
+    out = torch.zeros(max(cap, 1) + 4 * out_offset, dtype=torch.uint8, device=_dev())
+    st, size = fsz.fsz_compress(xd.data_ptr() + 4 * in_offset, n, mode, value, out.data_ptr() + 4 * out_offset,
+                                cap, _stream())
     if st != fsz.FSZ_OK:
         return st, None
-    return st, out[:size].cpu().numpy().tobytes()
+    return st, out[4 * out_offset:4 * out_offset + size].cpu().numpy().tobytes()
 
 
 def gpu_decompress(stream_bytes, n, out_offset=0):
@@ -192,6 +194,20 @@ def test_edge_sizes(n):
     x = workloads.sinusoid_field(n, n + 7)
     check_round_trip("edge", x, fsz.FSZ_REL, 1e-3)
     check_round_trip("edge-abs", x, fsz.FSZ_ABS, 1e-4)
+
+
+def test_compress_output_offsets():
+    """Aligned input (the pipelined kernel) into outputs at every 4-byte
+    phase of a 16-byte line: the staging area follows the destination's
+    phase, so each phase must give the oracle's bytes."""
+    x = workloads.grf_field((64, 64, 80), 11)
+    for rel in (1e-2, 1e-4):
+        ref = oracle.compress(x, oracle.REL, rel)
+        for off in (1, 2, 3):
+            announce(f"compress output offset {off} words, REL {rel:g}")
+            st, got = gpu_compress(x, fsz.FSZ_REL, rel, out_offset=off)
+            assert st == fsz.FSZ_OK
+            assert got == ref, first_diff(got, ref)
 
 
 def test_unaligned_pointers():
