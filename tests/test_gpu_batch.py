@@ -35,10 +35,12 @@ class DeviceBatch:
 
     spec ("c", x, mode, value[, capacity]) compresses numpy float32 x;
     spec ("d", stream_bytes, n) decompresses a stream into n floats.
-    offset > 0 shifts every device pointer by that many 4-byte words.
+    offset > 0 shifts every device pointer by that many 4-byte words;
+    out_offset (default: offset) shifts the compress outputs alone.
     """
 
-    def __init__(self, specs, offset=0):
+    def __init__(self, specs, offset=0, out_offset=None):
+        oo = offset if out_offset is None else out_offset
         dev = _dev()
         self.specs = specs
         self.res = torch.zeros((max(len(specs), 1), 4), dtype=torch.int32, device=dev)
@@ -52,11 +54,11 @@ class DeviceBatch:
                 xs = torch.zeros(n + offset + 4, dtype=torch.float32, device=dev)
                 if n:
                     xs[offset:offset + n] = torch.from_numpy(x).to(dev)
-                out = torch.full((cap + 4 * offset + 16,), 0xA5, dtype=torch.uint8, device=dev)
+                out = torch.full((cap + 4 * oo + 16,), 0xA5, dtype=torch.uint8, device=dev)
                 self.src.append(xs)
                 self.dst.append(out)
                 self.jobs.append(fsz.compress_job(xs.data_ptr() + 4 * offset, n, mode, value,
-                                                  out.data_ptr() + 4 * offset, cap, rp))
+                                                  out.data_ptr() + 4 * oo, cap, rp))
             else:
                 data, n = s[1], s[2]
                 buf = torch.zeros(len(data) + 4 * offset + 16, dtype=torch.uint8, device=dev)
@@ -69,6 +71,7 @@ class DeviceBatch:
                 self.jobs.append(fsz.decompress_job(buf.data_ptr() + 4 * offset, len(data),
                                                     out.data_ptr() + 4 * offset, n, rp))
         self.offset = offset
+        self.out_offset = oo
 
     def run(self, tuning=None):
         st = fsz.fsz_batch_async(self.jobs, tuning, _stream())
@@ -89,7 +92,7 @@ class DeviceBatch:
         if st != fsz.FSZ_OK:
             return st, None
         if s[0] == "c":
-            o = 4 * self.offset
+            o = 4 * self.out_offset
             return st, self.dst[k][o:o + size].cpu().numpy().tobytes()
         n = s[2]
         return st, self.dst[k][self.offset:self.offset + n].cpu().numpy()
@@ -263,6 +266,19 @@ def test_batch_compress_only_pipeline_errors():
         b = DeviceBatch(specs)
         b.run(shape)
         check_against_oracle(b, refs, f"compress-only errors {shape}")
+
+
+def test_batch_compress_only_output_offsets():
+    """Compress-only batch with aligned inputs (the pipelined kernel) writing
+    to outputs at every 4-byte phase of a 16-byte line."""
+    fields = small_fields(12, 23)
+    specs = [("c", f.data, fsz.FSZ_REL, f.rel) for f in fields]
+    refs = oracle_refs(specs)
+    for oo in (1, 2, 3):
+        announce(f"compress-only batch, outputs shifted by {oo} words")
+        b = DeviceBatch(specs, offset=0, out_offset=oo)
+        b.run((8, 0))
+        check_against_oracle(b, refs, f"output offset {oo}")
 
 
 def test_batch_decompress_only_persistent():
