@@ -229,3 +229,83 @@ def test_config_full_size_grf_512(config):
     assert int(res.cpu()[1]) & 0xFFFFFFFF == fsz.FSZ_OK
     y = out.cpu().numpy()
     assert np.array_equal(y.view(np.uint32), fmt.closed_form(x, E, inv).view(np.uint32))
+
+
+def _tile_sizes_np(s, n, B, T):
+    """Per-tile data bytes from the rate header (vectorised form of the
+    per-tile sum in fsz_format: a block costs (B/8)(1 + r) bytes when r > 0,
+    a centred tile 4 more)."""
+    rb = np.frombuffer(s, dtype=np.uint8, count=fmt.ceil_div(n, B), offset=fmt.HEADER)
+    nt = fmt.ceil_div(n, B * T)
+    r = np.zeros(nt * T, dtype=np.int64)
+    r[:rb.size] = rb & 0x1F
+    cost = np.where(r > 0, (B // 8) * (1 + r), 0).reshape(nt, T).sum(axis=1)
+    return cost + 4 * ((rb[::T].astype(np.int64) >> 6) & 1)
+
+
+def test_config_stream_beyond_4gib():
+    """64-bit sizes and offsets in the configuration kernels: 2^31 + 4099
+    uniform values at REL 1e-6 in 64 x 16 tiles give a stream of about 5.7
+    GB.  The rate header sums to the stream's size; the first and the last
+    1024 tiles (the last ones stored beyond 2^32 bytes) equal the oracle's
+    streams of the same elements; the decode equals the closed form
+    fl(rint(fl(x * inv)) * E) over the whole field."""
+    B, T = 64, 16
+    n = (1 << 31) + 4099
+    rng = np.random.default_rng(19)
+    x = rng.random(n, dtype=np.float32)
+    x *= 2
+    x -= 1
+    rel = 1e-6
+    announce(f"config {(B, T)} stream beyond 4 GiB: uniform n={n} REL {rel:g}")
+    xd = torch.from_numpy(x).to(_dev())
+    st, s = gpu_compress_config(x, oracle.REL, rel, (B, T), device_x=xd)
+    assert st == fsz.FSZ_OK and len(s) > (1 << 32)
+    hdr = fmt.parse_header(s)
+    assert hdr["total"] == len(s) and fmt.header_config(hdr["flags"]) == (B, T)
+    E = float(hdr["E"])
+    sizes = _tile_sizes_np(s, n, B, T)
+    d0 = fmt.data_start(n, B)
+    assert d0 + int(sizes.sum()) == len(s)
+    te = B * T
+    nt = sizes.size
+    for first in (0, nt - 1024):
+        lo, hi = first * te, min(n, (first + 1024) * te)
+        xs = x[lo:hi]
+        # an ABS bound of E/2 + 4 ulp(max|xs|) resolves to the same step E
+        u = float(np.spacing(np.float32(np.abs(xs).max())))
+        ref = oracle.compress(xs, oracle.ABS, E / 2 + 4 * u, config=(B, T))
+        assert fmt.parse_header(ref)["E"] == hdr["E"]
+        nb = fmt.ceil_div(hi - lo, B)
+        assert s[32 + lo // B:32 + lo // B + nb] == ref[32:32 + nb], f"rate bytes of tiles from {first}"
+        at = d0 + int(sizes[:first].sum())
+        body = int(sizes[first:first + 1024].sum())
+        if first:
+            assert at > (1 << 32)
+        ds = fmt.data_start(hi - lo, B)
+        assert len(ref) == ds + body
+        assert s[at:at + body] == ref[ds:], f"data of tiles from {first}"
+    announce(f"config {(B, T)} stream beyond 4 GiB: decode of {len(s)} bytes")
+    buf = torch.from_numpy(np.frombuffer(s, dtype=np.uint8).copy()).to(_dev())
+    del s
+    y = torch.empty(n, dtype=torch.float32, device=_dev())
+    res = torch.zeros(2, dtype=torch.int64, device=_dev())
+    assert fsz.fsz_decompress_config_async(buf.data_ptr(), buf.numel(), y.data_ptr(), n, B, T, res.data_ptr(),
+                                           _stream()) == fsz.FSZ_OK
+    torch.cuda.synchronize()
+    assert int(res.cpu()[1]) & 0xFFFFFFFF == fsz.FSZ_OK
+    del buf
+    inv = np.float32(1) / np.float32(E)
+    q = torch.round(xd * float(inv)).to(torch.int32)  # zero as +0 whatever the product's sign
+    del xd
+    expect = q.to(torch.float32) * E
+    del q
+    step = 1 << 28
+    for k in range(0, n, step):
+        a = y[k:k + step].view(torch.int32)
+        b = expect[k:k + step].view(torch.int32)
+        bad = (a != b).nonzero()
+        if bad.numel():
+            i = k + int(bad[0])
+            raise AssertionError(f"{bad.numel()} of the elements [{k}, {k + a.numel()}) differ; first at {i}: "
+                                 f"decoded {float(y[i])} expected {float(expect[i])} (x = {float(x[i])})")
