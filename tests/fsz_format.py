@@ -84,6 +84,17 @@ def tile_sizes(s: bytes, n: int, B=BLOCK, T=8):
     return [sum(block_cost(r, B) for r in rates) + 4 * c for (_, c, rates) in tile_choices(s, n, B, T)]
 
 
+def tile_sizes_np(s: bytes, n: int, B=BLOCK, T=8) -> np.ndarray:
+    """tile_sizes as one int64 array, computed with array operations (for
+    rate headers of millions of tiles)."""
+    rb = np.frombuffer(s, dtype=np.uint8, count=ceil_div(n, B), offset=HEADER)
+    nt = ceil_div(n, B * T)
+    r = np.zeros(nt * T, dtype=np.int64)
+    r[:rb.size] = rb & 0x1F
+    cost = np.where(r > 0, (B // 8) * (1 + r), 0).reshape(nt, T).sum(axis=1)
+    return cost + 4 * ((rb[::T].astype(np.int64) >> 6) & 1)
+
+
 def quantize(x: np.ndarray, inv: float) -> np.ndarray:
     """q = rint(fl32(x * inv)) in binary32, as int64."""
     y = (np.asarray(x, dtype=np.float32) * np.float32(inv)).astype(np.float32)

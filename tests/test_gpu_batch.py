@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from paper_2607_15413_amd import fsz, workloads
+from tests import fsz_format as fmt
 
 pytestmark = pytest.mark.gpu
 
@@ -396,3 +397,83 @@ def test_batch_64_fields_full_sizes():
     db = DeviceBatch(dspecs)
     db.run()
     check_against_oracle(db, drefs, "64 fields decompress")
+
+
+def test_batch_stream_beyond_4gib():
+    """64-bit offsets in the batched kernels: a ragged small field, 2^31 +
+    4099 uniform values at REL 1e-6 (a stream of about 5.7 GB) and another
+    small field, compressed in one launch (the pipelined kernel) and
+    decompressed in another (the persistent decoder).  The small jobs
+    against the oracle; for the large job, the rate header sums to the
+    stream's size, the first and the last 4096 tiles (the last ones stored
+    beyond 2^32 bytes) equal the oracle's streams of the same elements, and
+    the decode equals the closed form fl(rint(fl(x * inv)) * E)."""
+    small = small_fields(2, 21)
+    n = (1 << 31) + 4099
+    rng = np.random.default_rng(23)
+    x = rng.random(n, dtype=np.float32)
+    x *= 2
+    x -= 1
+    rel = 1e-6
+    specs = [("c", small[0].data, fsz.FSZ_REL, small[0].rel), ("c", x, fsz.FSZ_REL, rel),
+             ("c", small[1].data, fsz.FSZ_REL, small[1].rel)]
+    announce(f"batch with a stream beyond 4 GiB: jobs of {[s[1].size for s in specs]} elements, compress")
+    b = DeviceBatch(specs)
+    b.run()
+    for k in (0, 2):
+        st, got = b.output(k)
+        assert st == fsz.FSZ_OK and got == oracle.compress(specs[k][1], specs[k][2], specs[k][3]), k
+    st, s = b.output(1)
+    assert st == fsz.FSZ_OK and len(s) > (1 << 32)
+    hdr = fmt.parse_header(s)
+    assert hdr["total"] == len(s)
+    E = float(hdr["E"])
+    sizes = fmt.tile_sizes_np(s, n)
+    d0 = fmt.data_start(n)
+    assert d0 + int(sizes.sum()) == len(s)
+    m = 4096
+    for first in (0, sizes.size - m):
+        lo, hi = first * fmt.TILE, min(n, (first + m) * fmt.TILE)
+        xs = x[lo:hi]
+        # an ABS bound of E/2 + 4 ulp(max|xs|) resolves to the same step E
+        u = float(np.spacing(np.float32(np.abs(xs).max())))
+        ref = oracle.compress(xs, oracle.ABS, E / 2 + 4 * u)
+        assert fmt.parse_header(ref)["E"] == hdr["E"]
+        nb = fmt.ceil_div(hi - lo, fmt.BLOCK)
+        r0 = fmt.HEADER + lo // fmt.BLOCK
+        assert s[r0:r0 + nb] == ref[fmt.HEADER:fmt.HEADER + nb], f"rate bytes of tiles from {first}"
+        at = d0 + int(sizes[:first].sum())
+        body = int(sizes[first:first + m].sum())
+        if first:
+            assert at > (1 << 32)
+        ds = fmt.data_start(hi - lo)
+        assert len(ref) == ds + body
+        assert s[at:at + body] == ref[ds:], f"data of tiles from {first}"
+    xd = b.src[1][:n]
+    del b
+    dspecs = [("d", oracle.compress(small[0].data, fsz.FSZ_REL, small[0].rel), small[0].data.size), ("d", s, n),
+              ("d", oracle.compress(small[1].data, fsz.FSZ_REL, small[1].rel), small[1].data.size)]
+    del s
+    announce("batch with a stream beyond 4 GiB: decompress")
+    db = DeviceBatch(dspecs)
+    db.run()
+    r = db.results()
+    assert all(st == fsz.FSZ_OK for _, st in r), r
+    for k in (0, 2):
+        y_ref = oracle.decompress(dspecs[k][1], dspecs[k][2])
+        assert np.array_equal(db.output(k)[1].view(np.uint32), y_ref.view(np.uint32)), k
+    y = db.dst[1][:n]
+    inv = np.float32(1) / np.float32(E)
+    q = torch.round(xd * float(inv)).to(torch.int32)  # zero as +0 whatever the product's sign
+    del xd
+    expect = q.to(torch.float32) * E
+    del q
+    step = 1 << 28
+    for k in range(0, n, step):
+        a = y[k:k + step].view(torch.int32)
+        e = expect[k:k + step].view(torch.int32)
+        bad = (a != e).nonzero()
+        if bad.numel():
+            i = k + int(bad[0])
+            raise AssertionError(f"{bad.numel()} of the elements [{k}, {k + a.numel()}) differ; first at {i}: "
+                                 f"decoded {float(y[i])} expected {float(expect[i])} (x = {float(x[i])})")

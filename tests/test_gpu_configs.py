@@ -231,18 +231,6 @@ def test_config_full_size_grf_512(config):
     assert np.array_equal(y.view(np.uint32), fmt.closed_form(x, E, inv).view(np.uint32))
 
 
-def _tile_sizes_np(s, n, B, T):
-    """Per-tile data bytes from the rate header (vectorised form of the
-    per-tile sum in fsz_format: a block costs (B/8)(1 + r) bytes when r > 0,
-    a centred tile 4 more)."""
-    rb = np.frombuffer(s, dtype=np.uint8, count=fmt.ceil_div(n, B), offset=fmt.HEADER)
-    nt = fmt.ceil_div(n, B * T)
-    r = np.zeros(nt * T, dtype=np.int64)
-    r[:rb.size] = rb & 0x1F
-    cost = np.where(r > 0, (B // 8) * (1 + r), 0).reshape(nt, T).sum(axis=1)
-    return cost + 4 * ((rb[::T].astype(np.int64) >> 6) & 1)
-
-
 def test_config_stream_beyond_4gib():
     """64-bit sizes and offsets in the configuration kernels: 2^31 + 4099
     uniform values at REL 1e-6 in 64 x 16 tiles give a stream of about 5.7
@@ -264,7 +252,7 @@ def test_config_stream_beyond_4gib():
     hdr = fmt.parse_header(s)
     assert hdr["total"] == len(s) and fmt.header_config(hdr["flags"]) == (B, T)
     E = float(hdr["E"])
-    sizes = _tile_sizes_np(s, n, B, T)
+    sizes = fmt.tile_sizes_np(s, n, B, T)
     d0 = fmt.data_start(n, B)
     assert d0 + int(sizes.sum()) == len(s)
     te = B * T

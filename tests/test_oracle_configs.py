@@ -183,3 +183,16 @@ def test_config_worst_case_fits_the_bound(config):
         assert len(s) <= oracle.bound_config(n, B, T)
         st, _ = oracle.compress_status(x, oracle.REL, 1e-6, capacity=len(s) - 1, config=config)
         assert st == oracle.ERR_CAPACITY
+
+
+@pytest.mark.parametrize("config", CONFIGS)
+def test_tile_sizes_array_form(config):
+    """The array form of the per-tile size sum (used on streams of millions
+    of tiles) agrees with the per-tile form and with the stream's length."""
+    B, T = config
+    for n, seed in ((1, 1), (B * T + 1, 2), (40000, 3)):
+        x = workloads.sinusoid_field(n, seed)
+        s = oracle.compress(x, oracle.REL, 1e-4, config=config)
+        sizes = fmt.tile_sizes_np(s, n, B, T)
+        assert sizes.tolist() == fmt.tile_sizes(s, n, B, T)
+        assert fmt.data_start(n, B) + int(sizes.sum()) == len(s)
