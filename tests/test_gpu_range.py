@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from paper_2607_15413_amd import fsz, workloads
+from tests import fsz_format as fmt
 from tests.test_gpu_parity import announce
 
 pytestmark = pytest.mark.gpu
@@ -83,3 +84,53 @@ def test_range_decode_errors():
         announce(f"range: corrupt rate byte {name} (block {blk})")
         st, _ = gpu_decompress_range(bytes(bad), n, begin, end)
         assert st == fsz.FSZ_ERR_CORRUPT, name
+
+
+def test_range_decode_beyond_4gib():
+    """Random access in a stream of about 5.7 GB (2^31 + 4099 uniform values
+    at REL 1e-6): a range across the tile whose data straddles byte 2^32,
+    ranges whose data lies beyond it (several chunks, the field's end, its
+    last element) and one across element 2^31 decode to the closed form
+    fl(rint(fl(x * inv)) * E) bit for bit, with nothing written outside the
+    range."""
+    n = (1 << 31) + 4099
+    rng = np.random.default_rng(29)
+    x = rng.random(n, dtype=np.float32)
+    x *= 2
+    x -= 1
+    announce(f"range beyond 4 GiB: compress uniform n={n} REL 1e-6")
+    stream = torch.cuda.current_stream(_dev()).cuda_stream
+    xd = torch.from_numpy(x).to(_dev())
+    cap = fsz.fsz_compressed_bound(n)
+    cmp = torch.zeros(cap, dtype=torch.uint8, device=_dev())
+    r1 = torch.zeros(4, dtype=torch.int32, device=_dev())
+    assert fsz.fsz_compress_async(xd.data_ptr(), n, fsz.FSZ_REL, 1e-6, None, cmp.data_ptr(), cap, r1.data_ptr(),
+                                  stream) == fsz.FSZ_OK
+    size, st, _ = fsz.read_result(r1)
+    assert st == fsz.FSZ_OK and size > (1 << 32)
+    head = cmp[:fmt.data_start(n)].cpu().numpy().tobytes()
+    E = float(fmt.parse_header(head)["E"])
+    ends = fmt.data_start(n) + np.cumsum(fmt.tile_sizes_np(head, n))
+    assert int(ends[-1]) == size
+    t = int(np.searchsorted(ends, 1 << 32, side="right"))  # the first tile whose data ends beyond 2^32
+    assert int(ends[t - 1]) <= (1 << 32) < int(ends[t])
+    inv = float(np.float32(1) / np.float32(E))
+    ranges = [(fmt.TILE * t - 100, fmt.TILE * t + 300), (n - 70001, n - 3), (n - 1, n), (n - 1000003, n),
+              ((1 << 31) - 5, (1 << 31) + 4000)]
+    for begin, end in ranges:
+        for off in (0, 1):
+            announce(f"range beyond 4 GiB: [{begin}, {end}) output offset {off}")
+            m = end - begin
+            guard = 8
+            out = torch.full((m + off + 2 * guard,), float("nan"), dtype=torch.float32, device=_dev())
+            res = torch.zeros(2, dtype=torch.int64, device=_dev())
+            assert fsz.fsz_decompress_range_async(cmp.data_ptr(), size, n, begin, end,
+                                                  out.data_ptr() + 4 * (guard + off), res.data_ptr(),
+                                                  stream) == fsz.FSZ_OK
+            torch.cuda.synchronize()
+            assert int(res.cpu()[1]) & 0xFFFFFFFF == fsz.FSZ_OK
+            q = torch.round(xd[begin:end] * inv).to(torch.int32)  # zero as +0 whatever the product's sign
+            expect = q.to(torch.float32) * E
+            y = out[guard + off:guard + off + m]
+            assert torch.equal(y.view(torch.int32), expect.view(torch.int32)), (begin, end)
+            assert bool(torch.isnan(out[:guard + off]).all()) and bool(torch.isnan(out[guard + off + m:]).all())
