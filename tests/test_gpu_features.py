@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from paper_2607_15413_amd import fsz, workloads
+from tests import fsz_format as fmt
 from tests.test_gpu_parity import announce, first_diff, gpu_decompress
 
 pytestmark = pytest.mark.gpu
@@ -141,3 +142,78 @@ def test_five_read_reports_errors():
     x[77] = np.nan
     st, _ = gpu_compress_five_read(x, oracle.REL, 1e-3)
     assert st == fsz.FSZ_ERR_NONFINITE
+
+
+def test_base_features_stream_beyond_4gib():
+    """64-bit offsets in the feature-switch kernel: 2^31 + 4099 uniform values
+    at REL 1e-6 with every feature off (independent blocks, first order, no
+    centering) give a stream beyond 2^32 bytes.  The rate header sums to its
+    size, the first and the last 4096 tiles (the last ones stored beyond
+    2^32 bytes) equal the oracle's streams of the same elements, and the
+    plain decoder, which honours the independent-blocks flag, gives the
+    closed form fl(rint(fl(x * inv)) * E) over the whole field."""
+    n = (1 << 31) + 4099
+    rng = np.random.default_rng(31)
+    x = rng.random(n, dtype=np.float32)
+    x *= 2
+    x -= 1
+    rel = 1e-6
+    announce(f"features 0, stream beyond 4 GiB: uniform n={n} REL {rel:g}")
+    stream = torch.cuda.current_stream(_dev()).cuda_stream
+    xd = torch.from_numpy(x).to(_dev())
+    cap = fsz.fsz_compressed_bound(n)
+    out = torch.zeros(cap, dtype=torch.uint8, device=_dev())
+    res = torch.zeros(2, dtype=torch.int64, device=_dev())
+    assert fsz.fsz_compress_features_async(xd.data_ptr(), n, fsz.FSZ_REL, rel, None, 0, out.data_ptr(), cap,
+                                           res.data_ptr(), stream) == fsz.FSZ_OK
+    torch.cuda.synchronize()
+    r = res.cpu()
+    size, st = int(r[0]), int(r[1]) & 0xFFFFFFFF
+    assert st == fsz.FSZ_OK and size > (1 << 32)
+    d0 = fmt.data_start(n)
+    head = out[:d0].cpu().numpy().tobytes()
+    hdr = fmt.parse_header(head)
+    assert hdr["total"] == size and hdr["flags"] & 2
+    E = float(hdr["E"])
+    sizes = fmt.tile_sizes_np(head, n)
+    assert d0 + int(sizes.sum()) == size
+    m = 4096
+    for first in (0, sizes.size - m):
+        lo, hi = first * fmt.TILE, min(n, (first + m) * fmt.TILE)
+        xs = x[lo:hi]
+        # an ABS bound of E/2 + 4 ulp(max|xs|) resolves to the same step E
+        u = float(np.spacing(np.float32(np.abs(xs).max())))
+        ref = oracle.compress(xs, oracle.ABS, E / 2 + 4 * u, features=0)
+        assert fmt.parse_header(ref)["E"] == hdr["E"]
+        nb = fmt.ceil_div(hi - lo, fmt.BLOCK)
+        r0 = fmt.HEADER + lo // fmt.BLOCK
+        assert head[r0:r0 + nb] == ref[fmt.HEADER:fmt.HEADER + nb], f"rate bytes of tiles from {first}"
+        at = d0 + int(sizes[:first].sum())
+        body = int(sizes[first:first + m].sum())
+        if first:
+            assert at > (1 << 32)
+        ds = fmt.data_start(hi - lo)
+        assert len(ref) == ds + body
+        got = out[at:at + body].cpu().numpy().tobytes()
+        assert got == ref[ds:], f"data of tiles from {first}: " + first_diff(got, ref[ds:])
+    announce(f"features 0, stream beyond 4 GiB: decode of {size} bytes")
+    y = torch.empty(n, dtype=torch.float32, device=_dev())
+    r2 = torch.zeros(2, dtype=torch.int64, device=_dev())
+    assert fsz.fsz_decompress_async(out.data_ptr(), size, y.data_ptr(), n, r2.data_ptr(), stream) == fsz.FSZ_OK
+    torch.cuda.synchronize()
+    assert int(r2.cpu()[1]) & 0xFFFFFFFF == fsz.FSZ_OK
+    del out
+    inv = float(np.float32(1) / np.float32(E))
+    q = torch.round(xd * inv).to(torch.int32)  # zero as +0 whatever the product's sign
+    del xd
+    expect = q.to(torch.float32) * E
+    del q
+    step = 1 << 28
+    for k in range(0, n, step):
+        a = y[k:k + step].view(torch.int32)
+        e = expect[k:k + step].view(torch.int32)
+        bad = (a != e).nonzero()
+        if bad.numel():
+            i = k + int(bad[0])
+            raise AssertionError(f"{bad.numel()} of the elements [{k}, {k + a.numel()}) differ; first at {i}: "
+                                 f"decoded {float(y[i])} expected {float(expect[i])} (x = {float(x[i])})")
