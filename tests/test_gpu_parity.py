@@ -185,6 +185,88 @@ def test_stream_beyond_4gib():
                                  f"decoded {float(y[i])} expected {float(expect[i])} (x = {float(x[i])})")
 
 
+def test_stream_beyond_4gib_unaligned():
+    """The kernels for pointers that are not 16-byte aligned at 64-bit sizes:
+    2^31 + 4099 uniform values at REL 1e-6 read from an input one float past
+    a 16-byte boundary give the same 5.7 GB stream as the aligned
+    (pipelined) kernel, their first and last 4096 tiles (the last ones
+    stored beyond 2^32 bytes) equal the oracle's streams of the same
+    elements, and the decode into an output one float past a 16-byte
+    boundary equals the closed form fl(rint(fl(x * inv)) * E)."""
+    n = (1 << 31) + 4099
+    rng = np.random.default_rng(37)
+    x = rng.random(n, dtype=np.float32)
+    x *= 2
+    x -= 1
+    rel = 1e-6
+    cap = fsz.fsz_compressed_bound(n)
+    xa = torch.from_numpy(x).to(_dev())
+    xu = torch.empty(n + 4, dtype=torch.float32, device=_dev())
+    xu[1:n + 1] = xa
+    streams = []
+    for name, xp in (("aligned", xa.data_ptr()), ("unaligned", xu.data_ptr() + 4)):
+        announce(f"stream beyond 4 GiB, {name} input: uniform n={n} REL {rel:g}")
+        out = torch.zeros(cap, dtype=torch.uint8, device=_dev())
+        r = torch.zeros(4, dtype=torch.int32, device=_dev())
+        assert fsz.fsz_compress_async(xp, n, fsz.FSZ_REL, rel, None, out.data_ptr(), cap, r.data_ptr(),
+                                      _stream()) == fsz.FSZ_OK
+        size, st, _ = fsz.read_result(r)
+        assert st == fsz.FSZ_OK and size > (1 << 32)
+        streams.append((out, size))
+    del xu
+    (oa, sa), (ou, size) = streams
+    assert sa == size and torch.equal(oa[:size], ou[:size])
+    del oa, streams
+    d0 = fmt.data_start(n)
+    head = ou[:d0].cpu().numpy().tobytes()
+    hdr = fmt.parse_header(head)
+    E = float(hdr["E"])
+    sizes = fmt.tile_sizes_np(head, n)
+    assert hdr["total"] == size == d0 + int(sizes.sum())
+    m = 4096
+    for first in (0, sizes.size - m):
+        lo, hi = first * fmt.TILE, min(n, (first + m) * fmt.TILE)
+        xs = x[lo:hi]
+        # an ABS bound of E/2 + 4 ulp(max|xs|) resolves to the same step E
+        u = float(np.spacing(np.float32(np.abs(xs).max())))
+        ref = oracle.compress(xs, oracle.ABS, E / 2 + 4 * u)
+        assert fmt.parse_header(ref)["E"] == hdr["E"]
+        nb = fmt.ceil_div(hi - lo, fmt.BLOCK)
+        r0 = fmt.HEADER + lo // fmt.BLOCK
+        assert head[r0:r0 + nb] == ref[fmt.HEADER:fmt.HEADER + nb], f"rate bytes of tiles from {first}"
+        at = d0 + int(sizes[:first].sum())
+        body = int(sizes[first:first + m].sum())
+        if first:
+            assert at > (1 << 32)
+        ds = fmt.data_start(hi - lo)
+        assert len(ref) == ds + body
+        got = ou[at:at + body].cpu().numpy().tobytes()
+        assert got == ref[ds:], f"data of tiles from {first}: " + first_diff(got, ref[ds:])
+    announce(f"stream beyond 4 GiB: decode of {size} bytes into an unaligned output")
+    yb = torch.full((n + 8,), float("nan"), dtype=torch.float32, device=_dev())
+    r2 = torch.zeros(4, dtype=torch.int32, device=_dev())
+    assert fsz.fsz_decompress_async(ou.data_ptr(), size, yb.data_ptr() + 4, n, r2.data_ptr(),
+                                    _stream()) == fsz.FSZ_OK
+    assert fsz.read_result(r2)[1] == fsz.FSZ_OK
+    del ou
+    assert bool(torch.isnan(yb[0])) and bool(torch.isnan(yb[n + 1:]).all())
+    y = yb[1:n + 1]
+    inv = float(np.float32(1) / np.float32(E))
+    q = torch.round(xa * inv).to(torch.int32)  # zero as +0 whatever the product's sign
+    del xa
+    expect = q.to(torch.float32) * E
+    del q
+    step = 1 << 28
+    for k in range(0, n, step):
+        a = y[k:k + step].view(torch.int32)
+        b = expect[k:k + step].view(torch.int32)
+        bad = (a != b).nonzero()
+        if bad.numel():
+            i = k + int(bad[0])
+            raise AssertionError(f"{bad.numel()} of the elements [{k}, {k + a.numel()}) differ; first at {i}: "
+                                 f"decoded {float(y[i])} expected {float(expect[i])} (x = {float(x[i])})")
+
+
 # ----------------------------------------------------------------- ragged / edge sizes
 
 
