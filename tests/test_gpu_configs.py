@@ -103,6 +103,29 @@ def test_config_streams_match_oracle(config):
                 assert np.array_equal(y.view(np.uint32), y_ref.view(np.uint32))
 
 
+@pytest.mark.parametrize("config", CONFIGS)
+def test_config_edge_sizes(config):
+    """Sizes around a block (B), a tile (B T), a wave (64 segments of 32) and
+    a chunk (32768 elements) of the configuration kernels: streams byte for
+    byte, decodes bit for bit against the oracle."""
+    B, T = config
+    te = B * T
+    sizes = sorted({1, 2, 3, 31, 32, 33, B - 1, B, B + 1, te - 1, te, te + 1, 2 * te + 5, 2047, 2048, 2049,
+                    32767, 32768, 32769, 3 * 32768 + te - 1})
+    for n in sizes:
+        x = workloads.sinusoid_field(n, n + 11)
+        st_ref, exp = oracle.compress_status(x, oracle.REL, 1e-3, config=config)
+        announce(f"config {config} edge size n={n}")
+        st, got = gpu_compress_config(x, oracle.REL, 1e-3, config)
+        assert st == st_ref, (n, st, st_ref)  # n = 2: a range below the bound's resolution
+        if st != fsz.FSZ_OK:
+            continue
+        assert got == exp, (n, first_diff(got, exp))
+        st, y = gpu_decompress_config(exp, n, config)
+        assert st == fsz.FSZ_OK
+        assert np.array_equal(y.view(np.uint32), oracle.decompress(exp, n).view(np.uint32)), n
+
+
 def test_default_config_is_the_plain_stream():
     x = workloads.grf_field((64, 64, 64), 9)
     for rel in (1e-2, 1e-3):
