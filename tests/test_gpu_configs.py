@@ -126,6 +126,40 @@ def test_config_edge_sizes(config):
         assert np.array_equal(y.view(np.uint32), oracle.decompress(exp, n).view(np.uint32)), n
 
 
+@pytest.mark.parametrize("config", CONFIGS)
+def test_config_special_fields(config):
+    """Zeros, constants, subnormals, values near the largest float, a bound
+    too large or too small, NaN and -Inf: the oracle's status and bytes."""
+    n = 1024 * 9 + 5
+    big = np.full(700, 3.0e38, np.float32)
+    big[::2] = 2.9e38
+    too_large = np.full(10, 3.3e38, np.float32)
+    too_large[0] = -1
+    x = workloads.sinusoid_field(5000, 9)
+    nan = x.copy()
+    nan[4321] = np.nan
+    inf = x.copy()
+    inf[4321] = -np.inf
+    cases = [("zeros-abs", np.zeros(n, np.float32), oracle.ABS, 1e-3),
+             ("zeros-rel", np.zeros(n, np.float32), oracle.REL, 1e-3),
+             ("constant-neg-rel", np.full(n, -7.5, np.float32), oracle.REL, 1e-2),
+             ("subnormal-constant", np.full(n, 1e-40, np.float32), oracle.REL, 1e-3),
+             ("subnormal-ramp", (np.arange(n, dtype=np.float32) * np.float32(1e-41)), oracle.ABS, 1e-38),
+             ("huge-values", big, oracle.ABS, 1e35), ("eb-too-large", too_large, oracle.ABS, 1e37),
+             ("eb-too-small", x, oracle.ABS, 1e-9), ("nan", nan, oracle.REL, 1e-3), ("inf", inf, oracle.ABS, 1e-3)]
+    for name, f, mode, value in cases:
+        st_ref, exp = oracle.compress_status(f, mode, value, config=config)
+        announce(f"config {config} special field {name}")
+        st, got = gpu_compress_config(f, mode, value, config)
+        assert st == st_ref, (name, st, st_ref)
+        if st != fsz.FSZ_OK:
+            continue
+        assert got == exp, (name, first_diff(got, exp))
+        st, y = gpu_decompress_config(exp, f.size, config)
+        assert st == fsz.FSZ_OK
+        assert np.array_equal(y.view(np.uint32), oracle.decompress(exp, f.size).view(np.uint32)), name
+
+
 def test_default_config_is_the_plain_stream():
     x = workloads.grf_field((64, 64, 64), 9)
     for rel in (1e-2, 1e-3):
