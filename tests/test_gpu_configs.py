@@ -15,7 +15,7 @@ import pytest
 import oracle
 from paper_2607_15413_amd import fsz, workloads
 from tests import fsz_format as fmt
-from tests.test_gpu_parity import announce, first_diff, gpu_compress
+from tests.test_gpu_parity import _fuzz_field, announce, first_diff, gpu_compress
 
 pytestmark = pytest.mark.gpu
 
@@ -158,6 +158,31 @@ def test_config_special_fields(config):
         st, y = gpu_decompress_config(exp, f.size, config)
         assert st == fsz.FSZ_OK
         assert np.array_equal(y.view(np.uint32), oracle.decompress(exp, f.size).view(np.uint32)), name
+
+
+def test_config_fuzz():
+    """Random fields (seven kinds), sizes, bound modes, bounds and
+    configurations, with unaligned inputs and outputs now and then: statuses,
+    streams and decodes against the oracle."""
+    rng = np.random.default_rng(4321)
+    for case in range(48):
+        config = CONFIGS[int(rng.integers(0, len(CONFIGS)))]
+        n = int(rng.choice([int(rng.integers(1, 1100)), int(rng.integers(1, 70_000)),
+                            int(rng.integers(1, 1 << 20))]))
+        name, x = _fuzz_field(rng, n)
+        mode = int(rng.integers(0, 2))
+        value = float(10.0 ** rng.uniform(-5, -1)) if mode == 1 else float(10.0 ** rng.uniform(-4, 0))
+        off = int(rng.integers(0, 2))
+        st_ref, exp = oracle.compress_status(x, mode, value, config=config)
+        announce(f"config fuzz {case}: {config} {name} n={n} mode={mode} value={value:.3g} offset {off}")
+        st, got = gpu_compress_config(x, mode, value, config, in_offset=off)
+        assert st == st_ref, (case, st, st_ref)
+        if st != fsz.FSZ_OK:
+            continue
+        assert got == exp, (case, first_diff(got, exp))
+        st, y = gpu_decompress_config(exp, n, config, out_offset=off)
+        assert st == fsz.FSZ_OK
+        assert np.array_equal(y.view(np.uint32), oracle.decompress(exp, n).view(np.uint32)), case
 
 
 def test_default_config_is_the_plain_stream():
