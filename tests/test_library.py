@@ -2,6 +2,8 @@
 import ctypes
 import os
 import re
+import subprocess
+import sys
 
 import pytest
 
@@ -114,3 +116,14 @@ def test_server_invalid_config_rejected_on_host():
     assert fsz.fsz_server_poll(None) == []
     assert fsz.fsz_server_release(None, 16) == fsz.FSZ_ERR_INVALID_ARG
     assert fsz.fsz_server_now_ns() > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus N > 1 exits with status 2 and
+    says why, before it imports torch or touches a device."""
+    for n in (2, 8):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)], capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 2, (n, r.returncode, r.stderr)
+        assert "exactly one GPU" in r.stderr and f"--gpus {n}" in r.stderr
+        assert r.stdout == ""
