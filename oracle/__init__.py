@@ -71,12 +71,19 @@ def _load():
         lib.fszo_tile_eval_config.restype = ctypes.c_int
         lib.fszo_decompress.argtypes = [p, u64, p, u64]
         lib.fszo_decompress.restype = ctypes.c_int
+        lib.fszo_set_threads.argtypes = [ctypes.c_int]
+        lib.fszo_set_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
 
 def _f32(x):
     return np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1))
+
+
+def set_threads(n: int) -> int:
+    """Host threads for the oracle's tile loops (1 = serial); returns the previous count."""
+    return int(_load().fszo_set_threads(n))
 
 
 def bound(n: int) -> int:

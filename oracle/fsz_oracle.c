@@ -27,8 +27,13 @@
  *
  * Readings where the paper is silent (each one is listed in the design notes):
  *   - quantizer: multiply by inv = fl32(1/E) then round-half-even; the step
- *     E is 2*eb tightened by 4 ulp(max|x|) and rounded toward zero so that the
- *     pointwise bound holds in binary32 arithmetic;
+ *     E is the largest binary32 not above 2 (eb - 4 ulp(max|x|)), computed
+ *     exactly, so that the pointwise bound holds in binary32 arithmetic;
+ *     bounds below 8 ulp(max|x|) are rejected;
+ *   - four-way evaluation: each variant's residuals are formed in full and
+ *     rated block by block (the plain definition; the one-read shortcut that
+ *     Eq. (4) licenses is what the GPU kernels do, and the tests check the
+ *     two agree);
  *   - zero predictor state at each tile start: q[-1] = q[-2] = 0;
  *   - tile mean: index-order pairwise binary32 sum of the 256 slots (missing
  *     slots of a ragged last tile count as +0), times 2^-8, quantized like
@@ -189,6 +194,21 @@ static float to_f32_toward_zero(double d)
     return f;
 }
 
+/* a - b (a > b > 0) rounded toward zero in binary64.  The round-to-nearest
+ * difference s carries an exact error term e (Knuth's two-sum: a - b = s + e
+ * exactly); when e < 0 the rounding went up, so step s one unit down.  Taken
+ * toward zero again into binary32, the result is then the binary32 value of
+ * the exact difference rounded toward zero (the binary32 numbers are binary64
+ * numbers, so the two truncations compose). */
+static double sub_toward_zero(double a, double b)
+{
+    double s = a - b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (-b - bb);
+    if (e < 0.0) s = nextafter(s, 0.0);
+    return s;
+}
+
 int fszo_resolve(const float *x, uint64_t n, int mode, double value,
                  float *E_out, float *inv_out, uint32_t *flags_out)
 {
@@ -220,7 +240,8 @@ int fszo_resolve(const float *x, uint64_t n, int mode, double value,
         double eb = mode == 1 ? value * ((double)xmax - (double)xmin) : value;
         double u = ulp32(M);
         if (!(eb >= 8.0 * u)) return FSZO_ERR_EB_TOO_SMALL;
-        double eb_q = eb - 4.0 * u;
+        /* E = the largest binary32 <= 2 (eb - 4u), computed exactly */
+        double eb_q = sub_toward_zero(eb, 4.0 * u);
         E = to_f32_toward_zero(2.0 * eb_q);
         if (E > 0x1p126f) E = 0x1p126f;
         if (E < FLT_MIN) return FSZO_ERR_EB_TOO_SMALL;
@@ -242,7 +263,7 @@ typedef struct {
     int m;                          /* valid elements in the tile */
     int nb;                         /* blocks in the tile */
     int32_t q[MAX_TILE];            /* quantized values */
-    int32_t l1[MAX_TILE], l2[MAX_TILE]; /* LZ1 / LZ2 residuals, zero state at tile start */
+    int32_t res[4][MAX_TILE];       /* residuals of LZ1, LZ2, LZ1c, LZ2c */
     int32_t mu;                     /* quantized tile mean */
     int centre_ok;                  /* mean finite -> centered variants allowed */
     uint32_t cost[4];               /* C of LZ1, LZ2, LZ1c, LZ2c */
@@ -260,6 +281,60 @@ static int variant_allowed(int v, uint32_t features, int centre_ok)
     return 1;
 }
 
+/* Prequantization (Sec. IV-B item 1): q = round(x / (2 eb)), here one
+ * binary32 multiply by inv = fl32(1/E) and round-half-even.  Missing slots
+ * of a ragged last tile are 0. */
+static void quantize_tile(const float *x, int m, int tile, float inv, int32_t *q)
+{
+    for (int i = 0; i < tile; i++) q[i] = i < m ? (int32_t)rintf(x[i] * inv) : 0;
+}
+
+/* Residuals of one variant (Sec. IV-A Eq. (1)-(2), Sec. IV-B): the
+ * predicted sequence is p = q - c (c = the tile mean for a centered
+ * variant, else 0); the residual is its first (LZ1) or second (LZ2)
+ * difference, with zero prediction state before the tile start (before
+ * every block start when blocks are independent).  Missing slots of a
+ * ragged last tile carry residual 0. */
+static void variant_residuals(const int32_t *q, int m, int B, int tile, int indep, int order2, int32_t c,
+                              int32_t *res)
+{
+    int32_t pm1 = 0, pm2 = 0;
+    for (int i = 0; i < tile; i++) {
+        if (indep && i % B == 0) pm1 = pm2 = 0;
+        if (i >= m) {
+            res[i] = 0;
+            continue;
+        }
+        int32_t p = q[i] - c;
+        res[i] = order2 ? p - 2 * pm1 + pm2 : p - pm1;
+        pm2 = pm1;
+        pm1 = p;
+    }
+}
+
+/* Tile mean (Sec. IV-B item 3): index-order pairwise binary32 sum of the
+ * B*T slots (missing slots of a ragged last tile count as +0), divided by
+ * B*T (a power of two, so the division is exact), then quantized like any
+ * element.  Returns 0 when that value is not finite (centering disabled). */
+static int tile_mean(const float *x, int m, int tile, float inv, int32_t *mu)
+{
+    float s[MAX_TILE];
+    for (int i = 0; i < tile; i++) s[i] = i < m ? x[i] : 0.0f;
+    for (int w = 1; w < tile; w *= 2)
+        for (int i = 0; i < tile; i += 2 * w) s[i] = s[i] + s[i + w];
+    float mean_q = (s[0] * (1.0f / (float)tile)) * inv;
+    if (!isfinite(mean_q)) {
+        *mu = 0;
+        return 0;
+    }
+    *mu = (int32_t)rintf(mean_q);
+    return 1;
+}
+
+/* Four-way evaluation and selection of one tile (Sec. IV-B, Eq. (3)): each
+ * variant's residuals are formed in full, each block's rate is the bit
+ * length of its largest residual magnitude, the cost C sums the block costs
+ * plus 4 bytes for a stored mean; the minimum wins. */
 static void analyse_tile(const float *x, int m, float inv, uint32_t features, int B, int T, tile_t *t)
 {
     const int TILE = B * T;
@@ -269,73 +344,20 @@ static void analyse_tile(const float *x, int m, float inv, uint32_t features, in
     t->m = m;
     t->nb = (m + B - 1) / B;
 
-    /* Quantize + cross-block LZ1/LZ2 residuals in one loop (Sec. IV-A,
-     * Eq. (2); Sec. IV-B items 1-2).  The predictor state runs across all
-     * blocks of the tile; only the tile start has no predecessor (with
-     * independent blocks, Eq. (1), every block start has none). */
-    int32_t qm1 = 0, qm2 = 0;
-    for (int i = 0; i < TILE; i++) {
-        if (t->indep && i % B == 0) qm1 = qm2 = 0;
-        if (i < m) {
-            float y = x[i] * inv;
-            int32_t q = (int32_t)rintf(y);
-            t->q[i] = q;
-            t->l1[i] = q - qm1;
-            t->l2[i] = q - 2 * qm1 + qm2;
-            qm2 = qm1;
-            qm1 = q;
-        } else {
-            /* missing slots of a ragged last tile carry residual 0 */
-            t->q[i] = 0;
-            t->l1[i] = 0;
-            t->l2[i] = 0;
-        }
-    }
+    quantize_tile(x, m, TILE, inv, t->q);
+    t->centre_ok = tile_mean(x, m, TILE, inv, &t->mu);
 
-    /* Tile mean (Sec. IV-B item 3): index-order pairwise binary32 sum of
-     * the B*T slots (256 by default), then divided by B*T (a power of two,
-     * so the division is exact) and quantized. */
-    float s[MAX_TILE];
-    for (int i = 0; i < TILE; i++) s[i] = i < m ? x[i] : 0.0f;
-    for (int w = 1; w < TILE; w *= 2)
-        for (int i = 0; i < TILE; i += 2 * w) s[i] = s[i] + s[i + w];
-    float mean_q = (s[0] * (1.0f / (float)TILE)) * inv;
-    t->centre_ok = isfinite(mean_q) ? 1 : 0;
-    t->mu = t->centre_ok ? (int32_t)rintf(mean_q) : 0;
-
-    /* Per-block rates.  By the cancellation property (Eq. (4)) the centered
-     * residuals equal the plain ones except the first one (LZ1) or two (LZ2)
-     * after a prediction restart, so a block without a restart has one rate
-     * per order and a block with one (block 0; every block when blocks are
-     * independent) is rated per variant from its inner residuals and its
-     * first residuals: l[0] = q0 (or q0 - mu), LZ2 l[1] = q1 - 2 q0 (or
-     * q1 - 2 q0 + mu), absent when the block holds fewer than 2 values. */
-    for (int v = 0; v < 4; v++) t->cost[v] = (v >> 1) ? 4 : 0;
-    for (int b = 0; b < T; b++) {
-        if (b >= t->nb) {
-            for (int v = 0; v < 4; v++) t->vrate[v][b] = 0;
-            continue;
-        }
-        int restart = (b == 0 || t->indep);
-        int s0 = b * B;
-        uint32_t a1 = 0, a2 = 0;
-        for (int i = s0; i < s0 + B; i++) {
-            uint32_t m1 = magnitude(t->l1[i]), m2 = magnitude(t->l2[i]);
-            if (!restart || i >= s0 + 1) a1 = m1 > a1 ? m1 : a1;
-            if (!restart || i >= s0 + 2) a2 = m2 > a2 ? m2 : a2;
-        }
-        for (int v = 0; v < 4; v++) {
-            int ord2 = v & 1, cen = v >> 1;
-            uint32_t a = ord2 ? a2 : a1;
-            if (restart) {
-                int mb = m - s0 < B ? m - s0 : B;
-                int32_t q0 = t->q[s0];
-                int32_t d1 = mb >= 2 ? t->l2[s0 + 1] : 0;
-                int32_t f0 = cen ? q0 - t->mu : q0;
-                int32_t f1 = mb >= 2 ? (cen ? d1 + t->mu : d1) : 0;
-                if (magnitude(f0) > a) a = magnitude(f0);
-                if (ord2 && magnitude(f1) > a) a = magnitude(f1);
-            }
+    for (int v = 0; v < 4; v++) {
+        int ord2 = v & 1, cen = v >> 1;
+        variant_residuals(t->q, m, B, TILE, t->indep, ord2, cen ? t->mu : 0, t->res[v]);
+        t->cost[v] = cen ? 4 : 0;
+        for (int b = 0; b < T; b++) {
+            uint32_t a = 0;
+            if (b < t->nb)
+                for (int i = b * B; i < b * B + B; i++) {
+                    uint32_t mg = magnitude(t->res[v][i]);
+                    if (mg > a) a = mg;
+                }
             t->vrate[v][b] = rate_of(a);
             t->cost[v] += block_cost(t->vrate[v][b], B);
         }
@@ -386,33 +408,17 @@ int fszo_tile_eval(const float *x, int m, float inv, int32_t *mu, int *centre_ok
     return fszo_tile_eval_features(x, m, inv, FSZO_FEATURES_ALL, mu, centre_ok, cost4, rates4x8, &best);
 }
 
-/* residual of the selected variant at tile position i */
-static int32_t selected_residual(const tile_t *t, int i)
+/* Fixed-length encoding + bit-shuffle of one block of B residuals at rate r
+ * (Sec. IV-C): the sign map, then planes 0..r-1, each one B-bit word with
+ * element j at bit B - 1 - j. */
+static uint8_t *encode_block(const int32_t *res, uint32_t r, int B, uint8_t *p)
 {
-    if (i >= t->m) return 0;
-    int32_t e = t->order2 ? t->l2[i] : t->l1[i];
-    if (t->centred) {
-        int s0 = t->indep ? i / t->B * t->B : 0; /* start of the prediction run */
-        if (i == s0) e = t->q[i] - t->mu;
-        else if (i == s0 + 1 && t->order2) e = t->l2[i] + t->mu;
-    }
-    return e;
-}
-
-/* Fixed-length encoding + bit-shuffle of one block (Sec. IV-C): the sign
- * map, then planes 0..r-1, each one B-bit word with element j at bit
- * B - 1 - j. */
-static uint8_t *encode_block(const tile_t *t, int b, uint8_t *p)
-{
-    const int B = t->B;
-    uint32_t r = t->rate[b];
     if (r == 0) return p;
     uint32_t mag[MAX_BLOCK];
     uint64_t sign = 0;
     for (int j = 0; j < B; j++) {
-        int32_t e = selected_residual(t, b * B + j);
-        mag[j] = magnitude(e);
-        if (e < 0) sign |= 1ull << (B - 1 - j);
+        mag[j] = magnitude(res[j]);
+        if (res[j] < 0) sign |= 1ull << (B - 1 - j);
     }
     put_bits_msb_first(p, sign, B);
     p += B / 8;
@@ -425,6 +431,19 @@ static uint8_t *encode_block(const tile_t *t, int b, uint8_t *p)
     return p;
 }
 
+/* Host threads for the tile loops (the CPU baseline's parallel mode).
+ * Tiles are independent, so pass 1 (analysis) and pass 3 (encode) run over
+ * tiles in parallel; the prefix sum between them stays serial.  The bytes
+ * do not depend on the thread count. */
+static int g_threads = 1;
+
+int fszo_set_threads(int n)
+{
+    int old = g_threads;
+    if (n >= 1) g_threads = n;
+    return old;
+}
+
 int fszo_compress_config(const float *x, uint64_t n, int mode, double value, uint32_t features, int B, int T,
                          uint8_t *out, uint64_t cap, uint64_t *out_size)
 {
@@ -435,30 +454,51 @@ int fszo_compress_config(const float *x, uint64_t n, int mode, double value, uin
     if (st != FSZO_OK) return st;
 
     const uint64_t TILE = (uint64_t)B * T;
+    const int indep = (features & FSZO_FEAT_CROSS_BLOCK) ? 0 : 1;
     uint64_t nblocks = ceil_div(n, (uint64_t)B);
     uint64_t ntiles = ceil_div(n, TILE);
     uint64_t data0 = HEADER_BYTES + pad16(nblocks);
 
-    /* Pass 1: per-tile analysis -> rate bytes and tile sizes. */
-    tile_t *tl = (tile_t *)malloc(sizeof(tile_t));
     uint8_t *rates = (uint8_t *)malloc(nblocks ? nblocks : 1);
     uint64_t *offset = (uint64_t *)malloc(sizeof(uint64_t) * (ntiles + 1));
-    if (!tl || !rates || !offset) {
-        free(tl);
+    int32_t *mus = (int32_t *)malloc(sizeof(int32_t) * (ntiles ? ntiles : 1));
+    if (!rates || !offset || !mus) {
         free(rates);
         free(offset);
+        free(mus);
         return FSZO_ERR_INVALID_ARG;
     }
-    for (uint64_t t = 0; t < ntiles; t++) {
-        uint64_t start = t * TILE;
-        int m = (int)(n - start < TILE ? n - start : TILE);
-        analyse_tile(x + start, m, inv, features, B, T, tl);
-        for (int b = 0; b < tl->nb; b++) {
-            uint8_t byte = (uint8_t)tl->rate[b];
-            if (b == 0) byte |= (uint8_t)((tl->order2 << 7) | (tl->centred << 6)); /* Sec. III-A */
-            rates[t * (uint64_t)T + b] = byte;
+    int failed = 0;
+
+    /* Pass 1: per-tile analysis -> rate bytes, tile sizes, tile means. */
+#pragma omp parallel num_threads(g_threads)
+    {
+        tile_t *tl = (tile_t *)malloc(sizeof(tile_t));
+        if (!tl) {
+#pragma omp atomic write
+            failed = 1;
         }
-        offset[t + 1] = tl->bytes;
+#pragma omp for schedule(static)
+        for (uint64_t t = 0; t < ntiles; t++) {
+            if (!tl) continue;
+            uint64_t start = t * TILE;
+            int m = (int)(n - start < TILE ? n - start : TILE);
+            analyse_tile(x + start, m, inv, features, B, T, tl);
+            for (int b = 0; b < tl->nb; b++) {
+                uint8_t byte = (uint8_t)tl->rate[b];
+                if (b == 0) byte |= (uint8_t)((tl->order2 << 7) | (tl->centred << 6)); /* Sec. III-A */
+                rates[t * (uint64_t)T + b] = byte;
+            }
+            offset[t + 1] = tl->bytes;
+            mus[t] = tl->mu;
+        }
+        free(tl);
+    }
+    if (failed) {
+        free(rates);
+        free(offset);
+        free(mus);
+        return FSZO_ERR_INVALID_ARG;
     }
 
     /* Pass 2: exclusive prefix sum of tile sizes (Sec. IV-D). */
@@ -466,9 +506,9 @@ int fszo_compress_config(const float *x, uint64_t n, int mode, double value, uin
     for (uint64_t t = 0; t < ntiles; t++) offset[t + 1] += offset[t];
     uint64_t total = data0 + offset[ntiles];
     if (total > cap) {
-        free(tl);
         free(rates);
         free(offset);
+        free(mus);
         return FSZO_ERR_CAPACITY;
     }
 
@@ -480,30 +520,40 @@ int fszo_compress_config(const float *x, uint64_t n, int mode, double value, uin
     out[3] = '1';
     put_u16(out + 4, 1);
     out[6] = (uint8_t)mode;
-    out[7] = (uint8_t)(flags | ((features & FSZO_FEAT_CROSS_BLOCK) ? 0u : 2u) | config_flags(B, T));
+    out[7] = (uint8_t)(flags | (indep ? 2u : 0u) | config_flags(B, T));
     put_u64(out + 8, n);
     put_u32(out + 16, float_to_bits(E));
     put_u32(out + 20, float_to_bits((float)value));
     put_u64(out + 24, total);
     memcpy(out + HEADER_BYTES, rates, nblocks);
 
-    /* Pass 3: encode every tile at its offset (the analysis is repeated,
-     * as the paper's encoder re-reads its input). */
-    for (uint64_t t = 0; t < ntiles; t++) {
-        uint64_t start = t * TILE;
-        int m = (int)(n - start < TILE ? n - start : TILE);
-        analyse_tile(x + start, m, inv, features, B, T, tl);
-        uint8_t *p = out + data0 + offset[t];
-        if (tl->centred) {
-            put_u32(p, (uint32_t)tl->mu);
-            p += 4;
+    /* Pass 3: encode every tile at its offset with the variant recorded in
+     * its rate bytes: the residuals of that variant are formed again from
+     * the input (the paper's encoder re-reads its input too). */
+#pragma omp parallel num_threads(g_threads)
+    {
+        int32_t q[MAX_TILE], res[MAX_TILE];
+#pragma omp for schedule(static)
+        for (uint64_t t = 0; t < ntiles; t++) {
+            uint64_t start = t * TILE;
+            int m = (int)(n - start < TILE ? n - start : TILE);
+            int nb = (m + B - 1) / B;
+            const uint8_t *rb = rates + t * (uint64_t)T;
+            int order2 = (rb[0] >> 7) & 1, centred = (rb[0] >> 6) & 1;
+            quantize_tile(x + start, m, (int)TILE, inv, q);
+            variant_residuals(q, m, B, (int)TILE, indep, order2, centred ? mus[t] : 0, res);
+            uint8_t *p = out + data0 + offset[t];
+            if (centred) {
+                put_u32(p, (uint32_t)mus[t]);
+                p += 4;
+            }
+            for (int b = 0; b < nb; b++) p = encode_block(res + b * B, rb[b] & 0x1Fu, B, p);
         }
-        for (int b = 0; b < tl->nb; b++) p = encode_block(tl, b, p);
     }
 
-    free(tl);
     free(rates);
     free(offset);
+    free(mus);
     *out_size = total;
     return FSZO_OK;
 }
@@ -572,7 +622,9 @@ int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t 
         return FSZO_ERR_CORRUPT;
     }
 
-    /* 4-5: decode + bit-unshuffle, inverse prediction, dequantize */
+    /* 4-5: decode + bit-unshuffle, inverse prediction, dequantize (tiles
+     * are independent once their offsets are known) */
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (uint64_t t = 0; t < ntiles; t++) {
         uint64_t start = t * TILE;
         int m = (int)(n - start < TILE ? n - start : TILE);

@@ -78,6 +78,11 @@ int fszo_compress_config(const float *x, uint64_t n, int mode, double value, uin
 int fszo_tile_eval_config(const float *x, int m, float inv, uint32_t features, int B, int T, int32_t *mu,
                           int *centre_ok, uint32_t *cost4, uint32_t *rates, int *best);
 
+/* Host threads for the tile loops of compression and decompression
+ * (default 1).  The bytes written do not depend on it.  Returns the previous
+ * value; n < 1 leaves it unchanged. */
+int fszo_set_threads(int n);
+
 /* Full decompression of a stream of cmp_size bytes into n floats (any tile
  * configuration, read from the header). */
 int fszo_decompress(const uint8_t *cmp, uint64_t cmp_size, float *out, uint64_t n);

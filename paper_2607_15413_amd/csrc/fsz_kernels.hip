@@ -254,8 +254,21 @@ __device__ __forceinline__ float f32_toward_zero(double d)
     return f;
 }
 
+// a - b (a > b > 0) rounded toward zero in binary64: the round-to-nearest
+// difference plus its exact two-sum error term; a negative error means the
+// rounding went up, so the result steps one unit down.  Truncated again to
+// binary32 it gives the exact difference truncated to binary32.
+__device__ __forceinline__ double sub_toward_zero(double a, double b)
+{
+    double s = a - b;
+    const double bb = s - a;
+    const double e = (a - (s - bb)) + (-b - bb);
+    if (e < 0.0) s = __longlong_as_double(__double_as_longlong(s) - 1);
+    return s;
+}
+
 // Error-bound resolution (Sec. V-A) with the binary32 step tightening:
-// eb_q = eb - 4 ulp(max|x|), E = 2 eb_q rounded toward zero, inv = 1/E.
+// E = the largest binary32 <= 2 (eb - 4 ulp(max|x|)), inv = 1/E.
 __device__ Resolved resolve_bound(const fsz_stats *stp, int mode, double value, uint64_t n)
 {
     Resolved r{1.0f, 1.0f, 0u, FSZ_OK};
@@ -284,7 +297,7 @@ __device__ Resolved resolve_bound(const fsz_stats *stp, int mode, double value, 
             r.status = FSZ_ERR_EB_TOO_SMALL;
             return r;
         }
-        const double ebq = eb - 4.0 * u;
+        const double ebq = sub_toward_zero(eb, 4.0 * u);
         E = f32_toward_zero(2.0 * ebq);
         if (E > 0x1p126f) E = 0x1p126f;
         if (E < FLT_MIN) {

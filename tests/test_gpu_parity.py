@@ -460,3 +460,59 @@ def test_async_calls_chain_on_stream():
     assert fsz.fsz_compress_async(bad.data_ptr(), x.size, fsz.FSZ_REL, 1e-3, None, out.data_ptr(),
                                   cap, r1.data_ptr(), _stream()) == fsz.FSZ_OK
     assert fsz.read_result(r1)[1] == fsz.FSZ_ERR_NONFINITE
+
+
+def _check_bound_case(name, x, mode, value):
+    """Status and header step E through fsz_compress equal the exact rational
+    reading; accepted streams equal the oracle's byte for byte."""
+    from tests.test_oracle_resolve import expected
+
+    announce(f"{name} n={x.size} mode={mode} value={value!r}")
+    est, eE, _, _ = expected(x, mode, value)
+    st, got = gpu_compress(x, mode, value)
+    assert st == est, (name, st, est)
+    if st == fsz.FSZ_OK:
+        assert np.float32(fmt.parse_header(got)["E"]) == eE, name
+        assert got == oracle.compress(x, mode, value), name
+    return st
+
+
+def test_bound_threshold_at_eight_ulp():
+    """eb = 8 ulp(max|x|) is accepted and the next binary64 below it rejected,
+    through the device's bound resolution, for ABS and REL."""
+    from fractions import Fraction
+
+    from tests.test_oracle_resolve import ulp_above
+
+    for M in (1.0, 0.75, 1000.0, 6.0e37, 2.0 ** -100):
+        x = np.array([M, -M / 2, 0.0] * 100, dtype=np.float32)
+        at = float(8 * ulp_above(np.float32(M)))
+        assert _check_bound_case("abs at 8u", x, fsz.FSZ_ABS, at) == fsz.FSZ_OK
+        below = float(np.nextafter(at, 0.0))
+        assert _check_bound_case("abs below 8u", x, fsz.FSZ_ABS, below) == fsz.FSZ_ERR_EB_TOO_SMALL
+    for M in (1.0, 0.5, 128.0, 2.0 ** -40):
+        x = np.array([M, -M, M / 4] * 100, dtype=np.float32)
+        value = float(4 * ulp_above(np.float32(M)) / Fraction(M))
+        assert _check_bound_case("rel at 8u", x, fsz.FSZ_REL, value) == fsz.FSZ_OK
+        below = float(np.nextafter(value, 0.0))
+        assert _check_bound_case("rel below 8u", x, fsz.FSZ_REL, below) == fsz.FSZ_ERR_EB_TOO_SMALL
+
+
+def test_bound_step_exact_cases():
+    """Random (field, mode, value) pairs and the cases where a rounded binary64
+    difference eb - 4u would give another step: device E = exact rational E."""
+    from tests.test_oracle_resolve import _random_cases
+
+    seen = set()
+    for k, (x, mode, value) in enumerate(_random_cases(1, 300)):
+        seen.add(_check_bound_case(f"random {k}", np.tile(x, 9), mode, value))
+    assert fsz.FSZ_OK in seen and fsz.FSZ_ERR_EB_TOO_SMALL in seen
+    for value in (0.5, 3.0, 1024.0):
+        x = np.array([1e-12, -3e-13, 0.0] * 90, dtype=np.float32)
+        assert _check_bound_case("huge eb over tiny data", x, fsz.FSZ_ABS, value) == fsz.FSZ_OK
+    x = np.array([1e-40, -3e-41] * 200, dtype=np.float32)
+    assert _check_bound_case("subnormal step", x, fsz.FSZ_ABS, 1e-39) == fsz.FSZ_ERR_EB_TOO_SMALL
+    y = np.array([1.0, 2.0] * 200, dtype=np.float32)
+    assert _check_bound_case("clamped step", y, fsz.FSZ_ABS, 1e38) == fsz.FSZ_OK
+    big = np.array([3.3e38, -1.0] * 200, dtype=np.float32)
+    assert _check_bound_case("step too large", big, fsz.FSZ_ABS, 1e37) == fsz.FSZ_ERR_EB_TOO_LARGE

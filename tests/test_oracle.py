@@ -150,6 +150,49 @@ def test_cancellation_identity():
                 assert b[1] == a[1] + mu
 
 
+def one_pass_rates(q, mu):
+    """The one-read evaluation that Eq. (4) licenses (and the kernels use):
+    plain LZ1 / LZ2 residuals once; a block without a prediction restart has
+    one rate per order for all four variants; block 0 of each variant is
+    rated from its inner residuals plus its first one (LZ1) or two (LZ2)
+    residuals, moved by the tile mean for a centred variant."""
+    m = len(q)
+    l1 = fmt.residuals(q, 0, 0)
+    l2 = fmt.residuals(q, 1, 0)
+    nb = fmt.ceil_div(m, 32)
+    rates = [[0] * 8 for _ in range(4)]
+    for b in range(nb):
+        blk1 = [abs(int(v)) for v in l1[32 * b:32 * b + 32]]
+        blk2 = [abs(int(v)) for v in l2[32 * b:32 * b + 32]]
+        for v in range(4):
+            order2, cen = v & 1, v >> 1
+            if b > 0:
+                a = max(blk2 if order2 else blk1)
+            else:
+                c = mu if cen else 0
+                inner = blk2[2:] if order2 else blk1[1:]
+                first = [abs(int(q[0]) - c)]
+                if order2 and m >= 2:
+                    first.append(abs(int(l2[1]) + c))
+                a = max(inner + first)
+            rates[v][b] = fmt.bitlen(a)
+    cost = [sum(fmt.block_cost(r) for r in rates[v]) + 4 * (v >> 1) for v in range(4)]
+    return rates, cost
+
+
+def test_one_pass_evaluation_equals_plain_definition():
+    """Eq. (4) as a property: the one-read four-way evaluation gives the
+    oracle's per-variant rates and costs, which it forms from four full
+    residual passes."""
+    rng = np.random.default_rng(9)
+    for q in _tiny_tiles(rng):
+        x, eb, E, inv = unit_grid(q)
+        mu, ok, cost, rates = oracle.tile_eval(x, inv)
+        r1, c1 = one_pass_rates(q, mu)
+        assert rates.tolist() == r1
+        assert list(cost) == c1
+
+
 # ---------------------------------------------------------------- brute force
 
 
@@ -406,6 +449,24 @@ def test_corrupt_streams_rejected():
         assert oracle.decompress_status(c, n)[0] == want, name
     assert oracle.decompress_status(s[:-4], n)[0] == oracle.ERR_CORRUPT
     assert oracle.decompress_status(s[:20], n)[0] == oracle.ERR_CORRUPT
+
+
+@pytest.mark.parametrize("config", oracle.CONFIGS)
+def test_threaded_oracle_writes_the_serial_bytes(config):
+    """The CPU baseline's parallel mode (tiles over host threads) writes the
+    same stream and decodes to the same floats as the serial oracle."""
+    x = workloads.piecewise_quadratic((6, 50, 70), 4)[:20_993]
+    old = oracle.set_threads(1)
+    try:
+        feats = (oracle.FEATURES_ALL, 0, oracle.FEAT_CENTERING)
+        serial = [oracle.compress(x, oracle.REL, 1e-3, features=f, config=config) for f in feats]
+        dec = [oracle.decompress(s, x.size) for s in serial]
+        oracle.set_threads(5)
+        for f, s, y in zip(feats, serial, dec):
+            assert oracle.compress(x, oracle.REL, 1e-3, features=f, config=config) == s
+            assert np.array_equal(oracle.decompress(s, x.size), y)
+    finally:
+        oracle.set_threads(old)
 
 
 def test_tile_mean_is_pairwise_binary32():
