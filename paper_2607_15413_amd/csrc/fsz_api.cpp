@@ -842,6 +842,9 @@ fsz_status fsz_decompress_range_async(const void *d_cmp, size_t cmp_size, size_t
     if (!d_result || begin > end || end > n) return FSZ_ERR_INVALID_ARG;
     fsz_status st = check_decompress_args(d_cmp, cmp_size, d_out, end - begin);
     if (st != FSZ_OK) return st;
+    // The range pass reads rate bytes before the decoder checks the header:
+    // the buffer must hold every rate byte of an n-element stream.
+    if (cmp_size < kHeaderBytes + pad16(ceil_div((uint64_t)n, kBlock))) return FSZ_ERR_CORRUPT;
     Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);

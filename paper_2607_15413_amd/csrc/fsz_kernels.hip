@@ -1804,6 +1804,10 @@ __global__ __launch_bounds__(kStatsThreads) void range_partial_kernel(Decompress
     uint32_t bad = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
+        if (kHeaderBytes + b >= a.cmp_size) {  // a stream shorter than its rate header
+            bad = 1;
+            break;
+        }
         const uint32_t rb = a.cmp[kHeaderBytes + b];
         const bool head = (b & (kBlocksPerTile - 1)) == 0;
         bad |= head ? (rb & 0x20u) : (rb & 0xE0u);

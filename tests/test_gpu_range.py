@@ -134,3 +134,27 @@ def test_range_decode_beyond_4gib():
             y = out[guard + off:guard + off + m]
             assert torch.equal(y.view(torch.int32), expect.view(torch.int32)), (begin, end)
             assert bool(torch.isnan(out[:guard + off]).all()) and bool(torch.isnan(out[guard + off + m:]).all())
+
+
+def test_range_short_or_mismatched_stream_rejected():
+    """A buffer shorter than the rate header of the caller's n fails on the
+    host before any launch; a whole stream with another n fails in the decoder
+    with a size mismatch (the range pass then reads only the stream's own
+    rate bytes)."""
+    x = workloads.sinusoid_field(50_000, 6)
+    n = x.size
+    s = oracle.compress(x, oracle.REL, 1e-3)
+    rate_end = 32 + fmt.pad16(fmt.ceil_div(n, 32))
+    for size in (32, 40, rate_end - 1):
+        announce(f"range decode of a stream cut to {size} bytes")
+        st, _ = gpu_decompress_range(s[:size], n, 20_000, 30_000)
+        assert st == fsz.FSZ_ERR_CORRUPT, size
+    # the caller's n larger than the stream's: its rate header would end past the buffer
+    announce("range decode with n larger than the stream's rate header")
+    big = n + 64 * len(s)
+    st, _ = gpu_decompress_range(s, big, 20_000, 30_000)
+    assert st == fsz.FSZ_ERR_CORRUPT
+    # the caller's n a little larger: the buffer holds that many rate bytes, the header disagrees
+    announce("range decode with a mismatched n")
+    st, _ = gpu_decompress_range(s, n + 7, 20_000, 30_000)
+    assert st == fsz.FSZ_ERR_SIZE_MISMATCH

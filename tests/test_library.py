@@ -59,6 +59,10 @@ def test_invalid_arguments_rejected_on_host():
     assert st == fsz.FSZ_ERR_CAPACITY
     assert fsz.fsz_decompress(16, 8, 16, 10, None) == fsz.FSZ_ERR_CORRUPT
     assert fsz.fsz_decompress(0, 100, 16, 10, None) == fsz.FSZ_ERR_INVALID_ARG
+    # random access: a buffer shorter than the rate header of n elements is
+    # rejected before the range pass reads any rate byte (1000 elements: 32 + 32 bytes)
+    assert fsz.fsz_decompress_range_async(16, 63, 1000, 0, 10, 16, 16, None) == fsz.FSZ_ERR_CORRUPT
+    assert fsz.fsz_decompress_range_async(16, 40, 1000, 500, 990, 16, 16, None) == fsz.FSZ_ERR_CORRUPT
 
 
 def test_batch_invalid_jobs_rejected_on_host():
