@@ -45,9 +45,12 @@ class OracleError(RuntimeError):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        # FSZO_LIB: another build of the same source (the sanitizer test loads
+        # an AddressSanitizer / UBSan build this way)
+        path = os.environ.get("FSZO_LIB") or LIB
+        if path == LIB and not os.path.exists(LIB):
             build_library()
-        lib = ctypes.CDLL(LIB)
+        lib = ctypes.CDLL(path)
         u64 = ctypes.c_uint64
         p = ctypes.c_void_p
         lib.fszo_bound.argtypes = [u64]
