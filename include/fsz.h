@@ -52,7 +52,8 @@ typedef enum {
     FSZ_ERR_CORRUPT = 5,       /* stream fails validation */
     FSZ_ERR_SIZE_MISMATCH = 6, /* n differs from the stream's element count */
     FSZ_ERR_DEVICE = 7,        /* a HIP runtime call failed */
-    FSZ_ERR_EB_TOO_LARGE = 8   /* step so large that max|x| + step overflows binary32 */
+    FSZ_ERR_EB_TOO_LARGE = 8,  /* step so large that max|x| + step overflows binary32 */
+    FSZ_ERR_TOO_LARGE = 9      /* n beyond the fixed scratch of fsz_compress_noalloc_async */
 } fsz_status;
 
 /* Field statistics used to resolve the error bound (written by
@@ -131,6 +132,27 @@ fsz_status fsz_compress_async(const float *d_in, size_t n, fsz_eb_mode mode, dou
 
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
                                 fsz_result *d_result, void *stream);
+
+/* Allocation-free compression, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, work and stream bytes as
+ * fsz_compress_async (d_stats NULL runs the range pass), but the library's
+ * scratch words (chunk flags, ticket, range-pass partials and stats) live
+ * in one fixed array of device memory, 4,210,944 bytes per device, held
+ * from the first call on that device until the process ends; the call
+ * itself allocates nothing and enqueues only kernels (no memset or copy
+ * nodes), so it may be captured in a graph and replayed.
+ * Limit: n <= 2^30 elements, else FSZ_ERR_TOO_LARGE before any device work.
+ * Every call on one device shares that array and clears what it uses at
+ * its start: calls that overlap on one device (several streams, several
+ * host threads, or a graph replayed while another call runs) race and
+ * corrupt each other's output; serialize them.  The caller owns d_in,
+ * d_stats, d_out and d_result.  Errors: as fsz_compress_async, plus
+ * FSZ_ERR_TOO_LARGE; FSZ_ERR_DEVICE if the array's address cannot be
+ * found on the current device. */
+fsz_status fsz_compress_noalloc_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                                      const fsz_stats *d_stats, void *d_out, size_t out_capacity,
+                                      fsz_result *d_result, void *stream);
 
 /* Random-access decode: elements [begin, end) of the n-element field that
  * d_cmp[0..cmp_size) holds, into d_out[0 .. end - begin).  Decompression

@@ -745,6 +745,7 @@ const char *fsz_status_string(int s)
     case FSZ_ERR_SIZE_MISMATCH: return "element count differs from the stream";
     case FSZ_ERR_DEVICE: return "HIP runtime error";
     case FSZ_ERR_EB_TOO_LARGE: return "error bound too large for the field magnitude";
+    case FSZ_ERR_TOO_LARGE: return "field larger than the allocation-free scratch (2^30 elements)";
     default: return "unknown status";
     }
 }
@@ -877,6 +878,17 @@ fsz_status fsz_decompress_config_async(const void *d_cmp, size_t cmp_size, float
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);
     return enqueue_decompress_config(ws, d_cmp, cmp_size, d_out, n, block, tile_blocks, d_result);
+}
+
+fsz_status fsz_compress_noalloc_async(const float *d_in, size_t n, fsz_eb_mode mode, double value,
+                                      const fsz_stats *d_stats, void *d_out, size_t out_capacity,
+                                      fsz_result *d_result, void *stream)
+{
+    if (!d_result) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_compress_args(d_in, n, mode, value, d_out, out_capacity);
+    if (st != FSZ_OK) return st;
+    return compress_noalloc(d_in, n, mode, value, d_stats, d_out, out_capacity, d_result,
+                            static_cast<hipStream_t>(stream));
 }
 
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,

@@ -182,6 +182,12 @@ hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, b
                         const BatchShape &shape, hipStream_t s);
 bool batch_shape_supported(const BatchShape &shape);
 
+// Allocation-free compression: fsz_compress_async's work with every scratch
+// word in a fixed device array (fsz_kernels.hip); n above 2^30 elements
+// returns FSZ_ERR_TOO_LARGE.  Arguments already checked by the caller.
+fsz_status compress_noalloc(const float *d_in, uint64_t n, int mode, double value, const fsz_stats *d_stats,
+                            void *d_out, uint64_t cap, fsz_result *d_result, hipStream_t s);
+
 // Host-side argument checks shared by every entry point (fsz_api.cpp).
 bool aligned(const void *p, uintptr_t a);
 bool valid_bound(int mode, double value);

@@ -20,6 +20,8 @@
 
 #include <float.h>
 
+#include <mutex>
+
 namespace fsz {
 namespace {
 
@@ -2992,6 +2994,98 @@ hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, b
                              : launch_batch_t<false, 8>(b, any_compress, any_decompress, shape.groups_per_cu, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// ------------------------------------------------------------------ allocation-free compression
+//
+// fsz_compress_noalloc_async keeps its chunk flags, ticket and range-pass
+// partials in one fixed device array instead of the per-stream workspace.
+// Layout: [0, 16 KiB) range-pass partials, then the field stats (16 bytes)
+// and the ticket (8 bytes, 128 bytes further), then from byte 16640 one flag
+// word per chunk of the smallest chunk any compress kernel uses (8 tiles,
+// 2048 elements), enough for n <= kNoAllocMaxElements.  Each call clears the
+// flags it uses and the ticket with a fill kernel (no memset node, so the
+// call may be captured in a graph and replayed).
+constexpr uint64_t kNoAllocMaxElements = 1ull << 30;
+constexpr size_t kNoAllocStatsOff = sizeof(StatsPartial) * kStatsMaxBlocks;
+constexpr size_t kNoAllocTicketOff = kNoAllocStatsOff + 128;
+constexpr size_t kNoAllocFlagsOff = kNoAllocStatsOff + 256;
+constexpr uint64_t kNoAllocMaxFlags = kNoAllocMaxElements / ((uint64_t)kTile * kTilesPerWave);
+constexpr size_t kNoAllocScratchBytes = kNoAllocFlagsOff + kNoAllocMaxFlags * sizeof(unsigned long long);
+static_assert(kNoAllocScratchBytes == 16640 + 8 * 524288, "scratch layout");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array).  Host code passes
+// this address, never the array's name, to kernels.
+static unsigned char *scratch_address(int dev)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static unsigned char *addr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        addr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    return addr[dev];
+}
+
+__global__ __launch_bounds__(256) void zero_words_kernel(unsigned long long *p, uint64_t count,
+                                                         unsigned long long *one)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *one = 0;
+}
+
+fsz_status compress_noalloc(const float *d_in, uint64_t n, int mode, double value, const fsz_stats *d_stats,
+                            void *d_out, uint64_t cap, fsz_result *d_result, hipStream_t s)
+{
+    if (n > kNoAllocMaxElements) return FSZ_ERR_TOO_LARGE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FSZ_ERR_DEVICE;
+    unsigned char *base = scratch_address(dev);
+    if (!base) return FSZ_ERR_DEVICE;
+    StatsPartial *partials = reinterpret_cast<StatsPartial *>(base);
+    fsz_stats *stats = reinterpret_cast<fsz_stats *>(base + kNoAllocStatsOff);
+    unsigned long long *ticket = reinterpret_cast<unsigned long long *>(base + kNoAllocTicketOff);
+    unsigned long long *flags = reinterpret_cast<unsigned long long *>(base + kNoAllocFlagsOff);
+
+    CompressArgs a{};
+    a.x = d_in;
+    a.n = n;
+    a.ntiles = ceil_div(n, kTile);
+    a.nblocks = ceil_div(n, kBlock);
+    a.nchunks = a.ntiles ? ceil_div(a.ntiles, kTilesPerChunk) : 1;
+    a.data0 = kHeaderBytes + pad16(a.nblocks);
+    a.out = static_cast<uint8_t *>(d_out);
+    a.capacity = cap;
+    a.value = value;
+    a.mode = mode;
+    a.features = kFeaturesAll;
+    a.epoch = 1;       // flags start cleared at every call, so one epoch serves
+    a.flag_epoch = 1;  // every call
+    a.flags = flags;
+    a.ticket = ticket;
+    a.final = d_result;
+    const uint64_t nflags = a.ntiles ? ceil_div(a.ntiles, kTilesPerWave) : 1;  // <= kNoAllocMaxFlags
+    const uint64_t want = ceil_div(nflags, 256);
+    const unsigned grid = (unsigned)(want < 1024 ? want : 1024);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid), dim3(256), 0, s, flags, nflags, ticket);
+    if (hipGetLastError() != hipSuccess) return FSZ_ERR_DEVICE;
+    if (!d_stats) {
+        const StatsArgs sa{d_in, n, stats, partials};
+        if (launch_stats(sa, s) != hipSuccess) return FSZ_ERR_DEVICE;
+        d_stats = stats;
+    }
+    a.stats = d_stats;
+    const bool al16 = (reinterpret_cast<uintptr_t>(d_in) & 15u) == 0;
+    if (launch_compress(a, al16, tuning().staged_compress, s) != hipSuccess) return FSZ_ERR_DEVICE;
+    return FSZ_OK;
 }
 
 }  // namespace fsz

@@ -30,6 +30,7 @@ FSZ_ERR_CORRUPT = 5
 FSZ_ERR_SIZE_MISMATCH = 6
 FSZ_ERR_DEVICE = 7
 FSZ_ERR_EB_TOO_LARGE = 8
+FSZ_ERR_TOO_LARGE = 9
 
 # names of every C entry point declared in include/fsz.h
 EXPORTS = (
@@ -40,6 +41,7 @@ EXPORTS = (
     "fsz_compress_ex",
     "fsz_decompress",
     "fsz_compress_async",
+    "fsz_compress_noalloc_async",
     "fsz_decompress_async",
     "fsz_decompress_range_async",
     "fsz_compress_features_async",
@@ -149,6 +151,8 @@ def load_library():
     lib.fsz_decompress.restype = ctypes.c_int
     lib.fsz_compress_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, vp, sz, vp, vp]
     lib.fsz_compress_async.restype = ctypes.c_int
+    lib.fsz_compress_noalloc_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, vp, sz, vp, vp]
+    lib.fsz_compress_noalloc_async.restype = ctypes.c_int
     lib.fsz_compress_features_async.argtypes = [vp, sz, ctypes.c_int, ctypes.c_double, vp, ctypes.c_uint, vp, sz,
                                                 vp, vp]
     lib.fsz_compress_features_async.restype = ctypes.c_int
@@ -238,6 +242,13 @@ def fsz_compress_async(d_in: int, n: int, mode: int, value: float, d_stats, d_ou
     """Enqueue only; the outcome lands in the device fsz_result at d_result."""
     return load_library().fsz_compress_async(d_in, n, mode, value, d_stats, d_out, out_capacity,
                                              d_result, stream)
+
+
+def fsz_compress_noalloc_async(d_in: int, n: int, mode: int, value: float, d_stats, d_out: int,
+                               out_capacity: int, d_result: int, stream=None) -> int:
+    """As fsz_compress_async, with the library's scratch in a fixed device array (allocates nothing)."""
+    return load_library().fsz_compress_noalloc_async(d_in, n, mode, value, d_stats, d_out, out_capacity,
+                                                     d_result, stream)
 
 
 def fsz_decompress_range_async(d_cmp: int, cmp_size: int, n: int, begin: int, end: int, d_out: int,

@@ -38,8 +38,9 @@ def test_bound_matches_format_arithmetic():
 
 
 def test_status_strings():
-    for s in range(9):
+    for s in range(10):
         assert isinstance(fsz.fsz_status_string(s), str)
+        assert fsz.fsz_status_string(s) != "unknown status"
     assert fsz.fsz_status_string(0) == "ok"
 
 
@@ -59,6 +60,11 @@ def test_invalid_arguments_rejected_on_host():
     assert st == fsz.FSZ_ERR_CAPACITY
     assert fsz.fsz_decompress(16, 8, 16, 10, None) == fsz.FSZ_ERR_CORRUPT
     assert fsz.fsz_decompress(0, 100, 16, 10, None) == fsz.FSZ_ERR_INVALID_ARG
+    # allocation-free compression: fields beyond its fixed scratch (2^30 elements)
+    big = (1 << 30) + 1
+    assert fsz.fsz_compress_noalloc_async(16, big, 1, 1e-3, None, 16, fsz.fsz_compressed_bound(big), 16,
+                                          None) == fsz.FSZ_ERR_TOO_LARGE
+    assert fsz.fsz_compress_noalloc_async(16, 10, 1, 1e-3, None, 16, 1000, None, None) == fsz.FSZ_ERR_INVALID_ARG
     # random access: a buffer shorter than the rate header of n elements is
     # rejected before the range pass reads any rate byte (1000 elements: 32 + 32 bytes)
     assert fsz.fsz_decompress_range_async(16, 63, 1000, 0, 10, 16, 16, None) == fsz.FSZ_ERR_CORRUPT
