@@ -133,6 +133,19 @@ fsz_status fsz_compress_async(const float *d_in, size_t n, fsz_eb_mode mode, dou
 fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
                                 fsz_result *d_result, void *stream);
 
+/* Pre-zeroed decompression (Sec. III-A: the decoder clears the output first
+ * when the compression ratio is high, so that all-zero data need no
+ * decoding): fills d_out[0, n) with +0.0, then decodes, skipping every group
+ * of 8 tiles whose blocks all have rate 0 and whose tiles are all uncentred
+ * (they decode to +0.0).  The values equal fsz_decompress_async's bit for
+ * bit.  Arguments, ownership and errors as fsz_decompress_async; on an
+ * error the output holds zeros or partial values.  fsz_decompress and
+ * fsz_decompress_async choose this decoder by themselves when
+ * 4n / cmp_size exceeds the threshold in the environment variable
+ * FSZ_PREZERO_CR (read once; unset or 0: never). */
+fsz_status fsz_decompress_prezero_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
+                                        fsz_result *d_result, void *stream);
+
 /* Allocation-free compression, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments, work and stream bytes as

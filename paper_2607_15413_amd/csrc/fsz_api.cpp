@@ -36,6 +36,8 @@ const Tuning &tuning()
             const int k = std::atoi(e);
             if (k == 4 || k == 8 || k == 16) v.dec_waves = k;
         }
+        if (const char *e = std::getenv("FSZ_PREZERO_CR")) v.prezero_min_cr = std::atof(e);
+        if (const char *e = std::getenv("FSZ_DEC_PRESCAN")) v.dec_prescan = std::atoi(e) != 0;
         if (const char *e = std::getenv("FSZ_GRID_FACTOR")) {
             const int f = std::atoi(e);
             if (f >= 1 && f <= 64) v.grid_factor = f;
@@ -112,6 +114,10 @@ struct Workspace {
     // five-read baseline: evaluation tables (53 bytes per tile)
     uint8_t *d_naive = nullptr;
     uint64_t naive_cap = 0;
+    // whole-field decodes: chunk offsets of the pre-pass and its outcome word
+    unsigned long long *d_offs = nullptr;
+    uint64_t offs_cap = 0;
+    uint32_t *d_go = nullptr;
 };
 
 std::mutex g_mu;
@@ -140,6 +146,7 @@ Workspace *get_workspace(hipStream_t s, fsz_status *st)
                 ok(hipMalloc(&ws->d_stats, sizeof(fsz_stats))) &&
                 ok(hipMalloc(&ws->d_partials, sizeof(StatsPartial) * kStatsMaxBlocks)) &&
                 ok(hipMalloc(&ws->b_ticket, sizeof(unsigned long long))) &&
+                ok(hipMalloc(&ws->d_go, sizeof(uint32_t))) &&
                 ok(hipMemset(ws->d_ticket, 0, sizeof(unsigned long long))) &&
                 ok(hipMemset(ws->b_ticket, 0, sizeof(unsigned long long))) &&
                 ok(hipMemset(ws->d_final, 0, sizeof(fsz_result))) &&
@@ -274,7 +281,7 @@ fsz_status enqueue_compress_naive(Workspace *ws, const float *d_in, uint64_t n, 
 }
 
 fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_size, float *d_out, uint64_t n,
-                              fsz_result *d_final, uint32_t *epoch_out)
+                              fsz_result *d_final, uint32_t *epoch_out, bool prezero = false)
 {
     DecompressArgs a{};
     a.cmp = static_cast<const uint8_t *>(d_cmp);
@@ -295,9 +302,28 @@ fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_siz
     a.flags = ws->d_flags;
     a.ticket = ws->d_ticket;
     a.final = d_final;
-    if (!ok(launch_decompress(a, aligned(d_out, 16), tuning().staged_decompress, ws->stream))) return FSZ_ERR_DEVICE;
+    hipError_t e;
+    if (prezero) {
+        e = launch_decompress_prezero(a, aligned(d_out, 16), ws->stream);
+    } else if (tuning().dec_prescan && tuning().staged_decompress) {
+        // chunk offsets from the rate header first (chunks of 64 tiles)
+        if (!grow(&ws->d_offs, &ws->offs_cap, std::max<uint64_t>(ceil_div(a.ntiles, 64), 1), ws->stream))
+            return FSZ_ERR_DEVICE;
+        e = launch_decompress_prescan(a, ws->d_offs, ws->d_go, aligned(d_out, 16), ws->stream);
+    } else {
+        e = launch_decompress(a, aligned(d_out, 16), tuning().staged_decompress, ws->stream);
+    }
+    if (!ok(e)) return FSZ_ERR_DEVICE;
     *epoch_out = a.epoch;
     return FSZ_OK;
+}
+
+// Whole-field decodes pick the pre-zeroed decoder for streams whose
+// compression ratio, judged from the buffer size, exceeds the threshold.
+bool auto_prezero(uint64_t n, uint64_t cmp_size)
+{
+    const double cr = tuning().prezero_min_cr;
+    return cr > 0.0 && (double)(4 * n) > cr * (double)cmp_size;
 }
 
 // Tile configurations (Sec. VI-C, Table V): the generic lane-per-segment
@@ -791,7 +817,7 @@ fsz_status fsz_decompress(const void *d_cmp, size_t cmp_size, float *d_out, size
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);
     uint32_t epoch = 0;
-    st = enqueue_decompress(ws, d_cmp, cmp_size, d_out, n, ws->d_final, &epoch);
+    st = enqueue_decompress(ws, d_cmp, cmp_size, d_out, n, ws->d_final, &epoch, auto_prezero(n, cmp_size));
     if (st != FSZ_OK) return st;
     return finish(ws, epoch, nullptr);
 }
@@ -901,7 +927,20 @@ fsz_status fsz_decompress_async(const void *d_cmp, size_t cmp_size, float *d_out
     if (!ws) return st;
     std::lock_guard<std::mutex> g(ws->mu);
     uint32_t epoch = 0;
-    return enqueue_decompress(ws, d_cmp, cmp_size, d_out, n, d_result, &epoch);
+    return enqueue_decompress(ws, d_cmp, cmp_size, d_out, n, d_result, &epoch, auto_prezero(n, cmp_size));
+}
+
+fsz_status fsz_decompress_prezero_async(const void *d_cmp, size_t cmp_size, float *d_out, size_t n,
+                                        fsz_result *d_result, void *stream)
+{
+    if (!d_result) return FSZ_ERR_INVALID_ARG;
+    fsz_status st = check_decompress_args(d_cmp, cmp_size, d_out, n);
+    if (st != FSZ_OK) return st;
+    Workspace *ws = get_workspace(static_cast<hipStream_t>(stream), &st);
+    if (!ws) return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    uint32_t epoch = 0;
+    return enqueue_decompress(ws, d_cmp, cmp_size, d_out, n, d_result, &epoch, true);
 }
 
 fsz_status fsz_batch_async(const fsz_job *jobs, size_t njobs, const fsz_tuning *tuning, void *stream)

@@ -86,6 +86,10 @@ struct DecompressArgs {
     uint64_t tile_begin, tile_end, elem_begin, elem_end;
     const unsigned long long *range_base;
     uint32_t cfg_flags;  // tile-configuration decoders: the header flags bits 2-4 required
+    // Whole-field decodes with the offsets pre-pass: each chunk's byte offset
+    // after data0 (written by the pre-pass), and its outcome (FSZ_OK: decode).
+    const unsigned long long *offsets;
+    const uint32_t *go;
     uint32_t epoch, flag_epoch;
     unsigned long long *flags;
     unsigned long long *ticket;  // zero between launches (self-resetting)
@@ -154,6 +158,14 @@ hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged
 // (a.nchunks counts chunks of kTilesPerChunk tiles).
 hipError_t launch_compress_naive(const CompressArgs &a, const NaiveTables &t, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s);
+// Whole-field decompression with the chunk offsets computed first from the
+// rate header (no lookback in the decoder): offsets has room for one word per
+// chunk of kTilesPerWave * 8 tiles, go for one status word.
+hipError_t launch_decompress_prescan(const DecompressArgs &a, unsigned long long *offsets, uint32_t *go,
+                                     bool out_aligned16, hipStream_t s);
+// Pre-zeroed decompression (Sec. III-A): a fill of out[0, n) with +0.0, then
+// the decoder that skips waves whose tiles are all zero.
+hipError_t launch_decompress_prezero(const DecompressArgs &a, bool out_aligned16, hipStream_t s);
 // Tile configurations (Sec. VI-C): one chunk of kCfgWaves x 64 32-element segments per
 // workgroup (a.nchunks counts those), block in {32, 64}, tile_blocks in {4, 8, 16}.
 hipError_t launch_compress_cfg(const CompressArgs &a, int block, int tile_blocks, bool in_aligned16, hipStream_t s);
@@ -205,8 +217,11 @@ bool reserve_batch(hipStream_t stream, uint64_t jobs, uint64_t chunks, uint64_t 
 // compress input through LDS), FSZ_PIPE (0: no pipelined persistent
 // compression for 16-byte aligned inputs), FSZ_PIPE_WAVES (its waves per
 // workgroup: 1, 2, 4 or 8), FSZ_DEC_WAVES (waves per decompression
-// workgroup: 4, 8 or 16) and FSZ_GRID_FACTOR (persistent workgroups per CU slot,
-// default 1).
+// workgroup: 4, 8 or 16), FSZ_GRID_FACTOR (persistent workgroups per CU slot,
+// default 1) and FSZ_PREZERO_CR (whole-field decodes of streams above this
+// compression ratio, judged from the buffer size, use the pre-zeroed decoder)
+// and FSZ_DEC_PRESCAN (0: whole-field decodes find chunk offsets by lookback
+// instead of the offsets pre-pass).
 struct Tuning {
     bool staged_compress = true;
     bool staged_decompress = true;
@@ -215,6 +230,8 @@ struct Tuning {
     int pipe_waves = 8;         // waves per workgroup of the pipelined compression (1, 2, 4, 8)
     int dec_waves = 8;          // waves per workgroup of the decompression (4, 8, 16)
     int grid_factor = 1;
+    double prezero_min_cr = 0.0;  // whole-field decodes pre-zero above this CR (0: never)
+    bool dec_prescan = true;      // whole-field decodes take chunk offsets from a pre-pass (no lookback)
 };
 const Tuning &tuning();
 

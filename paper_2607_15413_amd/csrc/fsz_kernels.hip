@@ -1524,6 +1524,7 @@ __global__ __launch_bounds__(W * 64) void compress_pipe2_kernel(CompressArgs a)
 // Per-lane state of one chunk between the size pass and the decode pass.
 struct DecChunk {
     uint64_t chunk;
+    uint64_t base;  // the chunk's data offset after data0 (decodes with the offsets pre-pass)
     uint32_t r, blk_off, tile_excl, wave_total;
     int order2, cent;
 };
@@ -1541,8 +1542,26 @@ struct DecompressShared {
 // successors' lookbacks rarely wait.
 // RANGE: decode the tiles [a.tile_begin, a.tile_end) only (random access);
 // otherwise the whole field (the range fields are not read).
+// The lane's rate byte of `chunk` (0 past the end or outside a range).
 template <int W, bool RANGE = false>
-__device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t chunk, int slot,
+__device__ __forceinline__ uint32_t dec_rate_byte(const DecompressArgs &a, uint64_t chunk)
+{
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const uint64_t tile =
+        (RANGE ? a.tile_begin : 0) + chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave + (lane >> 3);
+    const bool tile_ok = tile < (RANGE ? a.tile_end : a.ntiles);
+    const uint64_t gblock = tile * kBlocksPerTile + (lane & 7);
+    const bool blk_ok = (RANGE ? tile_ok : true) && gblock < a.nblocks;
+    return blk_ok ? a.cmp[kHeaderBytes + gblock] : 0u;
+}
+
+// rb: the lane's rate byte from dec_rate_byte (loaded ahead by the caller).
+// PRESCAN: the offsets pre-pass has checked the rate bytes and placed every
+// chunk; the chunk's offset is read instead of publishing its aggregate.
+template <int W, bool RANGE = false, bool PRESCAN = false>
+__device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t chunk, uint32_t rb, int slot,
                                               DecompressShared<W> &sh)
 {
     const int tid = threadIdx.x;
@@ -1554,7 +1573,6 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
     const bool tile_ok = tile < (RANGE ? a.tile_end : a.ntiles);
     const uint64_t gblock = tile * kBlocksPerTile + j;
     const bool blk_ok = (RANGE ? tile_ok : true) && gblock < a.nblocks;
-    const uint32_t rb = blk_ok ? a.cmp[kHeaderBytes + gblock] : 0u;
     const bool bad = blk_ok && (j == 0 ? (rb & 0x20u) : (rb & 0xE0u)) != 0;
     const uint32_t head = (uint32_t)group_head((int)rb);
     DecChunk d;
@@ -1568,6 +1586,13 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
     d.tile_excl = (uint32_t)incl - Z;
     d.wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
     d.blk_off = d.tile_excl + group_excl_scan(S, j) + 4u * d.cent;
+    d.base = 0;
+    if (PRESCAN) {
+        d.base = a.offsets[__builtin_amdgcn_readfirstlane((uint32_t)chunk)];
+        if (lane == 0) sh.wave_total[slot][w] = d.wave_total;
+        lds_barrier();
+        return d;
+    }
     const bool wave_bad = __ballot(bad) != 0;
     if (lane == 0) {
         sh.wave_total[slot][w] = d.wave_total;
@@ -1583,12 +1608,23 @@ __device__ __forceinline__ DecChunk dec_sizes(const DecompressArgs &a, uint64_t 
     return d;
 }
 
-// Decompression steps 3-5: lookback offset, bit-unshuffle, inverse
-// cross-block prediction (one inclusive scan for LZ1, two for LZ2, plus the
-// tile mean), x' = (float)q * E.
-template <bool ALIGNED, bool STAGED, int W, bool RANGE = false>
-__device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChunk &d, int slot, float E,
-                                           uint64_t total, bool indep, uint32_t *st, DecompressShared<W> &sh)
+// Decompression step 3 (Sec. III-A): the chunk's byte offset from the
+// lookback (wave 0; the workgroup waits at one barrier), then where the
+// wave's share of the chunk's data starts.  The workgroup owning the last
+// chunk reports the outcome.  live: the wave has blocks to decode.
+// PREZERO: the output was cleared to +0.0 before the launch (Sec. III-A, for
+// highly compressible streams); a wave whose blocks all have rate 0 and whose
+// tiles are all uncentred decodes to q = 0, i.e. +0.0 everywhere, and is not
+// live.
+struct DecPlace {
+    const uint8_t *wave_data;
+    uint64_t tile0;
+    bool live;
+};
+
+template <int W, bool RANGE = false, bool PREZERO = false, bool PRESCAN = false>
+__device__ __forceinline__ DecPlace dec_place(const DecompressArgs &a, const DecChunk &d, int slot, uint64_t total,
+                                              DecompressShared<W> &sh)
 {
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -1599,6 +1635,17 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     for (int k = 0; k < W; k++) {
         if (k < w) wave_base += sh.wave_total[slot][k];
         chunk_total += sh.wave_total[slot][k];
+    }
+    if (PRESCAN) {  // placed and checked by the pre-pass
+        DecPlace p;
+        p.tile0 = d.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
+        p.wave_data = a.cmp + a.data0 + d.base + wave_base;
+        p.live = p.tile0 < a.ntiles;
+        if (PREZERO && p.live) {
+            const uint64_t gblock = (p.tile0 + (lane >> 3)) * kBlocksPerTile + j;
+            p.live = __ballot(gblock < a.nblocks && (d.r != 0 || d.cent != 0)) != 0;
+        }
+        return p;
     }
     const bool bad = sh.bad[slot] != 0;
     const uint64_t base0 = RANGE ? *a.range_base : 0;  // data of tiles before the range
@@ -1620,12 +1667,30 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     }
     lds_barrier();
     const uint64_t base = sh.base;
-    const uint64_t tile0 = (RANGE ? a.tile_begin : 0) + d.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
-    if (bad || a.data0 + base + chunk_total > total || tile0 >= (RANGE ? a.tile_end : a.ntiles)) return;
+    DecPlace p;
+    p.tile0 = (RANGE ? a.tile_begin : 0) + d.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
+    p.wave_data = a.cmp + a.data0 + base + wave_base;
+    p.live = !(bad || a.data0 + base + chunk_total > total || p.tile0 >= (RANGE ? a.tile_end : a.ntiles));
+    if (PREZERO && p.live) {
+        const uint64_t gblock = (p.tile0 + (lane >> 3)) * kBlocksPerTile + j;
+        p.live = __ballot(gblock < a.nblocks && (d.r != 0 || d.cent != 0)) != 0;
+    }
+    return p;
+}
 
+// Decompression steps 4-5 of a live wave: bit-unshuffle, inverse cross-block
+// prediction (one inclusive scan for LZ1, two for LZ2, plus the tile mean),
+// x' = (float)q * E.
+template <bool ALIGNED, bool STAGED, int W, bool RANGE = false>
+__device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChunk &d, const DecPlace &p, float E,
+                                           bool indep, uint32_t *st)
+{
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 7;
+    const uint64_t tile0 = p.tile0;
     const uint64_t gblock = (tile0 + (lane >> 3)) * kBlocksPerTile + j;
     const bool blk_ok = gblock < a.nblocks;
-    const uint8_t *wave_data = a.cmp + a.data0 + base + wave_base;
+    const uint8_t *wave_data = p.wave_data;
     int mu = 0;
     if (d.cent) mu = (int)*reinterpret_cast<const uint32_t *>(wave_data + d.tile_excl);
 
@@ -1638,7 +1703,7 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
         uint32_t Rg[8];
 #pragma unroll
-        for (int p = 0; p < 8; p++) Rg[p] = 8 * g + p < nwords ? words[8 * g + p] : 0u;
+        for (int k = 0; k < 8; k++) Rg[k] = 8 * g + k < nwords ? words[8 * g + k] : 0u;
         transpose8(Rg);
         // Rg[rho] byte k = byte g of code 8k + 7 - rho
 #pragma unroll
@@ -1759,7 +1824,7 @@ __device__ __forceinline__ int dec_header(const DecompressArgs &a, float &E, uin
 // publishes its aggregate) runs before the decode of the current one.
 // W waves per workgroup; a chunk is 8 tiles per wave (a.nchunks counts chunks
 // of that size).
-template <bool ALIGNED, bool STAGED, int W, bool RANGE = false>
+template <bool ALIGNED, bool STAGED, int W, bool RANGE = false, bool PREZERO = false, bool PRESCAN = false>
 __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint32_t stage[STAGED ? W * kStageWaveDwords : 4];
@@ -1771,7 +1836,9 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
     uint64_t total;
     bool indep;
     const int hst = dec_header(a, E, total, indep);
-    if (hst != FSZ_OK) {
+    if (PRESCAN) {  // the pre-pass checked the stream and reported its outcome
+        if (*a.go != FSZ_OK) return;
+    } else if (hst != FSZ_OK) {
         if (tid == 0 && blockIdx.x == 0) write_final(a.final, 0, hst, a.epoch);
         return;
     }
@@ -1781,15 +1848,134 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
     uint64_t cur = next_ticket(a.ticket, takes, sh, tslot);
     if (cur >= a.nchunks) return;
     int slot = 0;
-    DecChunk dc = dec_sizes<W, RANGE>(a, cur, slot, sh);
+    DecChunk dc = dec_sizes<W, RANGE, PRESCAN>(a, cur, dec_rate_byte<W, RANGE>(a, cur), slot, sh);
     for (;;) {
         const uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
         DecChunk dn;
-        if (nxt < a.nchunks) dn = dec_sizes<W, RANGE>(a, nxt, slot ^ 1, sh);
-        dec_decode<ALIGNED, STAGED, W, RANGE>(a, dc, slot, E, total, indep, st, sh);
+        if (nxt < a.nchunks)
+            dn = dec_sizes<W, RANGE, PRESCAN>(a, nxt, dec_rate_byte<W, RANGE>(a, nxt), slot ^ 1, sh);
+        const DecPlace pl = dec_place<W, RANGE, PREZERO, PRESCAN>(a, dc, slot, total, sh);
+        if (pl.live) dec_decode<ALIGNED, STAGED, W, RANGE>(a, dc, pl, E, indep, st);
         if (nxt >= a.nchunks) break;
         dc = dn;
         slot ^= 1;
+    }
+}
+
+// ------------------------------------------------------------------ whole-field decode: offsets pre-pass
+//
+// A whole-field decode's chunk offsets depend on the rate header alone
+// (decompression steps 1-2, Sec. III-A), so two small launches compute them
+// before the decoder starts, and the decoder reads its chunk's offset instead
+// of waiting on a lookback:
+//   dec_chunk_sizes_kernel: one lane per tile adds its block sizes (and the
+//     mean); a chunk's TPC lanes add up; bit 63 marks a reserved rate-byte bit;
+//   dec_offsets_kernel: one workgroup turns the sizes into exclusive offsets
+//     in place, checks them against the header's total and the padding, and
+//     writes the outcome (the decoder's go word and the call's result).
+
+// wave-uniform sum of v over the aligned group of TPC lanes holding this lane
+template <int TPC>
+__device__ __forceinline__ uint32_t group_sum_lanes(uint32_t v)
+{
+#pragma unroll
+    for (int off = 1; off < TPC; off <<= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
+    return v;
+}
+
+template <int TPC>
+__global__ __launch_bounds__(256) void dec_chunk_sizes_kernel(DecompressArgs a, unsigned long long *sizes,
+                                                              uint64_t nchunks)
+{
+    float E;
+    uint64_t total;
+    bool indep;
+    if (dec_header(a, E, total, indep) != FSZ_OK) return;  // the offsets kernel reports it
+    const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t z = 0, bad = 0;
+    if (tile < a.ntiles) {
+        // the 8 rate bytes of a tile lie inside the (zero-padded) rate header,
+        // which the header check placed inside the buffer
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(a.cmp + kHeaderBytes + tile * kBlocksPerTile);
+        const uint32_t w0 = p[0], w1 = p[1];
+        const uint64_t nb64 = a.nblocks - tile * kBlocksPerTile;
+        const uint32_t nb = nb64 < kBlocksPerTile ? (uint32_t)nb64 : (uint32_t)kBlocksPerTile;
+#pragma unroll
+        for (uint32_t b = 0; b < kBlocksPerTile; b++) {
+            const uint32_t rb = ((b < 4 ? w0 : w1) >> (8 * (b & 3))) & 0xFFu;
+            if (b < nb) {
+                bad |= b == 0 ? (rb & 0x20u) : (rb & 0xE0u);
+                z += block_bytes(rb & 31u) + ((b == 0 && (rb & 0x40u)) ? 4u : 0u);
+            }
+        }
+    }
+    const uint32_t sum = group_sum_lanes<TPC>(z);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long gmask = (TPC == 64 ? ~0ull : ((1ull << TPC) - 1)) << (lane & ~(TPC - 1));
+    const bool gbad = (__ballot(bad != 0) & gmask) != 0;
+    const uint64_t chunk = tile / TPC;
+    if ((lane & (TPC - 1)) == 0 && chunk < nchunks) sizes[chunk] = sum | (gbad ? 1ull << 63 : 0ull);
+}
+
+// inclusive prefix over the 64 lanes of the wave, 64-bit (every lane active)
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v)
+{
+    v += dpp64<kRowShr1>(v);
+    v += dpp64<kRowShr2>(v);
+    v += dpp64<kRowShr4>(v);
+    v += dpp64<kRowShr8>(v);
+    v += dpp64<kRowBcast15, 0xA>(v);
+    v += dpp64<kRowBcast31, 0xC>(v);
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void dec_offsets_kernel(DecompressArgs a, unsigned long long *offs,
+                                                           uint64_t nchunks, uint32_t *go)
+{
+    __shared__ unsigned long long wsum[16];
+    __shared__ int any_bad;
+    float E;
+    uint64_t total;
+    bool indep;
+    const int hst = dec_header(a, E, total, indep);
+    if (hst != FSZ_OK) {
+        if (threadIdx.x == 0) {
+            *go = (uint32_t)hst;
+            write_final(a.final, 0, hst, a.epoch);
+        }
+        return;
+    }
+    const int tid = threadIdx.x;
+    if (tid == 0) any_bad = 0;
+    const uint64_t per = (nchunks + 1023) / 1024;
+    const uint64_t lo = (uint64_t)tid * per < nchunks ? (uint64_t)tid * per : nchunks;
+    const uint64_t hi = lo + per < nchunks ? lo + per : nchunks;
+    constexpr unsigned long long kBad = 1ull << 63;
+    unsigned long long sum = 0;
+    bool bad = false;
+    for (uint64_t c = lo; c < hi; c++) {
+        const unsigned long long v = offs[c];
+        bad = bad || (v & kBad) != 0;
+        sum += v & ~kBad;
+    }
+    __syncthreads();
+    if (bad) any_bad = 1;
+    const unsigned long long incl = wave_incl_scan_u64(sum);
+    if ((tid & 63) == 63) wsum[tid >> 6] = incl;
+    __syncthreads();
+    unsigned long long excl = incl - sum;
+    for (int k = 0; k < (tid >> 6); k++) excl += wsum[k];
+    for (uint64_t c = lo; c < hi; c++) {
+        const unsigned long long v = offs[c] & ~kBad;
+        offs[c] = excl;
+        excl += v;
+    }
+    if (tid == 1023) {  // excl now holds the sum of every chunk
+        bool ok = any_bad == 0 && a.data0 + excl == total;
+        for (uint64_t k = kHeaderBytes + a.nblocks; ok && k < a.data0; k++) ok = a.cmp[k] == 0;
+        const uint32_t st = ok ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT;
+        *go = st;
+        write_final(a.final, total, st, a.epoch);
     }
 }
 
@@ -1997,8 +2183,9 @@ __global__ __launch_bounds__(W * 64) void batch_kernel(BatchArgs b)
             if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, hst, a.epoch);
             return;
         }
-        const DecChunk dc = dec_sizes<W>(a, chunk, 0, sh.d);
-        dec_decode<ALIGNED, true, W>(a, dc, 0, E, total, indep, st, sh.d);
+        const DecChunk dc = dec_sizes<W>(a, chunk, dec_rate_byte<W>(a, chunk), 0, sh.d);
+        const DecPlace pl = dec_place<W>(a, dc, 0, total, sh.d);
+        if (pl.live) dec_decode<ALIGNED, true, W>(a, dc, pl, E, indep, st);
     }
 }
 
@@ -2035,21 +2222,23 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (tid == 0 && chunk == a.nchunks - 1) write_final(a.final, 0, hst, a.epoch);
             have = false;
         } else {
-            if (!have) dc = dec_sizes<W>(a, chunk, slot, sh);
+            if (!have) dc = dec_sizes<W>(a, chunk, dec_rate_byte<W>(a, chunk), slot, sh);
             bool next_have = false;
             DecChunk dn;
             if (nxt < b.total_chunks) {
                 const uint32_t job2 = __builtin_amdgcn_readfirstlane(find_job(b.chunk_end, b.njobs, nxt));
                 const DecompressArgs a2 = batch_decompress_args(b, b.jobs[job2]);
+                const uint64_t chunk2 = nxt - b.jobs[job2].chunk_base;
                 float E2;
                 uint64_t total2;
                 bool indep2;
                 if (dec_header(a2, E2, total2, indep2) == FSZ_OK) {
-                    dn = dec_sizes<W>(a2, nxt - b.jobs[job2].chunk_base, slot ^ 1, sh);
+                    dn = dec_sizes<W>(a2, chunk2, dec_rate_byte<W>(a2, chunk2), slot ^ 1, sh);
                     next_have = true;
                 }
             }
-            dec_decode<ALIGNED, true, W>(a, dc, slot, E, total, indep, st, sh);
+            const DecPlace pl = dec_place<W>(a, dc, slot, total, sh);
+            if (pl.live) dec_decode<ALIGNED, true, W>(a, dc, pl, E, indep, st);
             if (next_have) {
                 dc = dn;
                 slot ^= 1;
@@ -2716,17 +2905,66 @@ static hipError_t launch_compress_t(const CompressArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool ALIGNED, bool STAGED, int W, bool RANGE = false>
+template <bool ALIGNED, bool STAGED, int W, bool RANGE = false, bool PREZERO = false, bool PRESCAN = false>
 static hipError_t launch_decompress_w(const DecompressArgs &a, hipStream_t s)
 {
     // the arguments count chunks of kTilesPerChunk tiles
     DecompressArgs p = a;
     const uint64_t tiles = p.tile_end - p.tile_begin;
     p.nchunks = tiles ? ceil_div(tiles, (uint64_t)kTilesPerWave * W) : 1;
-    static const unsigned cap = persistent_grid(decompress_kernel<ALIGNED, STAGED, W, RANGE>, ~0ull, W * 64);
+    static const unsigned cap =
+        persistent_grid(decompress_kernel<ALIGNED, STAGED, W, RANGE, PREZERO, PRESCAN>, ~0ull, W * 64);
     const unsigned grid = (unsigned)(p.nchunks < cap ? p.nchunks : cap);
-    hipLaunchKernelGGL((decompress_kernel<ALIGNED, STAGED, W, RANGE>), dim3(grid), dim3(W * 64), 0, s, p);
+    hipLaunchKernelGGL((decompress_kernel<ALIGNED, STAGED, W, RANGE, PREZERO, PRESCAN>), dim3(grid), dim3(W * 64), 0,
+                       s, p);
     return hipGetLastError();
+}
+
+hipError_t launch_decompress_prescan(const DecompressArgs &a, unsigned long long *offsets, uint32_t *go,
+                                     bool out_aligned16, hipStream_t s)
+{
+    constexpr int W = 8;  // the decoder's waves per workgroup; a chunk is 8 tiles per wave
+    DecompressArgs p = a;
+    p.offsets = offsets;
+    p.go = go;
+    const uint64_t nchunks = a.ntiles ? ceil_div(a.ntiles, (uint64_t)kTilesPerWave * W) : 1;
+    const uint64_t g1 = a.ntiles ? ceil_div(a.ntiles, 256) : 1;
+    hipLaunchKernelGGL(dec_chunk_sizes_kernel<kTilesPerWave * W>, dim3((unsigned)g1), dim3(256), 0, s, p, offsets,
+                       nchunks);
+    hipLaunchKernelGGL(dec_offsets_kernel, dim3(1), dim3(1024), 0, s, p, offsets, nchunks, go);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return out_aligned16 ? launch_decompress_w<true, true, W, false, false, true>(p, s)
+                         : launch_decompress_w<false, true, W, false, false, true>(p, s);
+}
+
+// +0.0 into out[0, n): 16-byte nontemporal stores from the first 16-byte
+// boundary, 4-byte stores for the ragged ends.
+__global__ __launch_bounds__(256) void fill_zero_kernel(float *out, uint64_t n)
+{
+    const uint64_t head = ((16u - (reinterpret_cast<uintptr_t>(out) & 15u)) & 15u) / 4u;
+    const uint64_t h = head < n ? head : n;
+    const uint64_t nv = (n - h) / 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    f4 *v = reinterpret_cast<f4 *>(out + h);
+    for (uint64_t i = t; i < nv; i += stride) __builtin_nontemporal_store(f4{0.0f, 0.0f, 0.0f, 0.0f}, v + i);
+    if (t < h) out[t] = 0.0f;
+    const uint64_t tail = h + 4 * nv;
+    if (t < n - tail) out[tail + t] = 0.0f;
+}
+
+hipError_t launch_decompress_prezero(const DecompressArgs &a, bool out_aligned16, hipStream_t s)
+{
+    if (a.n) {
+        const uint64_t want = ceil_div(a.n, 4ull * 256);
+        const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
+        hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(256), 0, s, a.out, a.n);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return out_aligned16 ? launch_decompress_w<true, true, 8, false, true>(a, s)
+                         : launch_decompress_w<false, true, 8, false, true>(a, s);
 }
 
 template <bool ALIGNED, bool STAGED>

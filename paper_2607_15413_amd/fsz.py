@@ -43,6 +43,7 @@ EXPORTS = (
     "fsz_compress_async",
     "fsz_compress_noalloc_async",
     "fsz_decompress_async",
+    "fsz_decompress_prezero_async",
     "fsz_decompress_range_async",
     "fsz_compress_features_async",
     "fsz_compress_five_read_async",
@@ -169,6 +170,8 @@ def load_library():
     lib.fsz_decompress_config_async.restype = ctypes.c_int
     lib.fsz_decompress_async.argtypes = [vp, sz, vp, sz, vp, vp]
     lib.fsz_decompress_async.restype = ctypes.c_int
+    lib.fsz_decompress_prezero_async.argtypes = [vp, sz, vp, sz, vp, vp]
+    lib.fsz_decompress_prezero_async.restype = ctypes.c_int
     jp, tp = ctypes.POINTER(FszJob), ctypes.POINTER(FszTuning)
     lib.fsz_batch_async.argtypes = [jp, sz, tp, vp]
     lib.fsz_batch_async.restype = ctypes.c_int
@@ -242,6 +245,12 @@ def fsz_compress_async(d_in: int, n: int, mode: int, value: float, d_stats, d_ou
     """Enqueue only; the outcome lands in the device fsz_result at d_result."""
     return load_library().fsz_compress_async(d_in, n, mode, value, d_stats, d_out, out_capacity,
                                              d_result, stream)
+
+
+def fsz_decompress_prezero_async(d_cmp: int, cmp_size: int, d_out: int, n: int, d_result: int,
+                                 stream=None) -> int:
+    """Decompression into an output cleared first; all-zero tile groups are skipped (enqueue only)."""
+    return load_library().fsz_decompress_prezero_async(d_cmp, cmp_size, d_out, n, d_result, stream)
 
 
 def fsz_compress_noalloc_async(d_in: int, n: int, mode: int, value: float, d_stats, d_out: int,

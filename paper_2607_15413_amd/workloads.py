@@ -197,6 +197,18 @@ class Request:
     rel: float             # REL error bound
 
 
+def sparse_field(n: int = 1 << 27, seed: int = 5, spacing: int = 20000) -> np.ndarray:
+    """Zeros with one spike per `spacing` elements on average: n // spacing
+    positions drawn uniformly (with repetition), values U[-50, 50].  At REL
+    1e-3 most tiles are all zero, so the stream is mostly its rate header
+    (CR near the format's cap of 128; about 122 for the 512^3 size)."""
+    rng = np.random.default_rng(seed)
+    x = np.zeros(n, dtype=np.float32)
+    k = max(1, n // spacing)
+    x[rng.integers(0, n, k)] = rng.uniform(-50, 50, k).astype(np.float32)
+    return x
+
+
 def request_stream(rate_per_s: float, count: int = 10000, seed: int = 4, lo: int = 1 << 10,
                    hi: int = 1 << 26, master_n: int = 269 * 500 * 500,
                    compress_fraction: float = 0.7) -> list:
