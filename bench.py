@@ -174,33 +174,38 @@ def batched_comparison(torch, fsz, workloads, reps: int, verify_oracle: bool):
     }
 
 
-def served_benchmark(args):
+SERVED_WORKLOAD = ("Poisson requests, seed 4, 70% compress / 30% decompress, 1K-64M elements log-uniform "
+                   "from the 269x500x500 piecewise-quadratic field (seed 2), REL {1e-3,1e-4}")
+
+
+def served_run(torch, fsz, workloads, loads, counts, plain_requests=10000, budget_gb=64.0, rounds_in_flight=4,
+               jobs_per_round=256, timeline=None, verify_sample=0):
     """Served form: open-loop Poisson requests (seed 4; 70% compress / 30%
     decompress of previously compressed streams; log-uniform 1K-64M elements
     sliced from the 269x500x500 piecewise-quadratic master field; REL from
-    {1e-3, 1e-4}) against a server with a 64 GB HBM admission budget, at
-    offered loads given as fractions of the plain kernels' measured
-    closed-loop throughput on the same requests.  Reports p50/p99 latency
-    (arrival to completion seen by the host) and sustained GB/s (original
-    bytes / span from first arrival to last completion)."""
-    import torch
+    {1e-3, 1e-4}) against a server with an HBM admission budget, at offered
+    loads given as fractions of the plain kernels' measured closed-loop
+    throughput on the same requests.  Per load: p50/p99 latency (arrival to
+    completion seen by the host) and sustained GB/s (original bytes / span
+    from first arrival to last completion).
 
-    from paper_2607_15413_amd import fsz, workloads
-
+    verify_sample > 0: a seeded sample of that many compress requests (every
+    one of at least 2^24 elements among the first requests included) and a
+    third as many decompress requests is served once more, at offered load
+    0.9, by a server that keeps its outputs; each output is compared on the
+    device with the plain path's output for the same request, byte for byte
+    (streams) and bit for bit (floats)."""
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     sh = stream.cuda_stream
-    loads = [float(v) for v in args.served_loads.split(",")]
-    counts = [int(v) for v in args.served_requests.split(",")]
-    if len(counts) == 1:
-        counts = counts * len(loads)
     nmax = max(counts)
     t0 = time.time()
     shape = (269, 500, 500)
     master_np = workloads.piecewise_quadratic(shape, 2)
     master = torch.from_numpy(master_np).to(dev)
     reqs = workloads.request_stream(1.0, nmax, 4, master_n=master_np.size)
+    del master_np
     print(f"[served] master {shape} + {nmax} requests generated in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
 
@@ -208,19 +213,22 @@ def served_benchmark(args):
         if st != fsz.FSZ_OK:
             raise RuntimeError(f"{what}: {fsz.fsz_status_string(st)}")
 
-    # streams that decompress requests read: compressed once by the plain path
+    # streams that decompress requests read: compressed once by the plain
+    # path, then kept in buffers of their exact size
     res = torch.zeros((nmax, 4), dtype=torch.int32, device=dev)
     streams = {}
+    ssize = {}
+    tmp = torch.empty(fsz.fsz_compressed_bound(max(r.n for r in reqs)), dtype=torch.uint8, device=dev)
     for k, r in enumerate(reqs):
         if r.op == "decompress":
-            cap = fsz.fsz_compressed_bound(r.n)
-            buf = torch.empty(cap, dtype=torch.uint8, device=dev)
             check(fsz.fsz_compress_async(master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel, None,
-                                         buf.data_ptr(), cap, res[k].data_ptr(), sh), "precompress")
-            streams[k] = buf
+                                         tmp.data_ptr(), tmp.numel(), res[k].data_ptr(), sh), "precompress")
+            size, st, _ = fsz.read_result(res[k])
+            check(st, "precompress")
+            streams[k] = tmp[:size].clone()
+            ssize[k] = int(size)
+    del tmp
     torch.cuda.synchronize()
-    rr = res.cpu().numpy().astype(np.uint32)
-    ssize = {k: int(rr[k, 0]) | (int(rr[k, 1]) << 32) for k in streams}
     print(f"[served] {len(streams)} decompress inputs ready", file=sys.stderr, flush=True)
 
     # plain closed loop over the same requests: every request one plain call,
@@ -230,18 +238,20 @@ def served_benchmark(args):
     out_c = torch.empty(fsz.fsz_compressed_bound(nmax_n), dtype=torch.uint8, device=dev)
     out_d = torch.empty(nmax_n, dtype=torch.float32, device=dev)
 
+    def plain_call(k, dst):
+        r = reqs[k]
+        if r.op == "compress":
+            check(fsz.fsz_compress_async(master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel, None,
+                                         dst.data_ptr(), dst.numel(), res[k].data_ptr(), sh), "plain compress")
+        else:
+            check(fsz.fsz_decompress_async(streams[k].data_ptr(), ssize[k], dst.data_ptr(), r.n,
+                                           res[k].data_ptr(), sh), "plain decompress")
+
     def plain_pass(n_req):
         for k in range(n_req):
-            r = reqs[k]
-            if r.op == "compress":
-                check(fsz.fsz_compress_async(master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel, None,
-                                             out_c.data_ptr(), out_c.numel(), res[k].data_ptr(), sh),
-                      "plain compress")
-            else:
-                check(fsz.fsz_decompress_async(streams[k].data_ptr(), ssize[k], out_d.data_ptr(), r.n,
-                                               res[k].data_ptr(), sh), "plain decompress")
+            plain_call(k, out_c if reqs[k].op == "compress" else out_d)
 
-    n_plain = min(nmax, args.served_plain_requests)
+    n_plain = min(nmax, plain_requests)
     plain_pass(n_plain)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
@@ -260,13 +270,7 @@ def served_benchmark(args):
     torch.cuda.empty_cache()
     print(f"[served] plain closed loop: {n_plain} requests, {plain_gbps:.1f} GB/s", file=sys.stderr, flush=True)
 
-    budget = int(args.served_budget_gb * 1e9)
-    results = []
-    # one long-running server for every load point, warmed up by one short pass
-    st, server = fsz.fsz_server_create(budget, args.served_jobs_per_round, args.served_rounds, True, (4, 0))
-    check(st, "server create")
-
-    # request table built once; arrival times are stamped just before each submission
+    budget = int(budget_gb * 1e9)
     table = fsz.request_table(nmax)
     for k, r in enumerate(reqs):
         if r.op == "compress":
@@ -275,11 +279,14 @@ def served_benchmark(args):
             table[k] = (fsz.FSZ_OP_DECOMPRESS, streams[k].data_ptr(), ssize[k], r.n, 0, 0.0, k, 0)
     arrival_s = np.array([r.arrival_s for r in reqs])
 
-    def serve(count, rate):
-        sub = table[:count]
+    def serve(server, sub, rate, keep=None):
+        """Submit the request table rows `sub` with arrivals scaled to `rate`
+        requests per second; collect every completion.  keep(c): called for
+        completions whose output the server holds (then released)."""
+        count = len(sub)
         before = fsz.fsz_server_get_stats(server)
         start = fsz.fsz_server_now_ns() + 5_000_000
-        sub["arrival_ns"] = start + (arrival_s[:count] / rate * 1e9).astype(np.uint64)
+        sub["arrival_ns"] = start + ((arrival_s[:count] - arrival_s[0]) / rate * 1e9).astype(np.uint64)
         check(fsz.fsz_server_submit_table(server, sub), "submit")
         lead_ms = (start - fsz.fsz_server_now_ns()) / 1e6  # > 0: submitted before the first arrival
         done = {}
@@ -287,6 +294,9 @@ def served_benchmark(args):
         while len(done) < count:
             for c in fsz.fsz_server_poll(server, 4096, 200):
                 done[c.tag] = (c.status, c.arrival_ns, c.admit_ns, c.launch_ns, c.complete_ns, c.size)
+                if c.d_out:
+                    keep(c)
+                    check(fsz.fsz_server_release(server, c.d_out), "release")
             if time.time() - last_print > 5:
                 print(f"[served] {len(done)}/{count} done", file=sys.stderr, flush=True)
                 last_print = time.time()
@@ -294,20 +304,25 @@ def served_benchmark(args):
         return done, int(after.rounds - before.rounds), after, lead_ms
 
     import gc
+    results = []
+    runs = []
     gc.disable()  # no collector pauses in the client while requests are in flight
+    # one long-running server for every load point, warmed up by one short pass
+    st, server = fsz.fsz_server_create(budget, jobs_per_round, rounds_in_flight, True, (4, 0))
+    check(st, "server create")
     try:
         n_warm = min(200, nmax)
-        serve(n_warm, 0.5 * plain_gbps * 1e9 / float(np.mean([4 * reqs[k].n for k in range(n_warm)])))
-        runs = []
+        serve(server, table[:n_warm].copy(),
+              0.5 * plain_gbps * 1e9 / float(np.mean([4 * reqs[k].n for k in range(n_warm)])))
         for load, count in zip(loads, counts):
             mean_bytes = float(np.mean([4 * reqs[k].n for k in range(count)]))
             rate = load * plain_gbps * 1e9 / mean_bytes  # requests per second
-            runs.append((load, count, rate) + serve(count, rate))
+            runs.append((load, count, rate) + serve(server, table[:count].copy(), rate))
     finally:
         fsz.fsz_server_destroy(server)
         gc.enable()
-    if args.served_timeline:
-        np.savez(args.served_timeline, **{
+    if timeline:
+        np.savez(timeline, **{
             f"load_{load}": np.array([[done[k][1], done[k][2], done[k][3], done[k][4], reqs[k].n,
                                        int(reqs[k].op == "compress")] for k in range(count)], dtype=np.int64)
             for load, count, rate, done, rounds, stats, lead in runs})
@@ -315,9 +330,14 @@ def served_benchmark(args):
         bad = [k for k, v in done.items() if v[0] != fsz.FSZ_OK]
         if bad:
             raise RuntimeError(f"served requests failed: {bad[:5]}")
+        sizes_ok = True
         for k, v in done.items():  # stream sizes equal the plain path's
-            if reqs[k].op == "decompress" and v[5] != ssize[k]:
-                raise RuntimeError(f"request {k}: size {v[5]} != {ssize[k]}")
+            if reqs[k].op == "decompress":
+                sizes_ok = sizes_ok and v[5] == ssize[k]
+            elif v[5] != int(rr[k, 0]) | (int(rr[k, 1]) << 32) and k < n_plain:
+                sizes_ok = False
+        if not sizes_ok:
+            raise RuntimeError("a served size differs from the plain path's")
         lat = np.array([(v[4] - v[1]) / 1e6 for v in done.values()])
         queue = np.array([(v[3] - v[1]) / 1e6 for v in done.values()])
         t_first = min(v[1] for v in done.values())
@@ -336,8 +356,10 @@ def served_benchmark(args):
             "p99_ms": round(float(np.percentile(lat, 99)), 4),
             "mean_ms": round(float(lat.mean()), 4),
             "p50_wait_to_launch_ms": round(float(np.percentile(queue, 50)), 4),
+            "p99_wait_to_launch_ms": round(float(np.percentile(queue, 99)), 4),
             "rounds": rounds,
             "mean_jobs_per_round": round(count / max(rounds, 1), 2),
+            "max_rounds_overlapping": int(stats.max_rounds_overlapping),
             "submit_lead_ms": round(lead, 3),
             "max_completion_gap_ms": round(float(gaps[gap_at]) / 1e6, 3) if gaps.size else 0.0,
             "max_gap_at_ms": round(float(comp[gap_at] - t_first) / 1e6, 3) if gaps.size else 0.0,
@@ -345,6 +367,115 @@ def served_benchmark(args):
         results.append(entry)
         print(f"[served] {json.dumps(entry)}", file=sys.stderr, flush=True)
 
+    verify = None
+    if verify_sample > 0:
+        verify = served_verify(torch, fsz, reqs, table, streams, ssize, master, serve, check, plain_gbps,
+                               budget, jobs_per_round, rounds_in_flight, verify_sample, res)
+        print(f"[served] verify {json.dumps(verify)}", file=sys.stderr, flush=True)
+    del streams, master
+    torch.cuda.empty_cache()
+    return {
+        "workload": SERVED_WORKLOAD,
+        "hbm_budget_GB": budget_gb,
+        "rounds_in_flight": rounds_in_flight,
+        "max_jobs_per_round": jobs_per_round,
+        "plain_closed_loop_GBps": round(plain_gbps, 1),
+        "plain_closed_loop_requests": n_plain,
+        "server_hbm_peak_GB": round(runs[-1][5].hbm_peak / 1e9, 3) if runs else None,
+        "per_load": results,
+        "verify": verify,
+    }
+
+
+def served_verify(torch, fsz, reqs, table, streams, ssize, master, serve, check, plain_gbps, budget,
+                  jobs_per_round, rounds_in_flight, sample, res):
+    """Serve a seeded sample of requests on a server that keeps outputs, and
+    compare each output with the plain path's for the same request."""
+    dev = master.device
+    sh = torch.cuda.current_stream(dev).cuda_stream
+    rng = np.random.default_rng(40)
+    comp = [k for k, r in enumerate(reqs) if r.op == "compress"]
+    deco = [k for k, r in enumerate(reqs) if r.op == "decompress"]
+    large = [k for k in comp if reqs[k].n >= 1 << 24][:max(8, sample // 20)]
+    rest = [k for k in comp if k not in set(large)]
+    pick_c = large + [int(k) for k in rng.choice(rest, size=max(0, sample - len(large)), replace=False)]
+    pick_d = [int(k) for k in rng.choice(deco, size=max(1, sample // 3), replace=False)]
+    tags = sorted(pick_c + pick_d)
+    sub = table[tags].copy()
+    # arrivals: Poisson at offered load 0.9 of the plain closed loop
+    mean_bytes = float(np.mean([4 * reqs[k].n for k in tags]))
+    rate = 0.9 * plain_gbps * 1e9 / mean_bytes
+    mismatched = []
+    checked = {"compress": 0, "decompress": 0}
+
+    def keep(c):
+        k = int(c.tag)
+        r = reqs[k]
+        if r.op == "compress":
+            ref = torch.empty(fsz.fsz_compressed_bound(r.n), dtype=torch.uint8, device=dev)
+            check(fsz.fsz_compress_async(master.data_ptr() + 4 * r.offset, r.n, fsz.FSZ_REL, r.rel, None,
+                                         ref.data_ptr(), ref.numel(), res[k].data_ptr(), sh), "reference compress")
+            size, st, _ = fsz.read_result(res[k])
+            check(st, "reference compress")
+            got = fsz.device_view(c.d_out, c.size, torch.uint8)
+            same = int(size) == int(c.size) and torch.equal(got, ref[:size])
+        else:
+            ref = torch.empty(r.n, dtype=torch.float32, device=dev)
+            check(fsz.fsz_decompress_async(streams[k].data_ptr(), ssize[k], ref.data_ptr(), r.n,
+                                           res[k].data_ptr(), sh), "reference decompress")
+            got = fsz.device_view(c.d_out, 4 * r.n, torch.float32)
+            same = torch.equal(got.view(torch.int32), ref.view(torch.int32))
+        torch.cuda.synchronize()
+        checked[r.op] += 1
+        if not same:
+            mismatched.append(k)
+
+    st, server = fsz.fsz_server_create(budget, jobs_per_round, rounds_in_flight, False, (4, 0))
+    check(st, "server create")
+    try:
+        gaps = rng.exponential(1.0 / rate, len(tags))
+        gaps[0] = 0.0
+        done = {}
+        start = fsz.fsz_server_now_ns() + 5_000_000
+        sub["arrival_ns"] = start + (np.cumsum(gaps) * 1e9).astype(np.uint64)
+        check(fsz.fsz_server_submit_table(server, sub), "submit")
+        while len(done) < len(tags):
+            for c in fsz.fsz_server_poll(server, 4096, 200):
+                if c.status != fsz.FSZ_OK:
+                    raise RuntimeError(f"served request {c.tag} failed")
+                done[c.tag] = c.size
+                keep(c)
+                check(fsz.fsz_server_release(server, c.d_out), "release")
+        stats = fsz.fsz_server_get_stats(server)
+    finally:
+        fsz.fsz_server_destroy(server)
+    return {
+        "sample_compress": len(pick_c),
+        "sample_decompress": len(pick_d),
+        "compress_at_least_2^24": len(large),
+        "largest_n": int(max(reqs[k].n for k in tags)),
+        "checked": checked,
+        "mismatched": mismatched[:10],
+        "identical": not mismatched and sum(checked.values()) == len(tags),
+        "mean_jobs_per_round": round(len(tags) / max(int(stats.rounds), 1), 2),
+        "max_rounds_overlapping": int(stats.max_rounds_overlapping),
+    }
+
+
+def served_benchmark(args):
+    """The served form alone (`--served`): every load point of --served-loads."""
+    import torch
+
+    from paper_2607_15413_amd import fsz, workloads
+
+    loads = [float(v) for v in args.served_loads.split(",")]
+    counts = [int(v) for v in args.served_requests.split(",")]
+    if len(counts) == 1:
+        counts = counts * len(loads)
+    served = served_run(torch, fsz, workloads, loads, counts, args.served_plain_requests, args.served_budget_gb,
+                        args.served_rounds, args.served_jobs_per_round, args.served_timeline,
+                        verify_sample=args.served_verify)
+    results = served["per_load"]
     top = max((e for e in results if e["offered_load"] <= 0.9), key=lambda e: e["offered_load"],
               default=results[-1])
     line = {
@@ -361,17 +492,11 @@ def served_benchmark(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "Poisson requests, seed 4, 70% compress / 30% decompress, 1K-64M elements log-uniform "
-                        "from the 269x500x500 piecewise-quadratic field (seed 2), REL {1e-3,1e-4}; "
-                        f"HBM budget {args.served_budget_gb} GB, {args.served_rounds} rounds in flight, "
-                        f"up to {args.served_jobs_per_round} jobs per round",
+            "workload": SERVED_WORKLOAD + f"; HBM budget {args.served_budget_gb} GB, {args.served_rounds} rounds "
+                        f"in flight, up to {args.served_jobs_per_round} jobs per round",
             "requests_per_load": counts,
         },
-        "server_max_rounds_overlapping": int(runs[-1][5].max_rounds_overlapping),
-        "server_hbm_peak_GB": round(runs[-1][5].hbm_peak / 1e9, 3),
-        "plain_closed_loop_GBps": round(plain_gbps, 1),
-        "plain_closed_loop_requests": n_plain,
-        "per_load": results,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
 
@@ -593,13 +718,14 @@ def tile_sweep(torch, fsz, workloads, x, stats, outs, sizes, reps: int = 5):
 def small_configs(torch, fsz, workloads, verify: bool, reps: int = 20):
     """The 2^20 sinusoid field (REL 1e-3; warm and MALL-flushed) and the
     100x500x500 piecewise-quadratic field (REL 1e-2/1e-3/1e-4; flushed: a
-    512 MB scratch buffer is rewritten before every timed call, since both
-    fields fit in the 256 MB MALL).  Median of `reps` calls per row, HIP
-    events around each asynchronous call (range pass precomputed)."""
+    1 GiB buffer is read before every timed call, so the MALL holds clean
+    lines of it and nothing of the field, since both fields fit in the
+    256 MB MALL).  Median of `reps` calls per row, HIP events around each
+    asynchronous call (range pass precomputed)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     sh = stream.cuda_stream
-    scratch = torch.empty(128 << 20, dtype=torch.float32, device=dev)  # 512 MiB
+    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB, read (not written) to flush
     rows = []
     cases = [("sinusoid 2^20, seed 0", workloads.sinusoid_field(1 << 20, 0), [1e-3], [False, True]),
              ("piecewise quadratic 100x500x500, seed 2", workloads.piecewise_quadratic((100, 500, 500), 2),
@@ -620,7 +746,7 @@ def small_configs(torch, fsz, workloads, verify: bool, reps: int = 20):
                     ts = []
                     for it in range(reps + 3):
                         if flushed:
-                            scratch.fill_(float(it))
+                            flush.sum()
                         a = torch.cuda.Event(enable_timing=True)
                         b = torch.cuda.Event(enable_timing=True)
                         a.record(stream)
@@ -656,7 +782,84 @@ def small_configs(torch, fsz, workloads, verify: bool, reps: int = 20):
                     "max_err_over_eb": round(err, 6), "oracle_identical": identical,
                 })
         del x, out, y
+    del flush
     return rows
+
+
+def prezero_rows(torch, fsz, workloads, x, outs, sizes, reps: int = 10):
+    """Pre-zeroed decompression (Sec. III-A) against the plain decoder: on a
+    512^3 sparse field (one U[-50,50] spike per 20000 zeros, REL 1e-3, CR
+    near the format's cap) and on the timed field's REL 1e-2 stream.  Each
+    decode is timed alone after a 1 GiB read refilled the MALL; the outputs
+    must agree bit for bit."""
+    dev = x.device
+    stream = torch.cuda.current_stream(dev)
+    sh = stream.cuda_stream
+    n = x.numel()
+    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    res = torch.zeros(4, dtype=torch.int32, device=dev)
+    sp = torch.from_numpy(workloads.sparse_field(n, 5)).to(dev)
+    cap = fsz.fsz_compressed_bound(n)
+    sbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    st = fsz.fsz_compress_async(sp.data_ptr(), n, fsz.FSZ_REL, 1e-3, None, sbuf.data_ptr(), cap, res.data_ptr(), sh)
+    if st != fsz.FSZ_OK:
+        raise RuntimeError("sparse compress failed")
+    ssize, st, _ = fsz.read_result(res)
+    del sp
+    ya = torch.empty(n, dtype=torch.float32, device=dev)
+    yb = torch.empty(n, dtype=torch.float32, device=dev)
+    rows = []
+    for name, buf, size in (("sparse 512^3, 1 spike per 20000, REL 1e-3", sbuf, int(ssize)),
+                            ("grf k^-3 512^3, REL 1e-2", outs[0], sizes[0])):
+        times = {}
+        for label, entry, dst in (("plain", fsz.fsz_decompress_async, ya),
+                                  ("prezero", fsz.fsz_decompress_prezero_async, yb)):
+            t = []
+            for _ in range(reps):
+                flush.sum()
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                e[0].record(stream)
+                st = entry(buf.data_ptr(), size, dst.data_ptr(), n, res.data_ptr(), sh)
+                e[1].record(stream)
+                torch.cuda.synchronize()
+                if st != fsz.FSZ_OK or fsz.read_result(res)[1] != fsz.FSZ_OK:
+                    raise RuntimeError(f"{label} decode failed")
+                t.append(e[0].elapsed_time(e[1]))
+            times[label] = float(np.median(t))
+        alg = 4 * n + size
+        rows.append({
+            "field": name, "cr": round(4 * n / size, 2),
+            "plain_ms": round(times["plain"], 4), "prezero_ms": round(times["prezero"], 4),
+            "plain_hbm_frac": round(alg / times["plain"] / 1e6 / HBM_PEAK_GBPS, 4),
+            "prezero_hbm_frac": round(alg / times["prezero"] / 1e6 / HBM_PEAK_GBPS, 4),
+            "identical": bool(torch.equal(ya.view(torch.int32), yb.view(torch.int32))),
+        })
+    del flush, sbuf, ya, yb
+    torch.cuda.empty_cache()
+    return rows
+
+
+def host_threads() -> int:
+    """Host threads for the oracle's parallel mode: the CPUs this process may
+    run on, at most 16 (one GPU's share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def host_description() -> str:
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs visible, {host_threads()} used"
 
 
 def parse_args():
@@ -685,6 +888,10 @@ def parse_args():
     ap.add_argument("--served-jobs-per-round", type=int, default=256)
     ap.add_argument("--served-timeline", type=str, default=None,
                     help="write per-request times (arrival, admit, launch, complete; ns) per load to this .npz")
+    ap.add_argument("--served-verify", type=int, default=200,
+                    help="compress requests of the served byte comparison against the plain path (0: none)")
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served section of the default line (offered loads 0.1 / 0.5 / 0.9)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain device copy of the input (n floats) so that "
                          "profiler counters can be calibrated against a kernel of known traffic")
@@ -868,31 +1075,54 @@ def main():
     if not args.no_cpu_baseline or not args.no_verify:
         import oracle
 
-        t_c = t_d = 0.0
-        identical = True
-        for k, rel in enumerate(RELS):
-            t = time.perf_counter()
-            ref = oracle.compress(x_np, oracle.REL, rel)
-            t_c += time.perf_counter() - t
-            t = time.perf_counter()
-            oracle.decompress(ref, n)
-            t_d += time.perf_counter() - t
-            if not args.no_verify:
-                got = outs[k][:sizes[k]].cpu().numpy().tobytes()
-                identical = identical and got == ref
+        threads = host_threads()
+
+        def oracle_pass(nthreads, x_part):
+            """One compress + one decompress of x_part per bound on nthreads host
+            threads; returns (compress s, decompress s, streams)."""
+            old = oracle.set_threads(nthreads)
+            try:
+                t_c = t_d = 0.0
+                refs = []
+                for rel in RELS:
+                    t = time.perf_counter()
+                    ref = oracle.compress(x_part, oracle.REL, rel)
+                    t_c += time.perf_counter() - t
+                    t = time.perf_counter()
+                    oracle.decompress(ref, x_part.size)
+                    t_d += time.perf_counter() - t
+                    refs.append(ref)
+                return t_c, t_d, refs
+            finally:
+                oracle.set_threads(old)
+
+        # the whole field on every host thread: the parallel CPU baseline, and
+        # the streams the GPU's are compared with (bytes do not depend on threads)
+        t_c, t_d, refs = oracle_pass(threads, x_np)
         if not args.no_verify:
-            verified = identical
+            verified = all(outs[k][:sizes[k]].cpu().numpy().tobytes() == refs[k] for k in range(len(RELS)))
+        del refs
         if not args.no_cpu_baseline:
+            # single thread on a bounded sample: the first 2^25 elements (a quarter of the field)
+            part = x_np[:min(n, 1 << 25)]
+            s_c, s_d, _ = oracle_pass(1, part)
             cpu = {
                 "value": round(2 * len(RELS) * 4 * n / (t_c + t_d) / 1e9, 4),
                 "unit": "GB/s",
-                "cores": 1,
+                "cores": threads,
                 "kind": "oracle",
-                "sample": f"full {shape} field, REL 1e-2/1e-3/1e-4, one compress + one decompress "
-                          f"each ({t_c:.1f}s + {t_d:.1f}s, single-threaded)",
+                "sample": f"full {shape} field, REL 1e-2/1e-3/1e-4, one compress + one decompress each "
+                          f"on {threads} host threads (tile loops in parallel, offset scan serial; "
+                          f"{t_c:.1f}s + {t_d:.1f}s); single thread on its first {part.size} elements",
                 "compress_GBps": round(len(RELS) * 4 * n / t_c / 1e9, 4),
                 "decompress_GBps": round(len(RELS) * 4 * n / t_d / 1e9, 4),
+                "single_thread_GBps": round(2 * len(RELS) * 4 * part.size / (s_c + s_d) / 1e9, 4),
+                "single_thread_compress_GBps": round(len(RELS) * 4 * part.size / s_c / 1e9, 4),
+                "single_thread_decompress_GBps": round(len(RELS) * 4 * part.size / s_d / 1e9, 4),
+                "host": host_description(),
             }
+
+    pre_zero = prezero_rows(torch, fsz, workloads, x, outs, sizes)
 
     ablation = five_read = ranges = sweep = None
     if not args.no_ablation:
@@ -907,6 +1137,14 @@ def main():
         del outs, y  # room for the 64-field workload
         torch.cuda.empty_cache()
         batched = batched_comparison(torch, fsz, workloads, args.batched_reps, not args.no_verify)
+    served = None
+    if not args.no_served:
+        # the served workload (10,000 Poisson requests per load) at three offered loads
+        x = outs = y = None
+        torch.cuda.empty_cache()
+        served = served_run(torch, fsz, workloads, [0.1, 0.5, 0.9], [10000] * 3, 10000, args.served_budget_gb,
+                            args.served_rounds, args.served_jobs_per_round,
+                            verify_sample=0 if args.no_verify else args.served_verify)
 
     line = {
         "metric": "compress/decompress GB/s on 1 MI355X (% of HBM peak) + compression ratio",
@@ -939,10 +1177,12 @@ def main():
         "oracle_identical": verified,
         "ablation": ablation,
         "five_read": five_read,
+        "pre_zero": pre_zero,
         "random_access": ranges,
         "tile_sweep": sweep,
         "batched": batched,
         "other_configs": others,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
 

@@ -191,3 +191,41 @@ def test_served_open_loop_poisson():
         assert np.percentile(lat, 50) > 0
     finally:
         fsz.fsz_server_destroy(server)
+
+
+def test_served_large_requests_match_oracle():
+    """Requests of the served workload's upper sizes (log-uniform up to 2^24
+    elements, plus four of 2^24 - k), several rounds in flight under a budget
+    that forces admission to wait: every stream equals the oracle's byte for
+    byte and every reconstruction bit for bit, in the mix and alone."""
+    from paper_2607_15413_amd.workloads import Request
+
+    old = oracle.set_threads(8)
+    try:
+        w = Workload(36, 11, hi=1 << 24, shape=(70, 500, 500))
+        big = [Request(0.0, op, off, (1 << 24) - k, rel)
+               for k, (op, off, rel) in enumerate((("compress", 12345, 1e-3), ("compress", 700_001, 1e-4),
+                                                   ("decompress", 77, 1e-3), ("compress", 0, 1e-4)))]
+        # every request lies inside the master field (no device read past its end)
+        assert all(r.offset + r.n <= w.master_np.size for r in w.reqs + big)
+        for r in big:
+            w.reqs.append(r)
+            if r.op == "decompress":
+                data = oracle.compress(w.slice(r), oracle.REL, r.rel)
+                buf = torch.from_numpy(np.frombuffer(data, dtype=np.uint8).copy()).to(_dev())
+                w.streams[len(w.reqs) - 1] = (data, buf)
+        tags = list(range(len(w.reqs)))
+        assert sum(w.reqs[k].n >= 1 << 22 for k in tags) >= 6
+        budget = 3 * fsz.fsz_compressed_bound(1 << 24)  # at most a few large outputs reserved at once
+        announce(f"served large mix: {len(tags)} requests up to 2^24 elements, budget {budget} B")
+        mixed, stats = run_server(w, tags, budget, 6, 3)
+        assert stats.completed == len(tags) and stats.hbm_peak <= budget
+        announce("served large requests alone")
+        alone, _ = run_server(w, tags, budget, 1, 1)
+        for k in tags:
+            exp = w.expected(k)
+            r = w.reqs[k]
+            assert same(mixed[k], exp), f"request {k} ({r.op}, n={r.n}) differs from the oracle in the mix"
+            assert same(alone[k], exp), f"request {k} ({r.op}, n={r.n}) differs from the oracle alone"
+    finally:
+        oracle.set_threads(old)
