@@ -38,6 +38,8 @@ const Tuning &tuning()
         }
         if (const char *e = std::getenv("FSZ_PREZERO_CR")) v.prezero_min_cr = std::atof(e);
         if (const char *e = std::getenv("FSZ_DEC_PRESCAN")) v.dec_prescan = std::atoi(e) != 0;
+        if (const char *e = std::getenv("FSZ_DEC_LOOKBACK_BELOW")) v.dec_lookback_below = std::strtoull(e, nullptr, 10);
+        if (const char *e = std::getenv("FSZ_DEC_DIRECT_BELOW")) v.dec_direct_below = std::strtoull(e, nullptr, 10);
         if (const char *e = std::getenv("FSZ_GRID_FACTOR")) {
             const int f = std::atoi(e);
             if (f >= 1 && f <= 64) v.grid_factor = f;
@@ -305,11 +307,12 @@ fsz_status enqueue_decompress(Workspace *ws, const void *d_cmp, uint64_t cmp_siz
     hipError_t e;
     if (prezero) {
         e = launch_decompress_prezero(a, aligned(d_out, 16), ws->stream);
-    } else if (tuning().dec_prescan && tuning().staged_decompress) {
-        // chunk offsets from the rate header first (chunks of 64 tiles)
-        if (!grow(&ws->d_offs, &ws->offs_cap, std::max<uint64_t>(ceil_div(a.ntiles, 64), 1), ws->stream))
+    } else if (tuning().dec_prescan && tuning().staged_decompress && n >= tuning().dec_lookback_below) {
+        // chunk offsets from the rate header first (chunks of 32 or 64 tiles)
+        if (!grow(&ws->d_offs, &ws->offs_cap, std::max<uint64_t>(ceil_div(a.ntiles, 32), 1), ws->stream))
             return FSZ_ERR_DEVICE;
-        e = launch_decompress_prescan(a, ws->d_offs, ws->d_go, aligned(d_out, 16), ws->stream);
+        e = launch_decompress_prescan(a, ws->d_offs, ws->d_go, aligned(d_out, 16), n < tuning().dec_direct_below,
+                                      ws->stream);
     } else {
         e = launch_decompress(a, aligned(d_out, 16), tuning().staged_decompress, ws->stream);
     }

@@ -160,9 +160,10 @@ hipError_t launch_compress_naive(const CompressArgs &a, const NaiveTables &t, bo
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s);
 // Whole-field decompression with the chunk offsets computed first from the
 // rate header (no lookback in the decoder): offsets has room for one word per
-// chunk of kTilesPerWave * 8 tiles, go for one status word.
+// chunk of 32 tiles, go for one status word.  direct: one chunk of 32 tiles
+// per workgroup instead of the persistent grid over chunks of 64 tiles.
 hipError_t launch_decompress_prescan(const DecompressArgs &a, unsigned long long *offsets, uint32_t *go,
-                                     bool out_aligned16, hipStream_t s);
+                                     bool out_aligned16, bool direct, hipStream_t s);
 // Pre-zeroed decompression (Sec. III-A): a fill of out[0, n) with +0.0, then
 // the decoder that skips waves whose tiles are all zero.
 hipError_t launch_decompress_prezero(const DecompressArgs &a, bool out_aligned16, hipStream_t s);
@@ -232,6 +233,8 @@ struct Tuning {
     int grid_factor = 1;
     double prezero_min_cr = 0.0;  // whole-field decodes pre-zero above this CR (0: never)
     bool dec_prescan = true;      // whole-field decodes take chunk offsets from a pre-pass (no lookback)
+    uint64_t dec_lookback_below = 1ull << 22;  // ... except fields below this many elements (one launch)
+    uint64_t dec_direct_below = 1ull << 26;    // pre-pass decodes below this size: one chunk per workgroup
 };
 const Tuning &tuning();
 

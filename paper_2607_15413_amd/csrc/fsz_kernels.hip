@@ -1843,14 +1843,18 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
         return;
     }
 
+    // Chunks come from the ticket counter, in increasing order over the
+    // running workgroups, so that lookbacks only wait on running chunks.  With
+    // offsets from the pre-pass no workgroup waits on another, and a static
+    // schedule (chunk = workgroup + k * grid) saves the ticket's round trip.
     int tslot = 0;
     const uint64_t takes = a.nchunks + gridDim.x;
-    uint64_t cur = next_ticket(a.ticket, takes, sh, tslot);
+    uint64_t cur = PRESCAN ? (uint64_t)blockIdx.x : next_ticket(a.ticket, takes, sh, tslot);
     if (cur >= a.nchunks) return;
     int slot = 0;
     DecChunk dc = dec_sizes<W, RANGE, PRESCAN>(a, cur, dec_rate_byte<W, RANGE>(a, cur), slot, sh);
     for (;;) {
-        const uint64_t nxt = next_ticket(a.ticket, takes, sh, tslot);
+        const uint64_t nxt = PRESCAN ? cur + gridDim.x : next_ticket(a.ticket, takes, sh, tslot);
         DecChunk dn;
         if (nxt < a.nchunks)
             dn = dec_sizes<W, RANGE, PRESCAN>(a, nxt, dec_rate_byte<W, RANGE>(a, nxt), slot ^ 1, sh);
@@ -1858,6 +1862,7 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
         if (pl.live) dec_decode<ALIGNED, STAGED, W, RANGE>(a, dc, pl, E, indep, st);
         if (nxt >= a.nchunks) break;
         dc = dn;
+        cur = nxt;
         slot ^= 1;
     }
 }
@@ -1947,6 +1952,10 @@ __global__ __launch_bounds__(1024) void dec_offsets_kernel(DecompressArgs a, uns
     }
     const int tid = threadIdx.x;
     if (tid == 0) any_bad = 0;
+    __syncthreads();
+    // the rate header's zero padding: at most 15 bytes, one lane each
+    if (tid < 16 && kHeaderBytes + a.nblocks + tid < a.data0 && a.cmp[kHeaderBytes + a.nblocks + tid] != 0)
+        any_bad = 1;
     const uint64_t per = (nchunks + 1023) / 1024;
     const uint64_t lo = (uint64_t)tid * per < nchunks ? (uint64_t)tid * per : nchunks;
     const uint64_t hi = lo + per < nchunks ? lo + per : nchunks;
@@ -1958,7 +1967,6 @@ __global__ __launch_bounds__(1024) void dec_offsets_kernel(DecompressArgs a, uns
         bad = bad || (v & kBad) != 0;
         sum += v & ~kBad;
     }
-    __syncthreads();
     if (bad) any_bad = 1;
     const unsigned long long incl = wave_incl_scan_u64(sum);
     if ((tid & 63) == 63) wsum[tid >> 6] = incl;
@@ -1971,12 +1979,32 @@ __global__ __launch_bounds__(1024) void dec_offsets_kernel(DecompressArgs a, uns
         excl += v;
     }
     if (tid == 1023) {  // excl now holds the sum of every chunk
-        bool ok = any_bad == 0 && a.data0 + excl == total;
-        for (uint64_t k = kHeaderBytes + a.nblocks; ok && k < a.data0; k++) ok = a.cmp[k] == 0;
+        const bool ok = any_bad == 0 && a.data0 + excl == total;
         const uint32_t st = ok ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT;
         *go = st;
         write_final(a.final, total, st, a.epoch);
     }
+}
+
+// Whole-field decoder for the offsets pre-pass, one chunk of 8*W tiles per
+// workgroup and no ticket: with every chunk's offset known there is no order
+// to keep, and the hardware dispatcher keeps the CUs busy.  Used for fields
+// too small to give a persistent grid several chunks per workgroup.
+template <bool ALIGNED, int W>
+__global__ __launch_bounds__(W * 64) void decompress_direct_kernel(DecompressArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t stage[W * kStageWaveDwords];
+    __shared__ DecompressShared<W> sh;
+    if (*a.go != FSZ_OK) return;  // the pre-pass checked the stream and reported its outcome
+    float E;
+    uint64_t total;
+    bool indep;
+    dec_header(a, E, total, indep);
+    const uint64_t chunk = blockIdx.x;
+    uint32_t *st = stage + (threadIdx.x >> 6) * kStageWaveDwords;
+    const DecChunk dc = dec_sizes<W, false, true>(a, chunk, dec_rate_byte<W>(a, chunk), 0, sh);
+    const DecPlace pl = dec_place<W, false, false, true>(a, dc, 0, total, sh);
+    if (pl.live) dec_decode<ALIGNED, true, W>(a, dc, pl, E, indep, st);
 }
 
 // ------------------------------------------------------------------ random-access decode
@@ -2062,26 +2090,32 @@ __global__ __launch_bounds__(kStatsThreads) void batch_stats_kernel(BatchArgs b)
     for (uint64_t i = (uint64_t)blockIdx.x * kStatsThreads + threadIdx.x; i < b.nflags;
          i += (uint64_t)gridDim.x * kStatsThreads)
         b.flags[i] = 0;
-    const uint64_t seg = blockIdx.x;
-    if (seg >= b.total_segs) return;
-    const uint32_t job = __builtin_amdgcn_readfirstlane(find_job(b.seg_end, b.njobs, seg));
-    if (job >= b.njobs) return;
-    const BatchJob &J = b.jobs[job];
-    const float *x = static_cast<const float *>(J.src);
-    const uint64_t e0 = (seg - J.seg_base) * kSegElems;
-    const uint64_t e1 = J.n - e0 < (uint64_t)kSegElems ? J.n : e0 + kSegElems;
-    RangeAcc acc;
-    const int tid = threadIdx.x;
-    if (ALIGNED && e1 - e0 == (uint64_t)kSegElems) {
-        const f4 *x4 = reinterpret_cast<const f4 *>(x + e0);
-#pragma unroll 8
-        for (int k = 0; k < kSegElems / (4 * kStatsThreads); k++)
-            acc.take4(__builtin_nontemporal_load(x4 + k * kStatsThreads + tid));
-    } else {
-        for (uint64_t i = e0 + tid; i < e1; i += kStatsThreads) acc.take(x[i]);
+    // workgroups loop over segments (one partial each), so the job search and
+    // the workgroup start are paid once per several segments
+    for (uint64_t seg = blockIdx.x; seg < b.total_segs; seg += gridDim.x) {
+        const uint32_t job = __builtin_amdgcn_readfirstlane(find_job(b.seg_end, b.njobs, seg));
+        if (job >= b.njobs) return;
+        const BatchJob &J = b.jobs[job];
+        const float *x = static_cast<const float *>(J.src);
+        const uint64_t e0 = (seg - J.seg_base) * kSegElems;
+        const uint64_t e1 = J.n - e0 < (uint64_t)kSegElems ? J.n : e0 + kSegElems;
+        RangeAcc acc;
+        const int tid = threadIdx.x;
+        if (ALIGNED && e1 - e0 == (uint64_t)kSegElems) {
+            const f4 *x4 = reinterpret_cast<const f4 *>(x + e0);
+            f4 v[kSegElems / (4 * kStatsThreads)];
+#pragma unroll
+            for (int k = 0; k < kSegElems / (4 * kStatsThreads); k++)
+                v[k] = __builtin_nontemporal_load(x4 + k * kStatsThreads + tid);
+#pragma unroll
+            for (int k = 0; k < kSegElems / (4 * kStatsThreads); k++) acc.take4(v[k]);
+        } else {
+            for (uint64_t i = e0 + tid; i < e1; i += kStatsThreads) acc.take(x[i]);
+        }
+        const StatsPartial p = acc.reduce();
+        if (tid == 0) b.partials[seg] = p;
+        __syncthreads();  // the reduction's shared slots are reused by the next segment
     }
-    const StatsPartial p = acc.reduce();
-    if (tid == 0) b.partials[seg] = p;
 }
 
 // Per-job fold of the batched range pass (one workgroup per job).
@@ -2921,21 +2955,34 @@ static hipError_t launch_decompress_w(const DecompressArgs &a, hipStream_t s)
 }
 
 hipError_t launch_decompress_prescan(const DecompressArgs &a, unsigned long long *offsets, uint32_t *go,
-                                     bool out_aligned16, hipStream_t s)
+                                     bool out_aligned16, bool direct, hipStream_t s)
 {
-    constexpr int W = 8;  // the decoder's waves per workgroup; a chunk is 8 tiles per wave
+    // chunks of 8 tiles per wave: 8 waves (persistent grid) or 4 (one chunk per workgroup)
+    const int W = direct ? 4 : 8;
     DecompressArgs p = a;
     p.offsets = offsets;
     p.go = go;
     const uint64_t nchunks = a.ntiles ? ceil_div(a.ntiles, (uint64_t)kTilesPerWave * W) : 1;
     const uint64_t g1 = a.ntiles ? ceil_div(a.ntiles, 256) : 1;
-    hipLaunchKernelGGL(dec_chunk_sizes_kernel<kTilesPerWave * W>, dim3((unsigned)g1), dim3(256), 0, s, p, offsets,
-                       nchunks);
+    if (direct)
+        hipLaunchKernelGGL(dec_chunk_sizes_kernel<kTilesPerWave * 4>, dim3((unsigned)g1), dim3(256), 0, s, p,
+                           offsets, nchunks);
+    else
+        hipLaunchKernelGGL(dec_chunk_sizes_kernel<kTilesPerWave * 8>, dim3((unsigned)g1), dim3(256), 0, s, p,
+                           offsets, nchunks);
     hipLaunchKernelGGL(dec_offsets_kernel, dim3(1), dim3(1024), 0, s, p, offsets, nchunks, go);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return out_aligned16 ? launch_decompress_w<true, true, W, false, false, true>(p, s)
-                         : launch_decompress_w<false, true, W, false, false, true>(p, s);
+    if (direct) {
+        p.nchunks = nchunks;
+        if (out_aligned16)
+            hipLaunchKernelGGL((decompress_direct_kernel<true, 4>), dim3((unsigned)nchunks), dim3(256), 0, s, p);
+        else
+            hipLaunchKernelGGL((decompress_direct_kernel<false, 4>), dim3((unsigned)nchunks), dim3(256), 0, s, p);
+        return hipGetLastError();
+    }
+    return out_aligned16 ? launch_decompress_w<true, true, 8, false, false, true>(p, s)
+                         : launch_decompress_w<false, true, 8, false, false, true>(p, s);
 }
 
 // +0.0 into out[0, n): 16-byte nontemporal stores from the first 16-byte
@@ -3210,7 +3257,8 @@ bool batch_shape_supported(const BatchShape &shape)
 hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, bool any_decompress,
                         const BatchShape &shape, hipStream_t s)
 {
-    uint64_t grid = b.total_segs;
+    // workgroups loop over segments; enough of them to clear the flags
+    uint64_t grid = b.total_segs < 2048 ? b.total_segs : 2048;
     const uint64_t clear = ceil_div(b.nflags, kStatsThreads);
     if (grid < clear) grid = clear < kStatsMaxBlocks ? clear : kStatsMaxBlocks;
     if (grid < 1) grid = 1;

@@ -516,3 +516,32 @@ def test_bound_step_exact_cases():
     assert _check_bound_case("clamped step", y, fsz.FSZ_ABS, 1e38) == fsz.FSZ_OK
     big = np.array([3.3e38, -1.0] * 200, dtype=np.float32)
     assert _check_bound_case("step too large", big, fsz.FSZ_ABS, 1e37) == fsz.FSZ_ERR_EB_TOO_LARGE
+
+
+@pytest.mark.timeout(600)
+def test_decoder_regimes_and_corrupt_streams():
+    """Whole-field decodes use the lookback decoder for small fields and the
+    offsets pre-pass (one chunk per workgroup, or the persistent grid) for
+    larger ones: each regime decodes bit-exactly and reports corrupt streams
+    (reserved bits, sizes that disagree with the total, padding, header
+    fields, a mismatched n) with the oracle's status."""
+    from tests.test_oracle import _mutations
+
+    old = oracle.set_threads(8)
+    try:
+        for n in (1000, (1 << 22) + 77, (1 << 26) + 5):
+            x = workloads.sinusoid_field(n, 17)
+            s = oracle.compress(x, oracle.REL, 1e-4)
+            announce(f"decoder regime n={n}: clean stream")
+            st, y = gpu_decompress(s, n)
+            assert st == fsz.FSZ_OK
+            assert np.array_equal(y.view(np.uint32), oracle.decompress(s, n).view(np.uint32))
+            for name, c, want in _mutations(s, n):
+                announce(f"decoder regime n={n}: {name}")
+                st, _ = gpu_decompress(c, n)
+                assert st == want == oracle.decompress_status(c, n)[0], (n, name, st, want)
+            announce(f"decoder regime n={n}: stream cut short")
+            st, _ = gpu_decompress(s[:-4], n)
+            assert st == fsz.FSZ_ERR_CORRUPT
+    finally:
+        oracle.set_threads(old)
