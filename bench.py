@@ -338,8 +338,17 @@ def served_run(torch, fsz, workloads, loads, counts, plain_requests=10000, budge
                 sizes_ok = False
         if not sizes_ok:
             raise RuntimeError("a served size differs from the plain path's")
-        lat = np.array([(v[4] - v[1]) / 1e6 for v in done.values()])
-        queue = np.array([(v[3] - v[1]) / 1e6 for v in done.values()])
+        keys = list(done.keys())
+        lat = np.array([(done[k][4] - done[k][1]) / 1e6 for k in keys])
+        queue = np.array([(done[k][3] - done[k][1]) / 1e6 for k in keys])
+        service = np.array([(done[k][4] - done[k][3]) / 1e6 for k in keys])
+        sizes_n = np.array([reqs[k].n for k in keys])
+        by_size = {}
+        for label, lo, hi in (("<1M", 0, 1 << 20), ("1M-16M", 1 << 20, 1 << 24), (">=16M", 1 << 24, 1 << 62)):
+            m = (sizes_n >= lo) & (sizes_n < hi)
+            if m.any():
+                by_size[label] = {"requests": int(m.sum()), "p50_ms": round(float(np.percentile(lat[m], 50)), 4),
+                                  "p99_ms": round(float(np.percentile(lat[m], 99)), 4)}
         t_first = min(v[1] for v in done.values())
         span_s = (max(v[4] for v in done.values()) - t_first) / 1e9
         comp = np.sort(np.array([v[4] for v in done.values()], dtype=np.int64))
@@ -357,6 +366,9 @@ def served_run(torch, fsz, workloads, loads, counts, plain_requests=10000, budge
             "mean_ms": round(float(lat.mean()), 4),
             "p50_wait_to_launch_ms": round(float(np.percentile(queue, 50)), 4),
             "p99_wait_to_launch_ms": round(float(np.percentile(queue, 99)), 4),
+            "p50_service_ms": round(float(np.percentile(service, 50)), 4),
+            "p99_service_ms": round(float(np.percentile(service, 99)), 4),
+            "latency_by_size": by_size,
             "rounds": rounds,
             "mean_jobs_per_round": round(count / max(rounds, 1), 2),
             "max_rounds_overlapping": int(stats.max_rounds_overlapping),

@@ -2101,14 +2101,37 @@ __global__ __launch_bounds__(kStatsThreads) void batch_stats_kernel(BatchArgs b)
         const uint64_t e1 = J.n - e0 < (uint64_t)kSegElems ? J.n : e0 + kSegElems;
         RangeAcc acc;
         const int tid = threadIdx.x;
-        if (ALIGNED && e1 - e0 == (uint64_t)kSegElems) {
+        if (ALIGNED) {  // 16-byte loads, four in flight per thread; a ragged segment's last 0-3 elements singly
             const f4 *x4 = reinterpret_cast<const f4 *>(x + e0);
-            f4 v[kSegElems / (4 * kStatsThreads)];
-#pragma unroll
-            for (int k = 0; k < kSegElems / (4 * kStatsThreads); k++)
-                v[k] = __builtin_nontemporal_load(x4 + k * kStatsThreads + tid);
-#pragma unroll
-            for (int k = 0; k < kSegElems / (4 * kStatsThreads); k++) acc.take4(v[k]);
+            const uint32_t nv = (uint32_t)((e1 - e0) / 4);
+            if (nv == kSegElems / 4) {
+#pragma unroll 2
+                for (int k = 0; k < kSegElems / (4 * kStatsThreads); k += 4) {
+                    const f4 f0 = __builtin_nontemporal_load(x4 + (k + 0) * kStatsThreads + tid);
+                    const f4 f1 = __builtin_nontemporal_load(x4 + (k + 1) * kStatsThreads + tid);
+                    const f4 f2 = __builtin_nontemporal_load(x4 + (k + 2) * kStatsThreads + tid);
+                    const f4 f3 = __builtin_nontemporal_load(x4 + (k + 3) * kStatsThreads + tid);
+                    acc.take4(f0);
+                    acc.take4(f1);
+                    acc.take4(f2);
+                    acc.take4(f3);
+                }
+            } else {
+                uint32_t k = tid;
+                for (; k + 3 * kStatsThreads < nv; k += 4 * kStatsThreads) {
+                    const f4 f0 = __builtin_nontemporal_load(x4 + k);
+                    const f4 f1 = __builtin_nontemporal_load(x4 + k + kStatsThreads);
+                    const f4 f2 = __builtin_nontemporal_load(x4 + k + 2 * kStatsThreads);
+                    const f4 f3 = __builtin_nontemporal_load(x4 + k + 3 * kStatsThreads);
+                    acc.take4(f0);
+                    acc.take4(f1);
+                    acc.take4(f2);
+                    acc.take4(f3);
+                }
+                for (; k < nv; k += kStatsThreads) acc.take4(x4[k]);
+                const uint64_t t = e0 + 4ull * nv + tid;
+                if (t < e1) acc.take(x[t]);
+            }
         } else {
             for (uint64_t i = e0 + tid; i < e1; i += kStatsThreads) acc.take(x[i]);
         }
