@@ -81,8 +81,9 @@ typedef struct {
  * arithmetic; never fails. */
 size_t fsz_compressed_bound(size_t n);
 
-/* Human-readable name of a status value (static string). */
-const char *fsz_status_string(int status);
+/* Human-readable name of a status value (static string; "unknown status"
+ * for values outside the enumeration). */
+const char *fsz_status_string(fsz_status status);
 
 /* Value-range pass (needed for REL, Sec. V-A, and for the step tightening
  * in both modes): min, max, max|x| and finiteness of d_in[0..n) into the

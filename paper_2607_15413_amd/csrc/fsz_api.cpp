@@ -762,9 +762,9 @@ size_t fsz_compressed_bound_config(size_t n, int block, int tile_blocks)
     return (size_t)(kHeaderBytes + pad16(nblocks) + 4 * ntiles + (uint64_t)(block / 8) * 32 * nblocks);
 }
 
-const char *fsz_status_string(int s)
+const char *fsz_status_string(fsz_status s)
 {
-    switch (s) {
+    switch (static_cast<int>(s)) {  // C callers may pass any int
     case FSZ_OK: return "ok";
     case FSZ_ERR_INVALID_ARG: return "invalid argument";
     case FSZ_ERR_NONFINITE: return "input holds NaN or Inf";

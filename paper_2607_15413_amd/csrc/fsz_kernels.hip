@@ -1870,33 +1870,48 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
 // ------------------------------------------------------------------ whole-field decode: offsets pre-pass
 //
 // A whole-field decode's chunk offsets depend on the rate header alone
-// (decompression steps 1-2, Sec. III-A), so two small launches compute them
+// (decompression steps 1-2, Sec. III-A), so one small launch computes them
 // before the decoder starts, and the decoder reads its chunk's offset instead
-// of waiting on a lookback:
-//   dec_chunk_sizes_kernel: one lane per tile adds its block sizes (and the
-//     mean); a chunk's TPC lanes add up; bit 63 marks a reserved rate-byte bit;
-//   dec_offsets_kernel: one workgroup turns the sizes into exclusive offsets
-//     in place, checks them against the header's total and the padding, and
-//     writes the outcome (the decoder's go word and the call's result).
+// of waiting on a lookback.
 
-// wave-uniform sum of v over the aligned group of TPC lanes holding this lane
-template <int TPC>
-__device__ __forceinline__ uint32_t group_sum_lanes(uint32_t v)
-{
-#pragma unroll
-    for (int off = 1; off < TPC; off <<= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
-    return v;
-}
+// The offsets pre-pass, in one pass: workgroups of 1024 threads, one
+// tile per thread, taken in ticket order.  A workgroup adds up its tiles'
+// sizes, publishes its total in the flag words and takes its exclusive prefix
+// by the decoupled lookback, then writes the offsets of its chunks (TPC tiles
+// each, so no chunk straddles two workgroups).  Reserved rate-byte bits ride
+// on the flags' error bit; the workgroup holding the last tiles checks the
+// header's total and the padding and reports the outcome.
+constexpr int kScanTiles = 1024;
 
 template <int TPC>
-__global__ __launch_bounds__(256) void dec_chunk_sizes_kernel(DecompressArgs a, unsigned long long *sizes,
-                                                              uint64_t nchunks)
+__global__ __launch_bounds__(kScanTiles) void dec_offsets_single_kernel(DecompressArgs a, unsigned long long *offs,
+                                                                        uint32_t *go, uint64_t ngroups)
 {
+    __shared__ uint32_t wsum[kScanTiles / 64];
+    __shared__ unsigned long long gbase;
+    __shared__ unsigned long long tk;
+    __shared__ int gbad;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    if (tid == 0) {
+        tk = take_ticket(a.ticket, ngroups);
+        gbad = 0;
+    }
+    __syncthreads();
+    const uint64_t g = tk;
     float E;
     uint64_t total;
     bool indep;
-    if (dec_header(a, E, total, indep) != FSZ_OK) return;  // the offsets kernel reports it
-    const uint64_t tile = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int hst = dec_header(a, E, total, indep);
+    if (hst != FSZ_OK) {
+        if (tid == 0 && g == 0) {
+            *go = (uint32_t)hst;
+            write_final(a.final, 0, hst, a.epoch);
+        }
+        return;
+    }
+    const uint64_t tile = g * kScanTiles + tid;
     uint32_t z = 0, bad = 0;
     if (tile < a.ntiles) {
         // the 8 rate bytes of a tile lie inside the (zero-padded) rate header,
@@ -1914,76 +1929,37 @@ __global__ __launch_bounds__(256) void dec_chunk_sizes_kernel(DecompressArgs a, 
             }
         }
     }
-    const uint32_t sum = group_sum_lanes<TPC>(z);
-    const int lane = threadIdx.x & 63;
-    const unsigned long long gmask = (TPC == 64 ? ~0ull : ((1ull << TPC) - 1)) << (lane & ~(TPC - 1));
-    const bool gbad = (__ballot(bad != 0) & gmask) != 0;
-    const uint64_t chunk = tile / TPC;
-    if ((lane & (TPC - 1)) == 0 && chunk < nchunks) sizes[chunk] = sum | (gbad ? 1ull << 63 : 0ull);
-}
-
-// inclusive prefix over the 64 lanes of the wave, 64-bit (every lane active)
-__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v)
-{
-    v += dpp64<kRowShr1>(v);
-    v += dpp64<kRowShr2>(v);
-    v += dpp64<kRowShr4>(v);
-    v += dpp64<kRowShr8>(v);
-    v += dpp64<kRowBcast15, 0xA>(v);
-    v += dpp64<kRowBcast31, 0xC>(v);
-    return v;
-}
-
-__global__ __launch_bounds__(1024) void dec_offsets_kernel(DecompressArgs a, unsigned long long *offs,
-                                                           uint64_t nchunks, uint32_t *go)
-{
-    __shared__ unsigned long long wsum[16];
-    __shared__ int any_bad;
-    float E;
-    uint64_t total;
-    bool indep;
-    const int hst = dec_header(a, E, total, indep);
-    if (hst != FSZ_OK) {
-        if (threadIdx.x == 0) {
-            *go = (uint32_t)hst;
-            write_final(a.final, 0, hst, a.epoch);
+    const uint32_t incl = (uint32_t)wave_incl_scan((int)z);
+    if (lane == 63) wsum[w] = incl;
+    if (__ballot(bad != 0) != 0 && lane == 0) gbad = 1;
+    __syncthreads();
+    uint32_t wave_base = 0, gtotal = 0;
+#pragma unroll
+    for (int k = 0; k < kScanTiles / 64; k++) {
+        if (k < w) wave_base += wsum[k];
+        gtotal += wsum[k];
+    }
+    if (w == 0) {
+        bool padbad = false;
+        if (g == ngroups - 1) {  // the rate header's zero padding: at most 15 bytes, one lane each
+            const uint64_t k = kHeaderBytes + a.nblocks + (uint64_t)lane;
+            padbad = __ballot(lane < 16 && k < a.data0 && a.cmp[k] != 0) != 0;
         }
-        return;
+        if (lane == 0) publish_aggregate(a.flags, g, a.flag_epoch, gtotal, gbad != 0);
+        const Prefix pre = lookback_wait(a.flags, g, a.flag_epoch, gtotal, gbad != 0);
+        if (lane == 0) {
+            gbase = pre.excl;
+            if (g == ngroups - 1) {  // pre.err: a reserved bit in any group (or a lookback that gave up)
+                const bool ok = !pre.err && !padbad && a.data0 + pre.excl + gtotal == total;
+                const uint32_t st = ok ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT;
+                *go = st;
+                write_final(a.final, total, st, a.epoch);
+            }
+        }
     }
-    const int tid = threadIdx.x;
-    if (tid == 0) any_bad = 0;
     __syncthreads();
-    // the rate header's zero padding: at most 15 bytes, one lane each
-    if (tid < 16 && kHeaderBytes + a.nblocks + tid < a.data0 && a.cmp[kHeaderBytes + a.nblocks + tid] != 0)
-        any_bad = 1;
-    const uint64_t per = (nchunks + 1023) / 1024;
-    const uint64_t lo = (uint64_t)tid * per < nchunks ? (uint64_t)tid * per : nchunks;
-    const uint64_t hi = lo + per < nchunks ? lo + per : nchunks;
-    constexpr unsigned long long kBad = 1ull << 63;
-    unsigned long long sum = 0;
-    bool bad = false;
-    for (uint64_t c = lo; c < hi; c++) {
-        const unsigned long long v = offs[c];
-        bad = bad || (v & kBad) != 0;
-        sum += v & ~kBad;
-    }
-    if (bad) any_bad = 1;
-    const unsigned long long incl = wave_incl_scan_u64(sum);
-    if ((tid & 63) == 63) wsum[tid >> 6] = incl;
-    __syncthreads();
-    unsigned long long excl = incl - sum;
-    for (int k = 0; k < (tid >> 6); k++) excl += wsum[k];
-    for (uint64_t c = lo; c < hi; c++) {
-        const unsigned long long v = offs[c] & ~kBad;
-        offs[c] = excl;
-        excl += v;
-    }
-    if (tid == 1023) {  // excl now holds the sum of every chunk
-        const bool ok = any_bad == 0 && a.data0 + excl == total;
-        const uint32_t st = ok ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT;
-        *go = st;
-        write_final(a.final, total, st, a.epoch);
-    }
+    if (tile < a.ntiles && (tile % TPC) == 0) offs[tile / TPC] = gbase + wave_base + incl - z;
+    if (a.ntiles == 0 && tid == 0) offs[0] = 0;
 }
 
 // Whole-field decoder for the offsets pre-pass, one chunk of 8*W tiles per
@@ -2986,14 +2962,13 @@ hipError_t launch_decompress_prescan(const DecompressArgs &a, unsigned long long
     p.offsets = offsets;
     p.go = go;
     const uint64_t nchunks = a.ntiles ? ceil_div(a.ntiles, (uint64_t)kTilesPerWave * W) : 1;
-    const uint64_t g1 = a.ntiles ? ceil_div(a.ntiles, 256) : 1;
+    const uint64_t ngroups = a.ntiles ? ceil_div(a.ntiles, (uint64_t)kScanTiles) : 1;
     if (direct)
-        hipLaunchKernelGGL(dec_chunk_sizes_kernel<kTilesPerWave * 4>, dim3((unsigned)g1), dim3(256), 0, s, p,
-                           offsets, nchunks);
+        hipLaunchKernelGGL(dec_offsets_single_kernel<kTilesPerWave * 4>, dim3((unsigned)ngroups), dim3(kScanTiles), 0,
+                           s, p, offsets, go, ngroups);
     else
-        hipLaunchKernelGGL(dec_chunk_sizes_kernel<kTilesPerWave * 8>, dim3((unsigned)g1), dim3(256), 0, s, p,
-                           offsets, nchunks);
-    hipLaunchKernelGGL(dec_offsets_kernel, dim3(1), dim3(1024), 0, s, p, offsets, nchunks, go);
+        hipLaunchKernelGGL(dec_offsets_single_kernel<kTilesPerWave * 8>, dim3((unsigned)ngroups), dim3(kScanTiles), 0,
+                           s, p, offsets, go, ngroups);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (direct) {
