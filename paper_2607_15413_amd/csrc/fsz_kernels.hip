@@ -1874,20 +1874,23 @@ __global__ __launch_bounds__(W * 64) void decompress_kernel(DecompressArgs a)
 // before the decoder starts, and the decoder reads its chunk's offset instead
 // of waiting on a lookback.
 
-// The offsets pre-pass, in one pass: workgroups of 1024 threads, one
-// tile per thread, taken in ticket order.  A workgroup adds up its tiles'
+// The offsets pre-pass, in one pass: workgroups of 1024 threads, each thread
+// 4 consecutive tiles, taken in ticket order.  A workgroup adds up its tiles'
 // sizes, publishes its total in the flag words and takes its exclusive prefix
 // by the decoupled lookback, then writes the offsets of its chunks (TPC tiles
-// each, so no chunk straddles two workgroups).  Reserved rate-byte bits ride
-// on the flags' error bit; the workgroup holding the last tiles checks the
-// header's total and the padding and reports the outcome.
-constexpr int kScanTiles = 1024;
+// each, so no chunk straddles two threads or workgroups).  Reserved rate-byte
+// bits ride on the flags' error bit; the workgroup holding the last tiles
+// checks the header's total and the padding and reports the outcome.
+constexpr int kScanThreads = 1024;
+constexpr int kScanTilesPerThread = 4;
+constexpr int kScanTiles = kScanThreads * kScanTilesPerThread;
 
 template <int TPC>
-__global__ __launch_bounds__(kScanTiles) void dec_offsets_single_kernel(DecompressArgs a, unsigned long long *offs,
-                                                                        uint32_t *go, uint64_t ngroups)
+__global__ __launch_bounds__(kScanThreads) void dec_offsets_single_kernel(DecompressArgs a, unsigned long long *offs,
+                                                                          uint32_t *go, uint64_t ngroups)
 {
-    __shared__ uint32_t wsum[kScanTiles / 64];
+    static_assert(TPC % kScanTilesPerThread == 0, "a chunk starts at a thread's first tile");
+    __shared__ uint32_t wsum[kScanThreads / 64];
     __shared__ unsigned long long gbase;
     __shared__ unsigned long long tk;
     __shared__ int gbad;
@@ -1911,21 +1914,25 @@ __global__ __launch_bounds__(kScanTiles) void dec_offsets_single_kernel(Decompre
         }
         return;
     }
-    const uint64_t tile = g * kScanTiles + tid;
+    // the rate bytes of a tile lie inside the (zero-padded) rate header, which
+    // the header check placed inside the buffer
+    const uint64_t tile0 = (g * kScanThreads + tid) * kScanTilesPerThread;
     uint32_t z = 0, bad = 0;
-    if (tile < a.ntiles) {
-        // the 8 rate bytes of a tile lie inside the (zero-padded) rate header,
-        // which the header check placed inside the buffer
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(a.cmp + kHeaderBytes + tile * kBlocksPerTile);
-        const uint32_t w0 = p[0], w1 = p[1];
-        const uint64_t nb64 = a.nblocks - tile * kBlocksPerTile;
-        const uint32_t nb = nb64 < kBlocksPerTile ? (uint32_t)nb64 : (uint32_t)kBlocksPerTile;
 #pragma unroll
-        for (uint32_t b = 0; b < kBlocksPerTile; b++) {
-            const uint32_t rb = ((b < 4 ? w0 : w1) >> (8 * (b & 3))) & 0xFFu;
-            if (b < nb) {
-                bad |= b == 0 ? (rb & 0x20u) : (rb & 0xE0u);
-                z += block_bytes(rb & 31u) + ((b == 0 && (rb & 0x40u)) ? 4u : 0u);
+    for (int i = 0; i < kScanTilesPerThread; i++) {
+        const uint64_t tile = tile0 + i;
+        if (tile < a.ntiles) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(a.cmp + kHeaderBytes + tile * kBlocksPerTile);
+            const uint32_t w0 = p[0], w1 = p[1];
+            const uint64_t nb64 = a.nblocks - tile * kBlocksPerTile;
+            const uint32_t nb = nb64 < kBlocksPerTile ? (uint32_t)nb64 : (uint32_t)kBlocksPerTile;
+#pragma unroll
+            for (uint32_t b = 0; b < kBlocksPerTile; b++) {
+                const uint32_t rb = ((b < 4 ? w0 : w1) >> (8 * (b & 3))) & 0xFFu;
+                if (b < nb) {
+                    bad |= b == 0 ? (rb & 0x20u) : (rb & 0xE0u);
+                    z += block_bytes(rb & 31u) + ((b == 0 && (rb & 0x40u)) ? 4u : 0u);
+                }
             }
         }
     }
@@ -1935,7 +1942,7 @@ __global__ __launch_bounds__(kScanTiles) void dec_offsets_single_kernel(Decompre
     __syncthreads();
     uint32_t wave_base = 0, gtotal = 0;
 #pragma unroll
-    for (int k = 0; k < kScanTiles / 64; k++) {
+    for (int k = 0; k < kScanThreads / 64; k++) {
         if (k < w) wave_base += wsum[k];
         gtotal += wsum[k];
     }
@@ -1958,7 +1965,7 @@ __global__ __launch_bounds__(kScanTiles) void dec_offsets_single_kernel(Decompre
         }
     }
     __syncthreads();
-    if (tile < a.ntiles && (tile % TPC) == 0) offs[tile / TPC] = gbase + wave_base + incl - z;
+    if (tile0 < a.ntiles && (tile0 % TPC) == 0) offs[tile0 / TPC] = gbase + wave_base + incl - z;
     if (a.ntiles == 0 && tid == 0) offs[0] = 0;
 }
 
@@ -2964,10 +2971,10 @@ hipError_t launch_decompress_prescan(const DecompressArgs &a, unsigned long long
     const uint64_t nchunks = a.ntiles ? ceil_div(a.ntiles, (uint64_t)kTilesPerWave * W) : 1;
     const uint64_t ngroups = a.ntiles ? ceil_div(a.ntiles, (uint64_t)kScanTiles) : 1;
     if (direct)
-        hipLaunchKernelGGL(dec_offsets_single_kernel<kTilesPerWave * 4>, dim3((unsigned)ngroups), dim3(kScanTiles), 0,
+        hipLaunchKernelGGL(dec_offsets_single_kernel<kTilesPerWave * 4>, dim3((unsigned)ngroups), dim3(kScanThreads), 0,
                            s, p, offsets, go, ngroups);
     else
-        hipLaunchKernelGGL(dec_offsets_single_kernel<kTilesPerWave * 8>, dim3((unsigned)ngroups), dim3(kScanTiles), 0,
+        hipLaunchKernelGGL(dec_offsets_single_kernel<kTilesPerWave * 8>, dim3((unsigned)ngroups), dim3(kScanThreads), 0,
                            s, p, offsets, go, ngroups);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
