@@ -49,10 +49,13 @@ __device__ __forceinline__ float dppf(float v)
     return __int_as_float(dpp<CTRL>(__float_as_int(v)));
 }
 
-// value of lane 8*(lane/8) (block 0 of the lane's tile)
+// value of lane 8*(lane/8) (block 0 of the lane's tile), in registers: each
+// quad takes its first lane, then banks 1 and 3 of every row (lanes 4-7,
+// 12-15) take the quad 4 lanes below
 __device__ __forceinline__ int group_head(int v)
 {
-    return __builtin_amdgcn_ds_swizzle(v, 0x0018);
+    v = dpp<0x00>(v);  // quad_perm:[0,0,0,0]
+    return __builtin_amdgcn_update_dpp(v, v, kRowShr4, 0xF, 0xA, false);
 }
 
 // sum over the 8 lanes of a tile, result in all 8 lanes
@@ -365,18 +368,43 @@ __device__ __forceinline__ void publish_aggregate(unsigned long long *flags, uin
 // the 64 nearest unresolved predecessors; while one of them is not ready the
 // wave re-reads only that single flag word (with a short sleep), so waiting
 // chunks add little memory traffic, and then probes the window again.
-// The first window's flags, read ahead of time by the whole wave (lane l
-// reads the flag of chunk - 1 - l); lookback_wait re-reads whatever was not
-// ready yet.
-__device__ __forceinline__ unsigned long long lookback_probe(unsigned long long *flags, uint64_t chunk, uint32_t ep)
+//
+// The caller may read the nearest kProbeWindows windows ahead of time
+// (window m, lane l: the flag of chunk - 1 - 64 m - l); the lookback walks
+// those values before it issues a load of its own.  A flag that was ready
+// when it was read stays valid (an aggregate or an inclusive prefix of this
+// launch never changes value); a window read ahead that still shows a word
+// not ready is read again before the wave waits on that word.  One window:
+// flag words are read across the XCDs' caches at agent scope, and on the
+// 512^3 field one more window read ahead per step (walked or not) cost the
+// compressor more time than the walks it saved.
+constexpr int kProbeWindows = 1;
+struct Probe {
+    unsigned long long f[kProbeWindows];
+};
+
+__device__ __forceinline__ Probe lookback_probe(unsigned long long *flags, uint64_t chunk, uint32_t ep)
 {
-    const long long idx = (long long)chunk - 1 - __lane_id();
-    return idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                    : pack_flag(kFlagInclusive, ep, false, 0);
+    Probe p;
+#pragma unroll
+    for (int m = 0; m < kProbeWindows; m++) {
+        const long long idx = (long long)chunk - 1 - 64 * m - __lane_id();
+        p.f[m] = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                          : pack_flag(kFlagInclusive, ep, false, 0);
+    }
+    return p;
+}
+
+// Makes the probe's loads complete here on every path (an empty asm that
+// reads the registers).
+__device__ __forceinline__ void consume_probe(const Probe &p)
+{
+#pragma unroll
+    for (int m = 0; m < kProbeWindows; m++) asm volatile("; probe %0" ::"v"(p.f[m]));
 }
 
 __device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint32_t ep, uint64_t total, bool err,
-                                bool has_probe = false, unsigned long long probe = 0)
+                                bool has_probe = false, Probe probe = Probe{})
 {
     const int lane = __lane_id();
     if (chunk == 0) return Prefix{0, err};
@@ -387,14 +415,20 @@ __device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint3
     auto state_of = [&](unsigned long long f) -> uint32_t {
         return (uint32_t)((f >> kEpochShift) & kEpochMask) == ep ? (uint32_t)(f >> 62) : 0u;
     };
-    bool use_probe = has_probe;
+    int window = has_probe ? 0 : kProbeWindows;  // windows walked so far (read-ahead ones first)
+    bool reread = false;                          // read the current window now
     for (;;) {
         const long long idx = pos - lane;
-        const unsigned long long f =
-            use_probe ? probe
-                      : (idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                  : pack_flag(kFlagInclusive, ep, false, 0));
-        use_probe = false;
+        const bool ahead = window < kProbeWindows && !reread;
+        unsigned long long f;
+        if (ahead) {
+            f = probe.f[0];
+#pragma unroll
+            for (int m = 1; m < kProbeWindows; m++) f = window == m ? probe.f[m] : f;
+        } else {
+            f = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         : pack_flag(kFlagInclusive, ep, false, 0);
+        }
         const uint32_t state = state_of(f);
         const unsigned long long not_ready = __ballot(state == 0);
         const unsigned long long incl = __ballot(state == kFlagInclusive);
@@ -412,9 +446,14 @@ __device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint3
             excl += wave_sum_u64(v);
             perr = perr || (__ballot(e) != 0);
             pos -= 64;
+            window = window < kProbeWindows ? window + 1 : kProbeWindows;
+            reread = false;
             continue;
         }
-        // wait on the nearest predecessor that is not ready yet
+        reread = true;
+        if (ahead) continue;  // the read-ahead values are old: read the window first
+        // wait on the nearest predecessor that is not ready yet, then read
+        // this window again
         const long long widx = pos - __builtin_ctzll(not_ready & need);
         for (;;) {
             if (++spins >= kLookbackSpinLimit) break;
@@ -605,8 +644,10 @@ __global__ __launch_bounds__(kStatsThreads) void stats_final_kernel(StatsArgs a,
 
 // ------------------------------------------------------------------ compress
 
-__device__ __forceinline__ int max3i(int a, int b, int c) { return max(a, max(b, c)); }
-__device__ __forceinline__ int min3i(int a, int b, int c) { return min(a, min(b, c)); }
+// The accumulator goes first: max(max(acc, a), b) selects to one v_max3 per
+// two new values, where max(acc, max(a, b)) costs a v_max and a v_max3.
+__device__ __forceinline__ int max3i(int acc, int a, int b) { return max(max(acc, a), b); }
+__device__ __forceinline__ int min3i(int acc, int a, int b) { return min(min(acc, a), b); }
 
 // Quantization (Sec. IV-B, q = round(x / (2 eb)) read as rint(fl(x * inv))):
 // for |t| < 2^22 the binary32 sum t + 1.5 * 2^23 rounds t to the nearest
@@ -618,14 +659,16 @@ constexpr float kQMagic = 12582912.0f;  // 1.5 * 2^23
 constexpr int kQBias = 0x4B400000;       // bits of kQMagic
 
 // Extrema of the LZ1 / LZ2 residual magnitudes of one block (Sec. IV-A,
-// Eq. (2); Sec. IV-B) from biased quantized values B.  The predictor state
+// Eq. (2); Sec. IV-B) from biased quantized values B, which are replaced by
+// the block's LZ1 residuals d[i] = q[i] - q[i-1] (0 in slots past the end of
+// the field); the LZ2 residual is d[i] - d[i-1].  The predictor state
 // (carry_b = biased q of the previous block's last element, carry_l1 = its
-// LZ1 residual) crosses the block boundary; at a tile start q[-1] = q[-2] = 0.
-// Block 0 of a tile (j == 0) leaves its first one (LZ1) or two (LZ2)
-// residuals out: they are re-rated per variant.  Slots whose bit in vm is
-// clear lie past the end of the field and carry residual 0.
+// LZ1 residual) crosses the block boundary; at a tile start q[-1] = q[-2] = 0,
+// so there d[0] = q[0].  Block 0 of a tile (j == 0) leaves its first one
+// (LZ1) or two (LZ2) residuals out: they are re-rated per variant.  Slots
+// whose bit in vm is clear lie past the end of the field and carry residual 0.
 template <bool FULL>
-__device__ __forceinline__ void block_extrema(const int (&B)[32], int carry_b, int carry_l1, int j, uint32_t vm,
+__device__ __forceinline__ void block_extrema(int (&B)[32], int carry_b, int carry_l1, int j, uint32_t vm,
                                               uint32_t &a1, uint32_t &a2, int &l2_1)
 {
     auto live = [&](int i, int v) { return FULL ? v : (v & ((int)(vm << (31 - i)) >> 31)); };
@@ -640,22 +683,29 @@ __device__ __forceinline__ void block_extrema(const int (&B)[32], int carry_b, i
     const int e21 = j ? l2_1v : l2_2;
     int mx1 = max3i(e10, l1_1, l1_2), mn1 = min3i(e10, l1_1, l1_2);
     int mx2 = max3i(e20, e21, l2_2), mn2 = min3i(e20, e21, l2_2);
-    int pl = d2;
+    int pl = d2, pb = B[2];
+    B[0] = l1_0;
+    B[1] = l1_1;
+    B[2] = l1_2;
 #pragma unroll
     for (int i = 3; i < 31; i += 2) {
-        const int da = B[i] - B[i - 1];
-        const int db = B[i + 1] - B[i];
+        const int ba = B[i], bb = B[i + 1];
+        const int da = ba - pb;
+        const int db = bb - ba;
         const int l1a = live(i, da), l2a = live(i, da - pl);
         const int l1b = live(i + 1, db), l2b = live(i + 1, db - da);
         pl = db;
+        pb = bb;
+        B[i] = l1a;
+        B[i + 1] = l1b;
         mx1 = max3i(mx1, l1a, l1b);
         mn1 = min3i(mn1, l1a, l1b);
         mx2 = max3i(mx2, l2a, l2b);
         mn2 = min3i(mn2, l2a, l2b);
-        __builtin_amdgcn_sched_barrier(0);  // stream: keep few residuals live at a time
     }
-    const int d31 = B[31] - B[30];
+    const int d31 = B[31] - pb;
     const int l1z = live(31, d31), l2z = live(31, d31 - pl);
+    B[31] = l1z;
     mx1 = max(mx1, l1z);
     mn1 = min(mn1, l1z);
     mx2 = max(mx2, l2z);
@@ -664,28 +714,34 @@ __device__ __forceinline__ void block_extrema(const int (&B)[32], int carry_b, i
     a2 = max(uabs(mx2), uabs(mn2));
 }
 
-// Residual codes of the selected variant, in place: code = (|e| << 1) | sign.
-// ORDER: 1 or 2 when the whole wave uses that order, 0 = per-tile order2.
+// Residual codes of the selected variant, in place, from the LZ1 residuals d
+// that block_extrema left: e[i] = d[i] - order2 * d[i-1] with d[-1] =
+// carry_l1, and at a centred tile start (j == 0, cent) d[0] = q[0] less the
+// tile mean (the later residuals are differences, so mu cancels there).
+// code = (|e| << 1) | sign.  |d| <= 2^22 + 2 fits the 24-bit multiplier.
 // Codes of slots past the end of the field are garbage; the encoder clears
 // them in the transposed plane words.
-template <int ORDER>
-__device__ __forceinline__ void block_codes(int (&B)[32], int carry_b, int carry_l1, int j, int order2, int cent,
-                                            int mu)
+// a * b + c with a and b taken as signed 24-bit integers (one VALU
+// instruction; the compiler splits __mul24(a, b) + c into two)
+__device__ __forceinline__ int mad_i24(int a, int b, int c)
 {
-    const int om = -order2;  // all ones for LZ2
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ void block_codes(int (&D)[32], int carry_l1, int j, int order2, int cent, int mu)
+{
+    const int no2 = -order2;
     int pl = carry_l1;
-    int pb = carry_b;
+    D[0] -= (j == 0 && cent) ? mu : 0;
 #pragma unroll
     for (int i = 0; i < 32; i++) {
-        const int bi = B[i];
-        const int l1 = bi - pb;
-        int e = ORDER == 1 ? l1 : (ORDER == 2 ? l1 - pl : l1 - (pl & om));
-        pb = bi;
-        pl = l1;
-        if (i == 0 && j == 0 && cent) e = bi - kQBias - mu;
-        if (i == 1 && j == 0 && cent) e = e + (ORDER == 1 ? 0 : (ORDER == 2 ? mu : (mu & om)));
+        const int d = D[i];
+        const int e = mad_i24(pl, no2, d);
+        pl = d;
         const uint32_t m = (uint32_t)max(e, -e);
-        B[i] = (int)__builtin_amdgcn_alignbit(m, (uint32_t)e, 31);  // (|e| << 1) | (e >> 31)
+        D[i] = (int)__builtin_amdgcn_alignbit(m, (uint32_t)e, 31);  // (|e| << 1) | (e >> 31)
     }
 }
 
@@ -693,7 +749,7 @@ __device__ __forceinline__ void block_codes(int (&B)[32], int carry_b, int carry
 struct ChunkState {
     uint64_t chunk;
     int first;  // the block restarts prediction (tile start; every block without cross-block state)
-    int carry_b, carry_l1, mu;
+    int carry_l1, mu;  // LZ1 residual of the previous block (0 where prediction restarts), tile mean
     uint32_t vm, r, blk_off, tile_excl, wave_total;
     int order2, cent;
     uint32_t rbyte;  // the block's rate byte (Sec. III-A)
@@ -712,7 +768,7 @@ struct CompressShared {
 //     block 0 is re-rated per variant from q0, q1 - 2 q0 and mu
 //   3 adaptive select (strict minimum in the order LZ1, LZ2, LZ1c, LZ2c),
 //     rate header; the chunk's byte count is published for the lookback.
-// On return x holds the biased quantized values.
+// On return x holds the blocks' LZ1 residuals (block_extrema).
 // DEFER: leave the rate byte in cs.rbyte for the caller to store, and publish
 // the aggregate from wave 1 (whose memory queue the lookback does not wait on).
 // FEAT: honour a.features (the ablation's switches, Sec. VI-B): without the
@@ -766,21 +822,21 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
     const bool first = FEAT ? (j == 0 || !(a.features & FSZ_FEAT_CROSS_BLOCK)) : j == 0;
     const int jr = first ? 0 : 1;  // 0: the leading residuals are re-rated per variant
     cs.first = first;
-    cs.carry_b = first ? kQBias : t0;
+    const int carry_b = first ? kQBias : t0;
     cs.carry_l1 = first ? 0 : t1;
 
     uint32_t a1, a2;
     int l2_1;
     if (full)
-        block_extrema<true>(x, cs.carry_b, cs.carry_l1, jr, cs.vm, a1, a2, l2_1);
+        block_extrema<true>(x, carry_b, cs.carry_l1, jr, cs.vm, a1, a2, l2_1);
     else
-        block_extrema<false>(x, cs.carry_b, cs.carry_l1, jr, cs.vm, a1, a2, l2_1);
+        block_extrema<false>(x, carry_b, cs.carry_l1, jr, cs.vm, a1, a2, l2_1);
     const uint32_t r1 = bitlen(a1), r2 = bitlen(a2);
     uint32_t Z;
     if (FEAT) {
         // every restarting block is rated per variant, the others have one
         // rate per order; tile costs by 8-lane sums (same in all 8 lanes)
-        const int q0 = x[0] - kQBias;
+        const int q0 = x[0];  // d[0] = q[0] at a tile start
         const int d1 = cnt >= 2 ? l2_1 : 0;  // q1 - 2 q0
         const int c0 = q0 - mu;
         const int c1 = cnt >= 2 ? l2_1 + mu : 0;
@@ -832,7 +888,7 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
     // ---- four-way evaluation of block 0 and the selection (valid in lane j == 0)
     int dec;
     {
-        const int q0 = x[0] - kQBias;
+        const int q0 = x[0];  // d[0] = q[0] at a tile start
         const int d1 = cnt >= 2 ? l2_1 : 0;  // q1 - 2 q0
         const int c0 = q0 - mu;
         const int c1 = cnt >= 2 ? l2_1 + mu : 0;
@@ -918,7 +974,7 @@ __device__ __forceinline__ void finish_stream(const CompressArgs &a, const Resol
 
 // Steps 4-5 of one chunk whose rate pass is done: wait for the chunk's output
 // offset (decoupled lookback, Sec. IV-D), then the sign / bit-plane encoding
-// (Sec. IV-C) straight to the output.  B holds the biased quantized values.
+// (Sec. IV-C) straight to the output.  B holds the LZ1 residuals.
 template <bool STAGED, int W, bool FEAT = false>
 __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Resolved &R, const ChunkState &cs,
                                                 int (&B)[32], int slot, CompressShared<W> &sh, uint32_t *st)
@@ -952,14 +1008,7 @@ __device__ __forceinline__ void compress_encode(const CompressArgs &a, const Res
         else
             *reinterpret_cast<uint32_t *>(wave_out + cs.tile_excl) = (uint32_t)cs.mu;
     }
-    const unsigned long long o2 = __ballot(cs.order2 != 0);
-    const unsigned long long o1 = __ballot(cs.order2 == 0);
-    if (o2 == 0)
-        block_codes<1>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, 0, cs.cent, cs.mu);
-    else if (o1 == 0)
-        block_codes<2>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, 1, cs.cent, cs.mu);
-    else
-        block_codes<0>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, cs.order2, cs.cent, cs.mu);
+    block_codes(B, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, cs.order2, cs.cent, cs.mu);
     // valid slots in stored bit order (element i at bit i ^ 7)
     const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(cs.vm));
     const uint32_t nwords = cs.r ? cs.r + 1 : 0;  // sign word + r planes
@@ -1116,7 +1165,7 @@ __global__ __launch_bounds__(kThreads) void naive_eval_kernel(CompressArgs a, Na
         block_extrema<false>(x, carry_b, carry_l1, j, vm, a1, a2, l2_1);
     uint32_t r = bitlen(order2 ? a2 : a1);
     if (j == 0) {  // block 0: the variant's own first residuals
-        const int q0 = x[0] - kQBias;
+        const int q0 = x[0];  // d[0] = q[0] at a tile start
         const int f0 = cen ? q0 - mu : q0;
         const int d1 = cnt >= 2 ? l2_1 : 0;
         const int f1 = cnt >= 2 ? (cen ? l2_1 + mu : d1) : 0;
@@ -1137,7 +1186,7 @@ __global__ __launch_bounds__(kThreads) void naive_eval_kernel(CompressArgs a, Na
 
 // Selection and bookkeeping of the encode pass: the rate pass of the single
 // pass with the evaluation replaced by reads of the tables (same choice,
-// same tie order).  On return x holds the biased quantized values.
+// same tie order).  On return x holds the blocks' LZ1 residuals.
 __device__ __forceinline__ ChunkState naive_select(const CompressArgs &a, const Resolved &R, const NaiveTables &t,
                                                    uint64_t chunk, int (&x)[32], CompressShared<kWaves> &sh)
 {
@@ -1158,8 +1207,16 @@ __device__ __forceinline__ ChunkState naive_select(const CompressArgs &a, const 
     const int t0 = dpp<kRowShr1>(x[31]);
     const int t1 = dpp<kRowShr1>(x[31] - x[30]);
     cs.first = j == 0;
-    cs.carry_b = j ? t0 : kQBias;
     cs.carry_l1 = j ? t1 : 0;
+    {  // LZ1 residuals in place, as the encoder takes them
+        int pb = j ? t0 : kQBias;
+#pragma unroll
+        for (int i = 0; i < 32; i++) {
+            const int b = x[i];
+            x[i] = b - pb;
+            pb = b;
+        }
+    }
 
     int best = 0;
     uint32_t Z = 0, r = 0;
@@ -1337,7 +1394,7 @@ __device__ __forceinline__ void chunk_read(const uint32_t *wbuf, int lane, int (
 // thread and the broadcast ticket in *next.
 template <bool W0, int W>
 __device__ __forceinline__ uint64_t pipe2_lookback(const CompressArgs &a, const Resolved &R, const ChunkState &cs,
-                                                   int slot, CompressShared<W> &sh, unsigned long long probe,
+                                                   int slot, CompressShared<W> &sh, const Probe &probe,
                                                    bool took, unsigned long long traw, uint64_t takes,
                                                    uint64_t *next)
 {
@@ -1347,8 +1404,8 @@ __device__ __forceinline__ uint64_t pipe2_lookback(const CompressArgs &a, const 
 #pragma unroll
         for (int k = 0; k < W; k++) chunk_total += sh.wave_total[slot][k];
         // the probe is consumed on every path (also for chunk 0), so the
-        // next step's read into its register does not wait on stale loads
-        asm volatile("; probe %0" ::"v"(probe));
+        // next step's reads into its registers do not wait on stale loads
+        consume_probe(probe);
         const Prefix pre = lookback_wait(a.flags, cs.chunk, a.flag_epoch, chunk_total, false, true, probe);
         const unsigned long long tk =
             took ? ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(traw >> 32)) << 32) |
@@ -1374,14 +1431,7 @@ __device__ __forceinline__ void pipe2_stage(const ChunkState &cs, int (&B)[32], 
 {
     const int j = __lane_id() & 7;
     if (cs.vm != 0 && j == 0 && cs.cent) st[cs.tile_excl >> 2] = (uint32_t)cs.mu;
-    const unsigned long long o2 = __ballot(cs.order2 != 0);
-    const unsigned long long o1 = __ballot(cs.order2 == 0);
-    if (o2 == 0)
-        block_codes<1>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, 0, cs.cent, cs.mu);
-    else if (o1 == 0)
-        block_codes<2>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, 1, cs.cent, cs.mu);
-    else
-        block_codes<0>(B, cs.carry_b, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, cs.order2, cs.cent, cs.mu);
+    block_codes(B, cs.carry_l1, FEAT ? (cs.first ? 0 : 1) : j, cs.order2, cs.cent, cs.mu);
     const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(cs.vm));
     const uint32_t nwords = cs.r ? cs.r + 1 : 0;
     uint32_t *words = st + (cs.blk_off >> 2);
@@ -1413,7 +1463,8 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
     const int lane = threadIdx.x & 63;
     const int j = lane & 7;
     const bool take = C < a.nchunks;
-    unsigned long long traw = 0, probe = 0;
+    unsigned long long traw = 0;
+    Probe probe{};
     if (W0) {
         if (take && lane == 0) traw = atomicAdd(a.ticket, 1ull);
         probe = lookback_probe(a.flags, ca.chunk, a.flag_epoch);
@@ -2398,7 +2449,8 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, const JobVi
     const CompressArgs aA = batch_compress_args(b, iA.job, JA);
     const Resolved RA = job_bound(b, v, iA.job, JA);
     const bool liveA = RA.status == FSZ_OK;
-    unsigned long long traw = 0, probe = 0;
+    unsigned long long traw = 0;
+    Probe probe{};
     if (W0) {
         if (take && lane == 0) traw = atomicAdd(b.ticket, 1ull);
         if (liveA) probe = lookback_probe(aA.flags, iA.c, aA.flag_epoch);
@@ -2422,7 +2474,7 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, const JobVi
         const uint32_t nj = b.njobs;
         const uint64_t jend = tk < N ? b.chunk_end[min((uint32_t)lane, nj - 1)] : 0;
         Prefix pre{0, false};
-        asm volatile("; probe %0" ::"v"(probe));
+        consume_probe(probe);
         if (liveA) pre = lookback_wait(aA.flags, iA.c, aA.flag_epoch, chunk_total, false, true, probe);
         uint32_t jobD = nj;
         if (tk < N) {
@@ -2653,7 +2705,7 @@ __global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressAr
     // variant, the tile start re-rated per variant
     uint32_t m0 = a1, m1 = a2, m2 = a1, m3 = a2;
     if (first) {
-        const int q0 = x[0] - kQBias;
+        const int q0 = x[0];  // d[0] = q[0] at a tile start
         const int d1 = cnt >= 2 ? l2_1 : 0;  // q1 - 2 q0
         const int c0 = q0 - mu;
         const int c1 = cnt >= 2 ? l2_1 + mu : 0;
@@ -2732,7 +2784,7 @@ __global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressAr
 
     // ---- encode (Sec. IV-C) into the wave's staging area, then one copy
     if (first && cent && tile_ok) st[tile_excl >> 2] = (uint32_t)mu;
-    block_codes<0>(x, carry_b, carry_l1, first ? 0 : 1, order2, cent, mu);
+    block_codes(x, carry_l1, first ? 0 : 1, order2, cent, mu);
     const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(vm));
     const uint32_t nwords = r ? r + 1 : 0;
     uint32_t *words = st + ((tile_excl + blk_rel) >> 2) + h;
