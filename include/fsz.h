@@ -152,7 +152,7 @@ fsz_status fsz_decompress_prezero_async(const void *d_cmp, size_t cmp_size, floa
  * forbid hipMalloc.  Same arguments, work and stream bytes as
  * fsz_compress_async (d_stats NULL runs the range pass), but the library's
  * scratch words (chunk flags, ticket, range-pass partials and stats) live
- * in one fixed array of device memory, 4,210,944 bytes per device, held
+ * in one fixed array of device memory, 16,793,856 bytes per device, held
  * from the first call on that device until the process ends; the call
  * itself allocates nothing and enqueues only kernels (no memset or copy
  * nodes), so it may be captured in a graph and replayed.

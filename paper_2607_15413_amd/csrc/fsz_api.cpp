@@ -176,8 +176,8 @@ bool ensure_flags(Workspace *ws, uint64_t nchunks)
         ws->d_flags = nullptr;
         ws->flags_cap = 0;
     }
-    if (!ok(hipMalloc(&ws->d_flags, cap * sizeof(unsigned long long)))) return false;
-    if (!ok(hipMemsetAsync(ws->d_flags, 0, cap * sizeof(unsigned long long), ws->stream))) return false;
+    if (!ok(hipMalloc(&ws->d_flags, cap * kFlagStride * sizeof(unsigned long long)))) return false;
+    if (!ok(hipMemsetAsync(ws->d_flags, 0, cap * kFlagStride * sizeof(unsigned long long), ws->stream))) return false;
     ws->flags_cap = cap;
     return true;
 }
@@ -189,7 +189,7 @@ bool next_epoch(Workspace *ws, uint32_t *epoch, uint32_t *flag_epoch)
     *epoch = ws->call;
     *flag_epoch = (ws->call - 1) % kEpochMask + 1;
     if (*flag_epoch == 1 && ws->call > 1 && ws->d_flags)
-        return ok(hipMemsetAsync(ws->d_flags, 0, ws->flags_cap * sizeof(unsigned long long), ws->stream));
+        return ok(hipMemsetAsync(ws->d_flags, 0, ws->flags_cap * kFlagStride * sizeof(unsigned long long), ws->stream));
     return true;
 }
 
@@ -640,7 +640,7 @@ BatchArgs batch_args(const BatchLayout &L, void *d_desc, uint32_t epoch, unsigne
     b.epoch = epoch;
     b.total_chunks = L.total_chunks;
     b.total_segs = L.total_segs;
-    b.nflags = L.total_chunks;
+    b.nflags = L.total_chunks * kFlagStride;  // words
     b.flags = flags;
     b.ticket = ticket;
     b.stats = stats;
@@ -671,7 +671,7 @@ fsz_status enqueue_batch(Workspace *ws, const fsz_job *jobs, size_t njobs, const
     BatchLayout L;
     fsz_status st = layout_batch(jobs, njobs, shape.waves, &L);
     if (st != FSZ_OK || njobs == 0) return st;
-    if (!grow(&ws->b_flags, &ws->b_flags_cap, L.total_chunks, ws->stream) ||
+    if (!grow(&ws->b_flags, &ws->b_flags_cap, L.total_chunks * kFlagStride, ws->stream) ||
         !grow(&ws->b_partials, &ws->b_partials_cap, std::max<uint64_t>(L.total_segs, 1), ws->stream) ||
         !grow(&ws->b_stats, &ws->b_stats_cap, njobs, ws->stream))
         return FSZ_ERR_DEVICE;
@@ -699,7 +699,7 @@ bool reserve_batch(hipStream_t stream, uint64_t jobs, uint64_t chunks, uint64_t 
     Workspace *ws = get_workspace(stream, &st);
     if (!ws) return false;
     std::lock_guard<std::mutex> g(ws->mu);
-    if (!grow(&ws->b_flags, &ws->b_flags_cap, std::max<uint64_t>(chunks, 1), ws->stream) ||
+    if (!grow(&ws->b_flags, &ws->b_flags_cap, std::max<uint64_t>(chunks, 1) * kFlagStride, ws->stream) ||
         !grow(&ws->b_partials, &ws->b_partials_cap, std::max<uint64_t>(segs, 1), ws->stream) ||
         !grow(&ws->b_stats, &ws->b_stats_cap, std::max<uint64_t>(jobs, 1), ws->stream))
         return false;
@@ -1029,7 +1029,7 @@ fsz_status fsz_plan_create(const fsz_job *jobs, size_t njobs, const fsz_tuning *
         L.pack(host.data());
         hipStream_t cs = nullptr;
         good = ok(hipMalloc(&p->d_desc, host.size())) &&
-               ok(hipMalloc(&p->d_flags, std::max<uint64_t>(L.total_chunks, 1) * sizeof(unsigned long long))) &&
+               ok(hipMalloc(&p->d_flags, std::max<uint64_t>(L.total_chunks, 1) * kFlagStride * sizeof(unsigned long long))) &&
                ok(hipMalloc(&p->d_ticket, sizeof(unsigned long long))) &&
                ok(hipMalloc(&p->d_partials, std::max<uint64_t>(L.total_segs, 1) * sizeof(StatsPartial))) &&
                ok(hipMalloc(&p->d_stats, njobs * sizeof(fsz_stats))) &&

@@ -38,6 +38,11 @@ constexpr uint32_t kEpochMask = (1u << kEpochBits) - 1;
 constexpr int kEpochShift = 44;
 constexpr int kErrorBit = 43;
 constexpr uint64_t kValueMask = (1ull << kErrorBit) - 1;
+// Chunk c's flag word sits at index c * kFlagStride of a flag array (32 bytes
+// apart, four per 128-byte line).  The words are read and written at agent
+// scope from all XCDs; packed eight to a line they measurably slowed the
+// compressor's data traffic, spread four to a line they did not.
+constexpr uint64_t kFlagStride = 4;
 
 // All prediction features on: cross-block state, centering, second order.
 constexpr uint32_t kFeaturesAll = FSZ_FEATURES_ALL;
@@ -135,7 +140,7 @@ struct BatchArgs {
     const uint64_t *seg_end;    // seg_end[j] = seg_base[j] + nsegs[j]
     uint32_t njobs;
     uint32_t epoch;             // result tag
-    uint64_t total_chunks, total_segs, nflags;
+    uint64_t total_chunks, total_segs, nflags;  // nflags: flag words (kFlagStride per chunk)
     unsigned long long *flags;  // cleared by the batch's range pass
     unsigned long long *ticket; // zero between launches (self-resetting)
     fsz_stats *stats;           // one per job

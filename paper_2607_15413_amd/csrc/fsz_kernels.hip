@@ -359,7 +359,7 @@ struct Prefix {
 __device__ __forceinline__ void publish_aggregate(unsigned long long *flags, uint64_t chunk, uint32_t ep,
                                                   uint64_t total, bool err)
 {
-    __hip_atomic_store(&flags[chunk], pack_flag(chunk == 0 ? kFlagInclusive : kFlagAggregate, ep, err, total),
+    __hip_atomic_store(&flags[chunk * kFlagStride], pack_flag(chunk == 0 ? kFlagInclusive : kFlagAggregate, ep, err, total),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -389,7 +389,7 @@ __device__ __forceinline__ Probe lookback_probe(unsigned long long *flags, uint6
 #pragma unroll
     for (int m = 0; m < kProbeWindows; m++) {
         const long long idx = (long long)chunk - 1 - 64 * m - __lane_id();
-        p.f[m] = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+        p.f[m] = idx >= 0 ? __hip_atomic_load(&flags[idx * kFlagStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                           : pack_flag(kFlagInclusive, ep, false, 0);
     }
     return p;
@@ -426,7 +426,7 @@ __device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint3
 #pragma unroll
             for (int m = 1; m < kProbeWindows; m++) f = window == m ? probe.f[m] : f;
         } else {
-            f = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+            f = idx >= 0 ? __hip_atomic_load(&flags[idx * kFlagStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                          : pack_flag(kFlagInclusive, ep, false, 0);
         }
         const uint32_t state = state_of(f);
@@ -459,7 +459,7 @@ __device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint3
             if (++spins >= kLookbackSpinLimit) break;
             __builtin_amdgcn_s_sleep(2);
             const unsigned long long g =
-                __hip_atomic_load(&flags[widx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_load(&flags[widx * kFlagStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (state_of(g) != 0) break;
         }
         if (spins >= kLookbackSpinLimit) {  // a predecessor never published: give up
@@ -469,7 +469,7 @@ __device__ Prefix lookback_wait(unsigned long long *flags, uint64_t chunk, uint3
     }
     err = err || perr;
     if (lane == 0)
-        __hip_atomic_store(&flags[chunk], pack_flag(kFlagInclusive, ep, err, excl + total), __ATOMIC_RELAXED,
+        __hip_atomic_store(&flags[chunk * kFlagStride], pack_flag(kFlagInclusive, ep, err, excl + total), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     return Prefix{excl, err};
 }
@@ -2207,7 +2207,7 @@ __device__ __forceinline__ CompressArgs batch_compress_args(const BatchArgs &b, 
     a.cfg_flags = 0;
     a.epoch = b.epoch;
     a.flag_epoch = 1;
-    a.flags = b.flags + J.chunk_base;
+    a.flags = b.flags + J.chunk_base * kFlagStride;
     a.ticket = nullptr;
     a.final = J.final;
     return a;
@@ -2232,7 +2232,7 @@ __device__ __forceinline__ DecompressArgs batch_decompress_args(const BatchArgs 
     a.cfg_flags = 0;
     a.epoch = b.epoch;
     a.flag_epoch = 1;
-    a.flags = b.flags + J.chunk_base;
+    a.flags = b.flags + J.chunk_base * kFlagStride;
     a.ticket = nullptr;
     a.final = J.final;
     return a;
@@ -3344,18 +3344,18 @@ hipError_t launch_batch(const BatchArgs &b, bool aligned16, bool any_compress, b
 // fsz_compress_noalloc_async keeps its chunk flags, ticket and range-pass
 // partials in one fixed device array instead of the per-stream workspace.
 // Layout: [0, 16 KiB) range-pass partials, then the field stats (16 bytes)
-// and the ticket (8 bytes, 128 bytes further), then from byte 16640 one flag
-// word per chunk of the smallest chunk any compress kernel uses (8 tiles,
-// 2048 elements), enough for n <= kNoAllocMaxElements.  Each call clears the
-// flags it uses and the ticket with a fill kernel (no memset node, so the
-// call may be captured in a graph and replayed).
+// and the ticket (8 bytes, 128 bytes further), then from byte 16640 the flag
+// words (kFlagStride words per chunk) of the smallest chunk any compress
+// kernel uses (8 tiles, 2048 elements), enough for n <= kNoAllocMaxElements.
+// Each call clears the flag words it uses and the ticket with a fill kernel
+// (no memset node, so the call may be captured in a graph and replayed).
 constexpr uint64_t kNoAllocMaxElements = 1ull << 30;
 constexpr size_t kNoAllocStatsOff = sizeof(StatsPartial) * kStatsMaxBlocks;
 constexpr size_t kNoAllocTicketOff = kNoAllocStatsOff + 128;
 constexpr size_t kNoAllocFlagsOff = kNoAllocStatsOff + 256;
 constexpr uint64_t kNoAllocMaxFlags = kNoAllocMaxElements / ((uint64_t)kTile * kTilesPerWave);
-constexpr size_t kNoAllocScratchBytes = kNoAllocFlagsOff + kNoAllocMaxFlags * sizeof(unsigned long long);
-static_assert(kNoAllocScratchBytes == 16640 + 8 * 524288, "scratch layout");
+constexpr size_t kNoAllocScratchBytes = kNoAllocFlagsOff + kNoAllocMaxFlags * kFlagStride * sizeof(unsigned long long);
+static_assert(kNoAllocScratchBytes == 16640 + 32 * 524288, "scratch layout");
 
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
@@ -3415,7 +3415,7 @@ fsz_status compress_noalloc(const float *d_in, uint64_t n, int mode, double valu
     a.flags = flags;
     a.ticket = ticket;
     a.final = d_result;
-    const uint64_t nflags = a.ntiles ? ceil_div(a.ntiles, kTilesPerWave) : 1;  // <= kNoAllocMaxFlags
+    const uint64_t nflags = (a.ntiles ? ceil_div(a.ntiles, kTilesPerWave) : 1) * kFlagStride;  // words
     const uint64_t want = ceil_div(nflags, 256);
     const unsigned grid = (unsigned)(want < 1024 ? want : 1024);
     hipLaunchKernelGGL(zero_words_kernel, dim3(grid), dim3(256), 0, s, flags, nflags, ticket);
