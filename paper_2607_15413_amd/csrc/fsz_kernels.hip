@@ -128,19 +128,29 @@ __device__ __forceinline__ void lds_barrier()
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Global-memory views of the hot loads and stores.  Pointers that come out of
+// a job table (the batched forms) carry no address space, and the compiler
+// accesses them with FLAT instructions, whose waits also cover LDS traffic;
+// accesses through these types are plain global loads and stores.
+typedef __attribute__((address_space(1))) uint8_t g_u8;
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) float g_f32;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+
 // Store of nw dwords from a wave's LDS staging area to global memory at a
 // 4-byte aligned address g, by the whole wave: 4-byte stores up to the first
 // 16-byte boundary of g and after the last one, 16-byte stores in between (a
 // quarter of the store instructions of a dword-wide copy).
-__device__ __forceinline__ void wave_store_staged(uint32_t *g, const uint32_t *st, uint32_t nw, int lane)
+__device__ __forceinline__ void wave_store_staged(uint32_t *gp, const uint32_t *st, uint32_t nw, int lane)
 {
-    const uint32_t head = min(nw, ((16u - ((uint32_t)(uintptr_t)g & 15u)) & 15u) >> 2);
+    g_u32 *g = (g_u32 *)gp;
+    const uint32_t head = min(nw, ((16u - ((uint32_t)(uintptr_t)gp & 15u)) & 15u) >> 2);
     if ((uint32_t)lane < head) g[lane] = st[lane];
     const uint32_t nq = (nw - head) >> 2;
     for (uint32_t q = lane; q < nq; q += 64) {
         const uint32_t o = head + 4 * q;
         const u32x4 v = {st[o], st[o + 1], st[o + 2], st[o + 3]};
-        *reinterpret_cast<u32x4 *>(g + o) = v;
+        *reinterpret_cast<g_u32x4 *>(g + o) = v;
     }
     const uint32_t t0 = head + 4 * nq;
     if ((uint32_t)lane < nw - t0) g[t0 + lane] = st[t0 + lane];
@@ -150,14 +160,15 @@ __device__ __forceinline__ void wave_store_staged(uint32_t *g, const uint32_t *s
 // phase as g (st + head is 16-byte aligned): the body is read with one
 // 16-byte LDS read per lane (consecutive lanes, consecutive 16 bytes), free of
 // bank conflicts.
-__device__ __forceinline__ void wave_store_staged_phased(uint32_t *g, const uint32_t *st, uint32_t nw, int lane)
+__device__ __forceinline__ void wave_store_staged_phased(uint32_t *gp, const uint32_t *st, uint32_t nw, int lane)
 {
-    const uint32_t head = min(nw, ((16u - ((uint32_t)(uintptr_t)g & 15u)) & 15u) >> 2);
+    g_u32 *g = (g_u32 *)gp;
+    const uint32_t head = min(nw, ((16u - ((uint32_t)(uintptr_t)gp & 15u)) & 15u) >> 2);
     if ((uint32_t)lane < head) g[lane] = st[lane];
     const uint32_t nq = (nw - head) >> 2;
     for (uint32_t q = lane; q < nq; q += 64) {
         const uint32_t o = head + 4 * q;
-        *reinterpret_cast<u32x4 *>(g + o) = *reinterpret_cast<const u32x4 *>(st + o);
+        *reinterpret_cast<g_u32x4 *>(g + o) = *reinterpret_cast<const u32x4 *>(st + o);
     }
     const uint32_t t0 = head + 4 * nq;
     if ((uint32_t)lane < nw - t0) g[t0 + lane] = st[t0 + lane];
@@ -928,7 +939,7 @@ __device__ __forceinline__ ChunkState compress_rates(const CompressArgs &a, cons
     cs.r = j == 0 ? (uint32_t)(dec & 31) : (cs.order2 ? r2 : r1);
     cs.rbyte = j == 0 ? (uint32_t)(dec & 0xFF) : cs.r;
     }
-    if (!DEFER && cnt > 0) a.out[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)cs.rbyte;
+    if (!DEFER && cnt > 0) ((g_u8 *)a.out)[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)cs.rbyte;
     const uint32_t S = block_bytes(cs.r);
 
     // ---- offsets inside the wave / chunk, aggregate for the lookback
@@ -1248,7 +1259,7 @@ __device__ __forceinline__ ChunkState naive_select(const CompressArgs &a, const 
     cs.cent = best >> 1;
     cs.r = r;
     cs.rbyte = j == 0 ? (r | (uint32_t)cs.order2 << 7 | (uint32_t)cs.cent << 6) : r;
-    if (cnt > 0) a.out[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)cs.rbyte;
+    if (cnt > 0) ((g_u8 *)a.out)[kHeaderBytes + tile * kBlocksPerTile + j] = (uint8_t)cs.rbyte;
     const uint32_t S = block_bytes(cs.r);
     const int incl = wave_incl_scan(j == 0 ? (int)Z : 0);
     cs.tile_excl = (uint32_t)incl - Z;
@@ -1490,7 +1501,7 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
         chunk_fetch<W>(a, D, qb, w, lane);
     }
     if (ca.vm != 0)
-        a.out[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
+        ((g_u8 *)a.out)[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
     if (ok) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1605,7 +1616,7 @@ __device__ __forceinline__ uint32_t dec_rate_byte(const DecompressArgs &a, uint6
     const bool tile_ok = tile < (RANGE ? a.tile_end : a.ntiles);
     const uint64_t gblock = tile * kBlocksPerTile + (lane & 7);
     const bool blk_ok = (RANGE ? tile_ok : true) && gblock < a.nblocks;
-    return blk_ok ? a.cmp[kHeaderBytes + gblock] : 0u;
+    return blk_ok ? ((const g_u8 *)a.cmp)[kHeaderBytes + gblock] : 0u;
 }
 
 // rb: the lane's rate byte from dec_rate_byte (loaded ahead by the caller).
@@ -1743,14 +1754,14 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     const bool blk_ok = gblock < a.nblocks;
     const uint8_t *wave_data = p.wave_data;
     int mu = 0;
-    if (d.cent) mu = (int)*reinterpret_cast<const uint32_t *>(wave_data + d.tile_excl);
+    if (d.cent) mu = (int)*(const g_u32 *)(wave_data + d.tile_excl);
 
     // ---- bit-unshuffle: stored words -> residual codes
     uint32_t code[32];
 #pragma unroll
     for (int i = 0; i < 32; i++) code[i] = 0;
     const uint32_t nwords = (blk_ok && d.r) ? d.r + 1 : 0;
-    const uint32_t *words = reinterpret_cast<const uint32_t *>(wave_data + d.blk_off);
+    const g_u32 *words = (const g_u32 *)(wave_data + d.blk_off);
     for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
         uint32_t Rg[8];
 #pragma unroll
@@ -1801,17 +1812,20 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
 
     const uint64_t eblk = gblock * kBlock;
     const int cnt = eblk >= a.n ? 0 : (a.n - eblk >= kBlock ? kBlock : (int)(a.n - eblk));
-    // element e of the field goes to a.out[e - eb], for eb <= e < ee
+    // element e of the field goes to out[e - eb], for eb <= e < ee
+    g_f32 *out = (g_f32 *)a.out;
     const uint64_t eb = RANGE ? a.elem_begin : 0, ee = RANGE ? a.elem_end : a.n;
     if (!STAGED) {  // lane-per-block stores, 8 x 16 B per lane
         if (ALIGNED && cnt == 32 && eblk >= eb && eblk + 32 <= ee) {
-            f4 *p = reinterpret_cast<f4 *>(a.out + (eblk - eb));
+            g_u32x4 *p = (g_u32x4 *)(out + (eblk - eb));
 #pragma unroll
-            for (int k = 0; k < 8; k++) p[k] = f4{xo[4 * k], xo[4 * k + 1], xo[4 * k + 2], xo[4 * k + 3]};
+            for (int k = 0; k < 8; k++)
+                p[k] = u32x4{__float_as_uint(xo[4 * k]), __float_as_uint(xo[4 * k + 1]), __float_as_uint(xo[4 * k + 2]),
+                             __float_as_uint(xo[4 * k + 3])};
         } else {
 #pragma unroll
             for (int i = 0; i < 32; i++)
-                if (i < cnt && eblk + i >= eb && eblk + i < ee) a.out[eblk + i - eb] = xo[i];
+                if (i < cnt && eblk + i >= eb && eblk + i < ee) out[eblk + i - eb] = xo[i];
         }
         return;
     }
@@ -1829,14 +1843,14 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
         for (int k = 0; k < 8; k++) {
             const int p = k * 64 + lane;
             const uint64_t e = e0 + 4ull * p;
-            const f4 f = *reinterpret_cast<const f4 *>(st + (p >> 3) * kStageRowDwords + (p & 7) * 4);
+            const u32x4 f = *reinterpret_cast<const u32x4 *>(st + (p >> 3) * kStageRowDwords + (p & 7) * 4);
             if (fullw || (e >= eb && e + 4 <= ee)) {
-                __builtin_nontemporal_store(f, reinterpret_cast<f4 *>(a.out + (e - eb)));
+                __builtin_nontemporal_store(f, (g_u32x4 *)(out + (e - eb)));
             } else {
-                if (e + 0 >= eb && e + 0 < ee) a.out[e + 0 - eb] = f.x;
-                if (e + 1 >= eb && e + 1 < ee) a.out[e + 1 - eb] = f.y;
-                if (e + 2 >= eb && e + 2 < ee) a.out[e + 2 - eb] = f.z;
-                if (e + 3 >= eb && e + 3 < ee) a.out[e + 3 - eb] = f.w;
+                if (e + 0 >= eb && e + 0 < ee) out[e + 0 - eb] = __uint_as_float(f.x);
+                if (e + 1 >= eb && e + 1 < ee) out[e + 1 - eb] = __uint_as_float(f.y);
+                if (e + 2 >= eb && e + 2 < ee) out[e + 2 - eb] = __uint_as_float(f.z);
+                if (e + 3 >= eb && e + 3 < ee) out[e + 3 - eb] = __uint_as_float(f.w);
             }
         }
     } else {
@@ -1845,7 +1859,7 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
             const int p = k * 64 + lane;
             const uint64_t e = e0 + p;
             if (fullw || (e >= eb && e < ee))
-                a.out[e - eb] = __uint_as_float(st[(p >> 5) * kStageRowDwords + (p & 31)]);
+                out[e - eb] = __uint_as_float(st[(p >> 5) * kStageRowDwords + (p & 31)]);
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -2377,8 +2391,9 @@ struct BItem {
 constexpr uint32_t kPipeLdsJobs = 96;
 
 struct JobView {
-    const BatchJob *jobs;  // LDS copy or the global table
-    const Resolved *bound; // LDS (null: resolve from the job's stats)
+    const BatchJob *jobs;       // LDS copy or the global table
+    const Resolved *bound;      // LDS (null: resolve from the job's stats)
+    const uint64_t *chunk_end;  // LDS copy or the global table
 };
 
 __device__ __forceinline__ Resolved job_bound(const BatchArgs &b, const JobView &v, uint32_t job, const BatchJob &J)
@@ -2398,7 +2413,7 @@ __device__ __forceinline__ BItem batch_item(const BatchArgs &b, const JobView &v
 
 __device__ __forceinline__ BItem batch_item_of(const BatchArgs &b, const JobView &v, uint64_t t)
 {
-    const uint32_t job = t < b.total_chunks ? __builtin_amdgcn_readfirstlane(find_job(b.chunk_end, b.njobs, t))
+    const uint32_t job = t < b.total_chunks ? __builtin_amdgcn_readfirstlane(find_job(v.chunk_end, b.njobs, t))
                                             : b.njobs;
     return batch_item(b, v, t, job);
 }
@@ -2465,22 +2480,16 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, const JobVi
         chunk_total += sh.wave_total[sa][k];
     }
     if (W0) {
+        // lookback first (as in the single-field pipeline), then the new
+        // ticket and its job, found in the LDS copy of the job ends
+        Prefix pre{0, false};
+        consume_probe(probe);
+        if (liveA) pre = lookback_wait(aA.flags, iA.c, aA.flag_epoch, chunk_total, false, true, probe);
         const unsigned long long tk =
             take ? ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(traw >> 32)) << 32) |
                        (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)traw)
                  : N;
-        // the new item's job: the first window of job ends is loaded before
-        // the lookback waits, so its latency hides behind them
-        const uint32_t nj = b.njobs;
-        const uint64_t jend = tk < N ? b.chunk_end[min((uint32_t)lane, nj - 1)] : 0;
-        Prefix pre{0, false};
-        consume_probe(probe);
-        if (liveA) pre = lookback_wait(aA.flags, iA.c, aA.flag_epoch, chunk_total, false, true, probe);
-        uint32_t jobD = nj;
-        if (tk < N) {
-            const unsigned long long m = __ballot((uint32_t)lane < nj && jend <= tk);
-            jobD = m != ~0ull ? (uint32_t)__builtin_popcountll(m) : find_job(b.chunk_end, nj, tk);
-        }
+        const uint32_t jobD = tk < N ? find_job(v.chunk_end, b.njobs, tk) : b.njobs;
         if (lane == 0) {
             if (take && tk == takes - 1)
                 __hip_atomic_store(b.ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2510,7 +2519,7 @@ __device__ __forceinline__ BItem batch_pipe_step(const BatchArgs &b, const JobVi
         batch_fetch<W>(b, v, iD, qb, w, lane);
     }
     if (liveA && ca.vm != 0)
-        aA.out[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
+        ((g_u8 *)aA.out)[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
     if (ok) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -2562,34 +2571,44 @@ __device__ __forceinline__ void batch_pipe_run(const BatchArgs &b, const JobView
     }
 }
 
-template <int W>
+// LDSJOBS (njobs <= kPipeLdsJobs): the job records, their resolved bounds
+// and chunk ends are copied to LDS at the start; the view's address space is
+// then fixed at compile time, so job fields are read with LDS instructions.
+template <int W, bool LDSJOBS>
 __global__ __launch_bounds__(W * 64) void batch_pipe_kernel(BatchArgs b)
 {
     __shared__ CompressShared<W> sh;
     __shared__ uint32_t s_job;
     __shared__ __attribute__((aligned(16))) uint32_t inbuf[W * kPipeWaveDwords];
     __shared__ __attribute__((aligned(16))) uint32_t stbuf[W * kPipeWaveDwords];
-    __shared__ __attribute__((aligned(16))) BatchJob ljobs[kPipeLdsJobs];
-    __shared__ Resolved lbound[kPipeLdsJobs];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     uint32_t *qb = inbuf + w * kPipeWaveDwords;
     uint32_t *pb = stbuf + w * kPipeWaveDwords;
-    JobView v{b.jobs, nullptr};
-    if (b.njobs <= kPipeLdsJobs) {  // job records and resolved bounds to LDS
+    if (LDSJOBS) {
+        __shared__ __attribute__((aligned(16))) BatchJob ljobs[kPipeLdsJobs];
+        __shared__ Resolved lbound[kPipeLdsJobs];
+        __shared__ uint64_t lend[kPipeLdsJobs];
         for (uint32_t k = threadIdx.x; k < b.njobs * (uint32_t)(sizeof(BatchJob) / 16); k += blockDim.x)
             reinterpret_cast<u32x4 *>(ljobs)[k] = reinterpret_cast<const u32x4 *>(b.jobs)[k];
         for (uint32_t k = threadIdx.x; k < b.njobs; k += blockDim.x) {
             const BatchJob &J = b.jobs[k];
             lbound[k] = J.op == FSZ_OP_COMPRESS ? resolve_bound(b.stats + k, J.mode, J.value, J.n)
                                                 : Resolved{1.0f, 1.0f, 0u, FSZ_ERR_INVALID_ARG};
+            lend[k] = b.chunk_end[k];
         }
-        v = JobView{ljobs, lbound};
         lds_barrier();
+        const JobView v{ljobs, lbound, lend};
+        if (w == 0)
+            batch_pipe_run<true, W>(b, v, sh, s_job, qb, pb, w);
+        else if (W > 1)
+            batch_pipe_run<false, W>(b, v, sh, s_job, qb, pb, w);
+    } else {
+        const JobView v{b.jobs, nullptr, b.chunk_end};
+        if (w == 0)
+            batch_pipe_run<true, W>(b, v, sh, s_job, qb, pb, w);
+        else if (W > 1)
+            batch_pipe_run<false, W>(b, v, sh, s_job, qb, pb, w);
     }
-    if (w == 0)
-        batch_pipe_run<true, W>(b, v, sh, s_job, qb, pb, w);
-    else if (W > 1)
-        batch_pipe_run<false, W>(b, v, sh, s_job, qb, pb, w);
 }
 
 // ------------------------------------------------------------------ tile configurations
@@ -2753,7 +2772,7 @@ __global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressAr
     }
     const int order2 = best & 1, cent = best >> 1;
     if (h == 0 && cnt > 0)  // the block's rate byte (Sec. III-A)
-        a.out[kHeaderBytes + seg / HB] = (uint8_t)(first ? (r | (uint32_t)order2 << 7 | (uint32_t)cent << 6) : r);
+        ((g_u8 *)a.out)[kHeaderBytes + seg / HB] = (uint8_t)(first ? (r | (uint32_t)order2 << 7 | (uint32_t)cent << 6) : r);
 
     // ---- offsets: the lane's block inside the tile, the tile inside the wave
     const uint32_t S = block_bytes(r);  // this lane's words: 4 (1 + r) bytes
@@ -3250,6 +3269,31 @@ static bool batch_lds_pad(K kernel, int groups, size_t *pad)
     return true;
 }
 
+template <int W, bool LDSJOBS>
+static hipError_t launch_batch_pipe(const BatchArgs &b, int groups, hipStream_t s)
+{
+    size_t pad = 0;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_pipe_kernel<W, LDSJOBS>, W * 64, 0) !=
+            hipSuccess ||
+        cus <= 0 || per_cu <= 0) {
+        cus = 256;
+        per_cu = 1;
+    }
+    if (groups > 0 && groups < per_cu) {  // the cap is a hint: dropped where no pad can set it
+        if (batch_lds_pad(batch_pipe_kernel<W, LDSJOBS>, groups, &pad))
+            per_cu = groups;
+        else
+            pad = 0;
+    }
+    const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
+    const unsigned grid = (unsigned)(b.total_chunks < g ? b.total_chunks : g);
+    hipLaunchKernelGGL((batch_pipe_kernel<W, LDSJOBS>), dim3(grid), dim3(W * 64), pad, s, b);
+    return hipGetLastError();
+}
+
 template <bool ALIGNED, int W>
 static hipError_t launch_batch_t(const BatchArgs &b, bool any_compress, bool any_decompress, int groups,
                                  hipStream_t s)
@@ -3258,24 +3302,8 @@ static hipError_t launch_batch_t(const BatchArgs &b, bool any_compress, bool any
     if (ALIGNED && any_compress && !any_decompress) {
         // compression only, 16-byte aligned inputs: the persistent pipeline,
         // one workgroup per CU at most (its LDS); a cap of 1 needs no pad
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_pipe_kernel<W>, W * 64, 0) != hipSuccess ||
-            cus <= 0 || per_cu <= 0) {
-            cus = 256;
-            per_cu = 1;
-        }
-        if (groups > 0 && groups < per_cu) {  // the cap is a hint: dropped where no pad can set it
-            if (batch_lds_pad(batch_pipe_kernel<W>, groups, &pad))
-                per_cu = groups;
-            else
-                pad = 0;
-        }
-        const uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
-        const unsigned grid = (unsigned)(b.total_chunks < g ? b.total_chunks : g);
-        hipLaunchKernelGGL((batch_pipe_kernel<W>), dim3(grid), dim3(W * 64), pad, s, b);
-        return hipGetLastError();
+        return b.njobs <= kPipeLdsJobs ? launch_batch_pipe<W, true>(b, groups, s)
+                                       : launch_batch_pipe<W, false>(b, groups, s);
     }
     if (any_compress) {
         if (!batch_lds_pad(batch_kernel<ALIGNED, W>, groups, &pad)) return hipErrorInvalidValue;
