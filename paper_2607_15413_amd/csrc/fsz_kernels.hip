@@ -185,6 +185,7 @@ __device__ __forceinline__ uint32_t block_bytes(uint32_t r) { return r ? 4u + 4u
 __device__ __forceinline__ uint32_t bswap32(uint32_t v) { return __builtin_bswap32(v); }
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f4 g_f4;  // global-memory view (see g_u32)
 
 // ------------------------------------------------------------------ bit planes
 //
@@ -2144,13 +2145,13 @@ __global__ __launch_bounds__(kStatsThreads) void batch_stats_kernel(BatchArgs b)
         const uint32_t job = __builtin_amdgcn_readfirstlane(find_job(b.seg_end, b.njobs, seg));
         if (job >= b.njobs) return;
         const BatchJob &J = b.jobs[job];
-        const float *x = static_cast<const float *>(J.src);
+        const g_f32 *x = (const g_f32 *)J.src;
         const uint64_t e0 = (seg - J.seg_base) * kSegElems;
         const uint64_t e1 = J.n - e0 < (uint64_t)kSegElems ? J.n : e0 + kSegElems;
         RangeAcc acc;
         const int tid = threadIdx.x;
         if (ALIGNED) {  // 16-byte loads, four in flight per thread; a ragged segment's last 0-3 elements singly
-            const f4 *x4 = reinterpret_cast<const f4 *>(x + e0);
+            const g_f4 *x4 = (const g_f4 *)(x + e0);
             const uint32_t nv = (uint32_t)((e1 - e0) / 4);
             if (nv == kSegElems / 4) {
 #pragma unroll 2
@@ -2176,7 +2177,7 @@ __global__ __launch_bounds__(kStatsThreads) void batch_stats_kernel(BatchArgs b)
                     acc.take4(f2);
                     acc.take4(f3);
                 }
-                for (; k < nv; k += kStatsThreads) acc.take4(x4[k]);
+                for (; k < nv; k += kStatsThreads) acc.take4(f4(x4[k]));
                 const uint64_t t = e0 + 4ull * nv + tid;
                 if (t < e1) acc.take(x[t]);
             }
