@@ -1064,7 +1064,13 @@ def main():
 
     dominant = "compress" if comp_time >= dec_time else "decompress"
     # kernel names as rocprofv3 reports them (torch allocations are 16-byte aligned)
-    comp_kernel = "compress_pipe2_kernel" if os.environ.get("FSZ_PIPE", "1") != "0" else "compress_kernel"
+    waves = os.environ.get("FSZ_PIPE_WAVES", "9")
+    if os.environ.get("FSZ_PIPE", "1") == "0":
+        comp_kernel = "compress_kernel"
+    elif waves in ("7", "9"):
+        comp_kernel = "compress_ctrl_kernel"
+    else:
+        comp_kernel = "compress_pipe2_kernel"
     dom_kernel = comp_kernel if dominant == "compress" else "decompress_kernel"
     dom_bytes, dom_time = (comp_bytes, comp_time) if dominant == "compress" else (dec_bytes, dec_time)
     achieved = dom_bytes / dom_time / 1e6  # GB/s

@@ -30,7 +30,7 @@ const Tuning &tuning()
         if (const char *e = std::getenv("FSZ_PIPE")) v.pipe_compress = std::atoi(e) != 0;
         if (const char *e = std::getenv("FSZ_PIPE_WAVES")) {
             const int k = std::atoi(e);
-            if (k == 1 || k == 2 || k == 4 || k == 8) v.pipe_waves = k;
+            if (k == 1 || k == 2 || k == 4 || k == 7 || k == 8 || k == 9) v.pipe_waves = k;  // 7, 9: + 1 control wave
         }
         if (const char *e = std::getenv("FSZ_DEC_WAVES")) {
             const int k = std::atoi(e);

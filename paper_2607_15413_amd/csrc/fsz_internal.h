@@ -233,7 +233,8 @@ struct Tuning {
     bool staged_decompress = true;
     bool staged_compress_loads = true;
     bool pipe_compress = true;  // persistent compression with asynchronous LDS prefetch
-    int pipe_waves = 8;         // waves per workgroup of the pipelined compression (1, 2, 4, 8)
+    int pipe_waves = 9;         // pipelined compression: data waves per workgroup (1, 2, 4, 8), or 9 / 7:
+                                // 8 / 7 data waves and a control wave (compress_ctrl_kernel)
     int dec_waves = 8;          // waves per workgroup of the decompression (4, 8, 16)
     int grid_factor = 1;
     double prezero_min_cr = 0.0;  // whole-field decodes pre-zero above this CR (0: never)

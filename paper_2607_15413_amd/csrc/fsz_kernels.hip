@@ -1554,6 +1554,88 @@ __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved 
     }
 }
 
+// The control wave of compress_ctrl_kernel: wave 0's part of the pipeline
+// without its data.  Per step it takes the ticket and walks the lookback of
+// the chunk rate-passed in the previous step while the data waves run the
+// next rate pass, so the offset is usually known when they reach the second
+// barrier; its own memory queue holds only flag reads, so they are not
+// queued behind copies and stores.  It passes every barrier the data waves
+// pass (pipe2_run<false, WD>): the ticket broadcasts, the rate pass's, and
+// the step's second one.
+template <int WD>
+__device__ __forceinline__ uint64_t ctrl_step(const CompressArgs &a, const Resolved &R, uint64_t takes,
+                                              uint64_t A, int sa, uint64_t B, uint64_t C, CompressShared<WD> &sh)
+{
+    const uint64_t N = a.nchunks;
+    const int lane = __lane_id();
+    const bool take = C < N;
+    unsigned long long traw = 0;
+    if (take && lane == 0) traw = atomicAdd(a.ticket, 1ull);
+    uint32_t chunk_total = 0;
+#pragma unroll
+    for (int k = 0; k < WD; k++) chunk_total += sh.wave_total[sa][k];  // A's, from the previous step
+    const Prefix pre = lookback_wait(a.flags, A, a.flag_epoch, chunk_total, false);
+    if (B < N) lds_barrier();  // the data waves' rate pass of B
+    const unsigned long long tk =
+        take ? ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(traw >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)traw)
+             : N;
+    if (lane == 0) {
+        if (take && tk == takes - 1) __hip_atomic_store(a.ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh.base = pre.excl;
+        sh.ticket[0] = tk;
+        if (A == N - 1) finish_stream(a, R, pre, chunk_total);
+    }
+    lds_barrier();  // the offset and the ticket go out
+    return tk;
+}
+
+template <int WD>
+__device__ __forceinline__ void ctrl_run(const CompressArgs &a, const Resolved &R, CompressShared<WD> &sh)
+{
+    const uint64_t N = a.nchunks;
+    const uint64_t takes = N + gridDim.x;
+    int tslot = 0;
+    uint64_t A = next_ticket(a.ticket, takes, sh, tslot);
+    if (A >= N) return;
+    uint64_t B = next_ticket(a.ticket, takes, sh, tslot);
+    lds_barrier();  // the rate pass of A
+    uint64_t C = N;
+    if (B < N) C = next_ticket(a.ticket, takes, sh, tslot);
+    for (int sa = 0;; sa ^= 1) {
+        const uint64_t D = ctrl_step<WD>(a, R, takes, A, sa, B, C, sh);
+        if (B >= N) return;
+        A = B;
+        B = C;
+        C = D;
+    }
+}
+
+// The pipelined compressor with WD data waves (8 tiles each per chunk) and
+// one control wave (ctrl_run).  a.nchunks must count chunks of 8 WD tiles.
+template <int WD>
+__global__ __launch_bounds__((WD + 1) * 64) void compress_ctrl_kernel(CompressArgs a)
+{
+    __shared__ CompressShared<WD> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t inbuf[WD * kPipeWaveDwords];
+    __shared__ __attribute__((aligned(16))) uint32_t stbuf[WD * kPipeWaveDwords];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status != FSZ_OK) {  // no data work: hand out the tickets, the last chunk reports
+        const uint64_t takes = a.nchunks + gridDim.x;
+        int tslot = 0;
+        for (;;) {
+            const uint64_t t = next_ticket(a.ticket, takes, sh, tslot);
+            if (t >= a.nchunks) return;
+            if (threadIdx.x == 0 && t == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
+        }
+    }
+    if (w < WD)
+        pipe2_run<false, WD, false>(a, R, sh, inbuf + w * kPipeWaveDwords, stbuf + w * kPipeWaveDwords, w);
+    else
+        ctrl_run<WD>(a, R, sh);
+}
+
 // W waves per workgroup; a chunk is 8 tiles per wave.  a.nchunks must count
 // chunks of that size.  FEAT: honour the feature switches in a.features.
 template <int W, bool FEAT = false>
@@ -3122,7 +3204,21 @@ hipError_t launch_compress(const CompressArgs &a, bool in_aligned16, bool staged
         CompressArgs p = a;
         const int W = tuning().pipe_waves;
         p.nchunks = p.ntiles ? ceil_div(p.ntiles, (uint64_t)kTilesPerWave * W) : 1;
+        if (W == 7) p.nchunks = p.ntiles ? ceil_div(p.ntiles, (uint64_t)kTilesPerWave * 7) : 1;
+        if (W == 9) p.nchunks = p.ntiles ? ceil_div(p.ntiles, (uint64_t)kTilesPerWave * 8) : 1;
         switch (W) {
+        case 7: {  // 7 data waves + 1 control wave
+            static const unsigned cap = persistent_grid(compress_ctrl_kernel<7>, ~0ull, 512);
+            hipLaunchKernelGGL(compress_ctrl_kernel<7>, dim3((unsigned)(p.nchunks < cap ? p.nchunks : cap)),
+                               dim3(512), 0, s, p);
+            break;
+        }
+        case 9: {  // 8 data waves + 1 control wave
+            static const unsigned cap = persistent_grid(compress_ctrl_kernel<8>, ~0ull, 576);
+            hipLaunchKernelGGL(compress_ctrl_kernel<8>, dim3((unsigned)(p.nchunks < cap ? p.nchunks : cap)),
+                               dim3(576), 0, s, p);
+            break;
+        }
         case 1: {
             static const unsigned cap = persistent_grid(compress_pipe2_kernel<1>, ~0ull, 64);
             hipLaunchKernelGGL(compress_pipe2_kernel<1>, dim3((unsigned)(p.nchunks < cap ? p.nchunks : cap)),
