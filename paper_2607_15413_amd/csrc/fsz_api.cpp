@@ -354,7 +354,9 @@ fsz_status enqueue_compress_config(Workspace *ws, const float *d_in, uint64_t n,
     a.mode = mode;
     a.features = kFeaturesAll;
     a.cfg_flags = cfg_flag_bits(block, tile_blocks);
-    if (!ensure_flags(ws, a.nchunks)) return FSZ_ERR_DEVICE;
+    // flags for the generic kernel's chunks or the pipelined one's (smaller)
+    if (!ensure_flags(ws, std::max<uint64_t>(a.nchunks, ceil_div(ceil_div(n, kBlock), kCfgPipeChunkSegs))))
+        return FSZ_ERR_DEVICE;
     if (!next_epoch(ws, &a.epoch, &a.flag_epoch)) return FSZ_ERR_DEVICE;
     a.flags = ws->d_flags;
     a.ticket = ws->d_ticket;

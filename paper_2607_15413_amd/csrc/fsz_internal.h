@@ -173,12 +173,15 @@ hipError_t launch_decompress_prescan(const DecompressArgs &a, unsigned long long
 // the decoder that skips waves whose tiles are all zero.
 hipError_t launch_decompress_prezero(const DecompressArgs &a, bool out_aligned16, hipStream_t s);
 // Tile configurations (Sec. VI-C): one chunk of kCfgWaves x 64 32-element segments per
-// workgroup (a.nchunks counts those), block in {32, 64}, tile_blocks in {4, 8, 16}.
+// workgroup (a.nchunks counts those), block in {32, 64}, tile_blocks in {4, 8, 16}.  A
+// 16-byte aligned input runs the pipelined compressor instead, whose chunks of
+// kCfgPipeChunkSegs segments the launch counts itself (the flags must cover them).
 hipError_t launch_compress_cfg(const CompressArgs &a, int block, int tile_blocks, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
                                  hipStream_t s);
 constexpr int kCfgWaves = 16;
 constexpr int kCfgChunkSegs = kCfgWaves * 64;
+constexpr int kCfgPipeChunkSegs = 8 * 64;  // the pipelined configuration compressor's chunk
 // header flags bits 2-4 of a tile configuration (0 for B 32, T 8)
 inline uint32_t cfg_flag_bits(int block, int tile_blocks)
 {

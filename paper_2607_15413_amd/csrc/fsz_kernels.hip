@@ -1460,20 +1460,50 @@ __device__ __forceinline__ void pipe2_stage(const ChunkState &cs, int (&B)[32], 
     }
 }
 
+// The tile geometry a compression pipeline runs: its rate pass (one
+// workgroup barrier), its staging of the codes, whether a wave's first tile
+// exists, and where a lane's rate byte goes.  TileB32T8 is the default format
+// (blocks of 32 elements, tiles of 8 blocks); the tile-configuration sweep
+// has its own.
+struct TileB32T8 {
+    template <int W, bool FEAT>
+    static __device__ __forceinline__ ChunkState rates(const CompressArgs &a, const Resolved &R, uint64_t chunk,
+                                                       int (&x)[32], int slot, CompressShared<W> &sh)
+    {
+        return compress_rates<W, true, FEAT>(a, R, chunk, x, slot, sh);
+    }
+    template <bool FEAT>
+    static __device__ __forceinline__ void stage(const ChunkState &cs, int (&B)[32], uint32_t *st)
+    {
+        pipe2_stage<FEAT>(cs, B, st);
+    }
+    template <int W>
+    static __device__ __forceinline__ bool wave_live(const CompressArgs &a, uint64_t chunk, int w)
+    {
+        return chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave < a.ntiles;
+    }
+    template <int W>
+    static __device__ __forceinline__ void store_rate(const CompressArgs &a, const ChunkState &cs, int w, int lane)
+    {
+        const uint64_t tile0 = cs.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
+        if (cs.vm != 0)
+            ((g_u8 *)a.out)[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + (lane & 7)] = (uint8_t)cs.rbyte;
+    }
+};
+
 // One step with chunk A rate-passed (registers xa, wave totals in slot sa),
 // chunk B read (registers yb) and chunk C being copied into qb: rate pass of
 // B, lookback + staging of A, read C into xa, start the copy of the ticket
 // taken in this step, store A.  Returns that ticket (nchunks if none).
 // W0: the calling wave is wave 0, which takes the ticket and reads the
 // lookback window at the start and uses both after the rate pass.
-template <bool W0, int W, bool FEAT>
+template <bool W0, int W, bool FEAT, class M = TileB32T8>
 __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Resolved &R, uint64_t takes,
                                                const ChunkState &ca, int (&xa)[32], int sa, uint64_t B,
                                                int (&yb)[32], ChunkState &cb, uint64_t C, uint32_t *qb,
                                                uint32_t *pb, CompressShared<W> &sh, int w)
 {
     const int lane = threadIdx.x & 63;
-    const int j = lane & 7;
     const bool take = C < a.nchunks;
     unsigned long long traw = 0;
     Probe probe{};
@@ -1481,7 +1511,7 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
         if (take && lane == 0) traw = atomicAdd(a.ticket, 1ull);
         probe = lookback_probe(a.flags, ca.chunk, a.flag_epoch);
     }
-    if (B < a.nchunks) cb = compress_rates<W, true, FEAT>(a, R, B, yb, sa ^ 1, sh);
+    if (B < a.nchunks) cb = M::template rates<W, FEAT>(a, R, B, yb, sa ^ 1, sh);
     uint64_t D;
     const uint64_t base = pipe2_lookback<W0, W>(a, R, ca, sa, sh, probe, take, traw, takes, &D);
 
@@ -1491,18 +1521,16 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
         if (k < w) wave_base += sh.wave_total[sa][k];
         chunk_total += sh.wave_total[sa][k];
     }
-    const uint64_t tile0 = ca.chunk * (kTilesPerWave * W) + (uint64_t)w * kTilesPerWave;
-    const bool ok = a.data0 + base + chunk_total <= a.capacity && tile0 < a.ntiles;
+    const bool ok = a.data0 + base + chunk_total <= a.capacity && M::template wave_live<W>(a, ca.chunk, w);
     uint32_t *wave_out = reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base);
     uint32_t *ps = pb + (((uint32_t)(uintptr_t)wave_out >> 2) & 3u);  // staging at the output's 16-byte phase
-    if (ok) pipe2_stage<FEAT>(ca, xa, ps);
+    if (ok) M::template stage<FEAT>(ca, xa, ps);
     if (C < a.nchunks) chunk_read(qb, lane, xa);
     if (D < a.nchunks) {
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the read of qb is done before it is overwritten
         chunk_fetch<W>(a, D, qb, w, lane);
     }
-    if (ca.vm != 0)
-        ((g_u8 *)a.out)[kHeaderBytes + (tile0 + (lane >> 3)) * kBlocksPerTile + j] = (uint8_t)ca.rbyte;
+    M::template store_rate<W>(a, ca, w, lane);
     if (ok) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1514,7 +1542,7 @@ __device__ __forceinline__ uint64_t pipe2_step(const CompressArgs &a, const Reso
 }
 
 // The whole pipeline of one wave (W0: wave 0's role), from the first ticket on.
-template <bool W0, int W, bool FEAT>
+template <bool W0, int W, bool FEAT, class M = TileB32T8>
 __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved &R, CompressShared<W> &sh,
                                           uint32_t *qb, uint32_t *pb, int w)
 {
@@ -1532,7 +1560,7 @@ __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved 
         __builtin_amdgcn_s_waitcnt(0xC07F);
         chunk_fetch<W>(a, B, qb, w, lane);
     }
-    ChunkState ca = compress_rates<W, true, FEAT>(a, R, A, x, 0, sh);
+    ChunkState ca = M::template rates<W, FEAT>(a, R, A, x, 0, sh);
     ChunkState cb = ca;
     uint64_t C = N;
     if (B < N) {
@@ -1545,9 +1573,9 @@ __device__ __forceinline__ void pipe2_run(const CompressArgs &a, const Resolved 
     }
     // loop invariant: A rate-passed in x (slot 0), B read into y, C in flight
     for (;;) {
-        const uint64_t D = pipe2_step<W0, W, FEAT>(a, R, takes, ca, x, 0, B, y, cb, C, qb, pb, sh, w);
+        const uint64_t D = pipe2_step<W0, W, FEAT, M>(a, R, takes, ca, x, 0, B, y, cb, C, qb, pb, sh, w);
         if (B >= N) return;
-        const uint64_t E = pipe2_step<W0, W, FEAT>(a, R, takes, cb, y, 1, C, x, ca, D, qb, pb, sh, w);
+        const uint64_t E = pipe2_step<W0, W, FEAT, M>(a, R, takes, cb, y, 1, C, x, ca, D, qb, pb, sh, w);
         if (C >= N) return;
         B = D;
         C = E;
@@ -2734,6 +2762,216 @@ __device__ __forceinline__ uint32_t lane_run_incl_scan(uint32_t v, int pos, int 
     return v;
 }
 
+// Rate pass of one chunk of W waves in a tile configuration (the pipelined
+// counterpart of compress_cfg_kernel's first half, for TileCfg): tile mean,
+// quantization, cross-block extrema, four-way evaluation and selection, and
+// the offsets of the lane's words inside its wave (blk_off, with the lane's
+// half h of a 64-element block at byte 4 h).  One workgroup barrier; wave 1
+// publishes the chunk's aggregate.  On return x holds the LZ1 residuals.
+template <int HB, int L, int W>
+__device__ __forceinline__ ChunkState cfg_rates(const CompressArgs &a, const Resolved &R, uint64_t chunk,
+                                                int (&x)[32], int slot, CompressShared<W> &sh)
+{
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int tl = lane % L;  // lane inside the tile
+    const int h = tl % HB;    // half of a 64-element block
+    const uint64_t seg0 = (chunk * W + (uint64_t)w) * 64;  // the wave's first segment
+    const uint64_t seg = seg0 + lane;
+    const uint64_t e0 = seg * 32;
+    const int cnt = e0 >= a.n ? 0 : (a.n - e0 >= 32 ? 32 : (int)(a.n - e0));
+    const bool tile_ok = seg / L < a.ntiles;
+    const bool full = (seg0 + 64) * 32 <= a.n;  // wave-uniform
+    ChunkState cs;
+    cs.chunk = chunk;
+    cs.vm = cnt >= 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u);
+
+    // ---- tile mean: pairwise binary32 tree over the B T slots, times 1/(B T)
+    float s16[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) s16[i] = __int_as_float(x[2 * i]) + __int_as_float(x[2 * i + 1]);
+#pragma unroll
+    for (int i = 0; i < 8; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+#pragma unroll
+    for (int i = 0; i < 4; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+#pragma unroll
+    for (int i = 0; i < 2; i++) s16[i] = s16[2 * i] + s16[2 * i + 1];
+    const float ts = lane_group_sum<L>(s16[0] + s16[1]);
+    const float mean_q = (ts * (1.0f / (float)(32 * L))) * R.inv;
+    const bool centre_ok = __builtin_isfinite(mean_q);
+    const int mu = centre_ok ? (int)__builtin_rintf(mean_q) : 0;
+    cs.mu = mu;
+
+    // ---- quantize (biased), cross-block state from the previous lane of the tile
+#pragma unroll
+    for (int i = 0; i < 32; i++) x[i] = __float_as_int(__int_as_float(x[i]) * R.inv + kQMagic);
+    const int p31 = __shfl_up(x[31], 1);
+    const int p30 = __shfl_up(x[30], 1);
+    const bool first = tl == 0;  // the tile start: the prediction restarts
+    cs.first = first;
+    const int carry_b = first ? kQBias : p31;
+    cs.carry_l1 = first ? 0 : p31 - p30;
+    uint32_t a1, a2;
+    int l2_1;
+    if (full)
+        block_extrema<true>(x, carry_b, cs.carry_l1, first ? 0 : 1, cs.vm, a1, a2, l2_1);
+    else
+        block_extrema<false>(x, carry_b, cs.carry_l1, first ? 0 : 1, cs.vm, a1, a2, l2_1);
+
+    // ---- four-way evaluation (Eq. (3)-(4)) and selection
+    uint32_t m0 = a1, m1 = a2, m2 = a1, m3 = a2;
+    if (first) {
+        const int q0 = x[0];  // d[0] = q[0] at a tile start
+        const int d1 = cnt >= 2 ? l2_1 : 0;  // q1 - 2 q0
+        const int c0 = q0 - mu;
+        const int c1 = cnt >= 2 ? l2_1 + mu : 0;
+        m0 = max(uabs(q0), a1);
+        m1 = max(max(uabs(q0), uabs(d1)), a2);
+        m2 = max(uabs(c0), a1);
+        m3 = max(max(uabs(c0), uabs(c1)), a2);
+    }
+    if (cnt == 0) m0 = m1 = m2 = m3 = 0;  // segments past the end of the field
+    if (HB == 2) {
+        m0 = max(m0, (uint32_t)__shfl_xor((int)m0, 1));
+        m1 = max(m1, (uint32_t)__shfl_xor((int)m1, 1));
+        m2 = max(m2, (uint32_t)__shfl_xor((int)m2, 1));
+        m3 = max(m3, (uint32_t)__shfl_xor((int)m3, 1));
+    }
+    const uint32_t r0 = bitlen(m0), r1 = bitlen(m1), r2 = bitlen(m2), r3 = bitlen(m3);
+    const uint32_t Ca = lane_group_sum<L>(h == 0 ? (uint32_t)HB * block_bytes(r0) : 0u);
+    const uint32_t Cb = lane_group_sum<L>(h == 0 ? (uint32_t)HB * block_bytes(r1) : 0u);
+    const uint32_t Cc = lane_group_sum<L>(h == 0 ? (uint32_t)HB * block_bytes(r2) : 0u) + 4u;
+    const uint32_t Cd = lane_group_sum<L>(h == 0 ? (uint32_t)HB * block_bytes(r3) : 0u) + 4u;
+    int best = 0;
+    uint32_t C = Ca, r = r0;
+    if (Cb < C) {
+        best = 1;
+        C = Cb;
+        r = r1;
+    }
+    if (centre_ok) {
+        if (Cc < C) {
+            best = 2;
+            C = Cc;
+            r = r2;
+        }
+        if (Cd < C) {
+            best = 3;
+            C = Cd;
+            r = r3;
+        }
+    }
+    if (!tile_ok) {
+        best = 0;
+        C = 0;
+        r = 0;
+    }
+    cs.order2 = best & 1;
+    cs.cent = best >> 1;
+    cs.r = r;
+    cs.rbyte = first ? (r | (uint32_t)cs.order2 << 7 | (uint32_t)cs.cent << 6) : r;
+
+    // ---- offsets: the lane's block inside the tile, the tile inside the wave
+    const uint32_t S = block_bytes(r);  // this lane's words: 4 (1 + r) bytes
+    const uint32_t pre = lane_run_incl_scan<L>(S, tl, L) - S;
+    const int incl = wave_incl_scan(first ? (int)C : 0);
+    cs.tile_excl = (uint32_t)incl - C;
+    cs.wave_total = (uint32_t)__builtin_amdgcn_readlane(incl, 63);
+    cs.blk_off = cs.tile_excl + 4u * (uint32_t)cs.cent + pre - (uint32_t)h * S + 4u * (uint32_t)h;
+    if (lane == 0) sh.wave_total[slot][w] = cs.wave_total;
+    lds_barrier();
+    if (tid == (W > 1 ? 64 : 0)) {
+        uint32_t chunk_total = 0;
+#pragma unroll
+        for (int k = 0; k < W; k++) chunk_total += sh.wave_total[slot][k];
+        publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, false);
+    }
+    return cs;
+}
+
+// Residual codes and bit planes of one wave's segments into its staging area
+// (word k of the lane's half h of a block at dword blk_off / 4 + HB k).
+template <int HB>
+__device__ __forceinline__ void cfg_stage(const ChunkState &cs, int (&B)[32], uint32_t *st)
+{
+    if (cs.vm != 0 && cs.first && cs.cent) st[cs.tile_excl >> 2] = (uint32_t)cs.mu;
+    block_codes(B, cs.carry_l1, cs.first ? 0 : 1, cs.order2, cs.cent, cs.mu);
+    const uint32_t keep = __builtin_bswap32(__builtin_bitreverse32(cs.vm));
+    const uint32_t nwords = cs.r ? cs.r + 1 : 0;
+    uint32_t *words = st + (cs.blk_off >> 2);
+    for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
+        uint32_t Rg[8];
+#pragma unroll
+        for (int rho = 0; rho < 8; rho++)
+            Rg[rho] = pack_byte_g((uint32_t)B[7 - rho], (uint32_t)B[15 - rho], (uint32_t)B[23 - rho],
+                                  (uint32_t)B[31 - rho], g);
+        transpose8(Rg);
+#pragma unroll
+        for (int p = 0; p < 8; p++)
+            if (8 * g + p < nwords) words[HB * (8 * g + p)] = Rg[p] & keep;
+    }
+}
+
+// Tile geometry of a configuration for the compression pipeline: HB lanes
+// per block, L lanes per tile (a wave's 64 segments hold 64 / L tiles).
+template <int HB, int L>
+struct TileCfg {
+    template <int W, bool FEAT>
+    static __device__ __forceinline__ ChunkState rates(const CompressArgs &a, const Resolved &R, uint64_t chunk,
+                                                       int (&x)[32], int slot, CompressShared<W> &sh)
+    {
+        static_assert(!FEAT, "the configuration kernels run the full method");
+        return cfg_rates<HB, L, W>(a, R, chunk, x, slot, sh);
+    }
+    template <bool FEAT>
+    static __device__ __forceinline__ void stage(const ChunkState &cs, int (&B)[32], uint32_t *st)
+    {
+        cfg_stage<HB>(cs, B, st);
+    }
+    template <int W>
+    static __device__ __forceinline__ bool wave_live(const CompressArgs &a, uint64_t chunk, int w)
+    {
+        return (chunk * W + (uint64_t)w) * 64 / L < a.ntiles;
+    }
+    template <int W>
+    static __device__ __forceinline__ void store_rate(const CompressArgs &a, const ChunkState &cs, int w, int lane)
+    {
+        if (cs.vm != 0 && lane % HB == 0)
+            ((g_u8 *)a.out)[kHeaderBytes + ((cs.chunk * W + (uint64_t)w) * 64 + lane) / HB] = (uint8_t)cs.rbyte;
+    }
+};
+
+// Pipelined compressor of a tile configuration: compress_ctrl_kernel's
+// pipeline (8 data waves, one control wave, persistent workgroups, chunks of
+// 8 x 64 segments from the ticket counter) over the configuration's tiles.
+// The input must be 16-byte aligned; a.nchunks counts chunks of
+// kCfgPipeChunkSegs segments.  A wave's output (rates <= 24: at most 64 x 100
+// B of words and 16 tile means) fits its staging area.
+template <int HB, int L>
+__global__ __launch_bounds__(9 * 64) void compress_cfg_pipe_kernel(CompressArgs a)
+{
+    __shared__ CompressShared<8> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t inbuf[8 * kPipeWaveDwords];
+    __shared__ __attribute__((aligned(16))) uint32_t stbuf[8 * kPipeWaveDwords];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const Resolved R = resolve_bound(a.stats, a.mode, a.value, a.n);
+    if (R.status != FSZ_OK) {  // no data work: hand out the tickets, the last chunk reports
+        const uint64_t takes = a.nchunks + gridDim.x;
+        int tslot = 0;
+        for (;;) {
+            const uint64_t t = next_ticket(a.ticket, takes, sh, tslot);
+            if (t >= a.nchunks) return;
+            if (threadIdx.x == 0 && t == a.nchunks - 1) write_final(a.final, 0, R.status, a.epoch);
+        }
+    }
+    if (w < 8)
+        pipe2_run<false, 8, false, TileCfg<HB, L>>(a, R, sh, inbuf + w * kPipeWaveDwords,
+                                                    stbuf + w * kPipeWaveDwords, w);
+    else
+        ctrl_run<8>(a, R, sh);
+}
+
 template <bool ALIGNED, int HB, int L>
 __global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressArgs a)
 {
@@ -3327,10 +3565,33 @@ static hipError_t launch_decompress_cfg_t(const DecompressArgs &a, int block, in
     return hipGetLastError();
 }
 
+// Pipelined form (16-byte aligned input): persistent workgroups of 8 data
+// waves and a control wave, chunks of kCfgPipeChunkSegs segments.
+template <int HB, int L>
+static hipError_t launch_compress_cfg_pipe_t(const CompressArgs &a, hipStream_t s)
+{
+    static const unsigned cap = persistent_grid(compress_cfg_pipe_kernel<HB, L>, ~0ull, 9 * 64);
+    hipLaunchKernelGGL((compress_cfg_pipe_kernel<HB, L>), dim3((unsigned)(a.nchunks < cap ? a.nchunks : cap)),
+                       dim3(9 * 64), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_compress_cfg(const CompressArgs &a, int block, int tile_blocks, bool in_aligned16, hipStream_t s)
 {
-    return in_aligned16 ? launch_compress_cfg_t<true>(a, block, tile_blocks, s)
-                        : launch_compress_cfg_t<false>(a, block, tile_blocks, s);
+    if (in_aligned16) {
+        CompressArgs p = a;
+        p.nchunks = a.n ? ceil_div(ceil_div(a.n, (uint64_t)kBlock), (uint64_t)kCfgPipeChunkSegs) : 1;
+        switch (block * 100 + tile_blocks) {
+        case 3204: return launch_compress_cfg_pipe_t<1, 4>(p, s);
+        case 3208: return launch_compress_cfg_pipe_t<1, 8>(p, s);
+        case 3216: return launch_compress_cfg_pipe_t<1, 16>(p, s);
+        case 6404: return launch_compress_cfg_pipe_t<2, 8>(p, s);
+        case 6408: return launch_compress_cfg_pipe_t<2, 16>(p, s);
+        case 6416: return launch_compress_cfg_pipe_t<2, 32>(p, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return launch_compress_cfg_t<false>(a, block, tile_blocks, s);
 }
 
 hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
