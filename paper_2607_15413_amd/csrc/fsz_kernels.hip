@@ -1900,8 +1900,9 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     // carries from the blocks before in the tile (none when every block
     // restarts prediction)
     const uint32_t start1 = indep ? 0u : group_excl_scan(acc, j);
+    const bool any2 = __ballot(d.order2) != 0;  // wave-uniform: some tile of the wave is LZ2
     uint32_t acc2 = 0;
-    if (__ballot(d.order2) != 0) {
+    if (any2) {
 #pragma unroll
         for (int i = 0; i < 32; i++) {
             acc2 += code[i] + start1;
@@ -1909,15 +1910,19 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     }
     const uint32_t start2 = indep ? 0u : group_excl_scan(acc2, j);
     float xo[32];
-    {
-        const uint32_t om = (uint32_t)-d.order2;
-        uint32_t run = start2;
+    // the tile mean enters the start of the running sum that is the lane's
+    // result: the first (LZ1) or the second (LZ2)
+    const uint32_t s1 = start1 + (d.order2 ? 0u : (uint32_t)mu);
+    if (!any2) {
+#pragma unroll
+        for (int i = 0; i < 32; i++) xo[i] = (float)(int)(code[i] + s1) * E;
+    } else {
+        uint32_t run = start2 + (d.order2 ? (uint32_t)mu : 0u);
 #pragma unroll
         for (int i = 0; i < 32; i++) {
-            const uint32_t d1 = code[i] + start1;  // first running sum with the carry
-            run += d1;                             // second running sum
-            const uint32_t qh = (run & om) | (d1 & ~om);
-            xo[i] = (float)(int)(qh + (uint32_t)mu) * E;
+            const uint32_t d1 = code[i] + s1;  // first running sum with the carry
+            run += d1;                         // second running sum
+            xo[i] = (float)(int)(d.order2 ? run : d1) * E;
         }
     }
 
@@ -3268,14 +3273,14 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
     const uint32_t start2 = lane_run_incl_scan<L>(acc2, tl, run) - acc2;
     float xo[32];
     {
-        const uint32_t om = (uint32_t)-order2;
-        uint32_t run2 = start2;
+        // the tile mean enters the start of the running sum that is the result
+        const uint32_t s1 = start1 + (order2 ? 0u : (uint32_t)mu);
+        uint32_t run2 = start2 + (order2 ? (uint32_t)mu : 0u);
 #pragma unroll
         for (int i = 0; i < 32; i++) {
-            const uint32_t d1 = code[i] + start1;  // first running sum with the carry
-            run2 += d1;                            // second running sum
-            const uint32_t qh = (run2 & om) | (d1 & ~om);
-            xo[i] = (float)(int)(qh + (uint32_t)mu) * E;
+            const uint32_t d1 = code[i] + s1;  // first running sum with the carry
+            run2 += d1;                        // second running sum
+            xo[i] = (float)(int)(order2 ? run2 : d1) * E;
         }
     }
     // ---- write back through LDS with coalesced stores (the wave's 2048 elements)
