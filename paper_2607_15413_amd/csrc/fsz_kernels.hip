@@ -722,8 +722,9 @@ __device__ __forceinline__ void block_extrema(int (&B)[32], int carry_b, int car
     mn1 = min(mn1, l1z);
     mx2 = max(mx2, l2z);
     mn2 = min(mn2, l2z);
-    a1 = max(uabs(mx1), uabs(mn1));
-    a2 = max(uabs(mx2), uabs(mn2));
+    // max(|mx|, |mn|) = max(mx, -mn) for mx >= mn
+    a1 = (uint32_t)max(mx1, -mn1);
+    a2 = (uint32_t)max(mx2, -mn2);
 }
 
 // Residual codes of the selected variant, in place, from the LZ1 residuals d
@@ -1867,18 +1868,25 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     int mu = 0;
     if (d.cent) mu = (int)*(const g_u32 *)(wave_data + d.tile_excl);
 
-    // ---- bit-unshuffle: stored words -> residual codes
+    // ---- bit-unshuffle: stored words -> residuals.  With ns = -sign, a
+    // residual is (m ^ ns) + sign for its magnitude m, and the bit planes of
+    // m ^ ns are the stored magnitude planes xor the sign map (word 0); the
+    // planes at or above the block's rate are zero, so there it is the sign
+    // map itself.  G groups of 8 planes give x = (m ^ ns) mod 2^(8 G), so the
+    // residual is x + sign (1 - 2^(8 G)) (mod 2^32).
     uint32_t code[32];
 #pragma unroll
     for (int i = 0; i < 32; i++) code[i] = 0;
-    const uint32_t nwords = (blk_ok && d.r) ? d.r + 1 : 0;
+    const uint32_t r = blk_ok ? d.r : 0;  // magnitude planes
     const g_u32 *words = (const g_u32 *)(wave_data + d.blk_off);
-    for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
+    const uint32_t sw = r ? words[0] : 0u;  // sign map: element i at bit i ^ 7
+    uint32_t G = 0;                         // groups assembled (wave-uniform)
+    for (uint32_t g = 0; __ballot(8 * g < r) != 0; g++) {
         uint32_t Rg[8];
 #pragma unroll
-        for (int k = 0; k < 8; k++) Rg[k] = 8 * g + k < nwords ? words[8 * g + k] : 0u;
+        for (int k = 0; k < 8; k++) Rg[k] = (8 * g + k < r ? words[1 + 8 * g + k] : 0u) ^ sw;
         transpose8(Rg);
-        // Rg[rho] byte k = byte g of code 8k + 7 - rho
+        // Rg[rho] byte k = byte g of x of element 8k + 7 - rho
 #pragma unroll
         for (int rho = 0; rho < 8; rho++) {
 #pragma unroll
@@ -1887,14 +1895,16 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
                 code[8 * k + 7 - rho] = __builtin_amdgcn_perm(Rg[rho], code[8 * k + 7 - rho], sel);
             }
         }
+        G = g + 1;
     }
 
     // ---- inverse cross-block prediction + dequantization
+    const uint32_t M = 1u - (1u << (8 * G));  // 1 - 2^(8 G) mod 2^32 (G <= 3: rates <= 24)
     uint32_t acc = 0;
 #pragma unroll
     for (int i = 0; i < 32; i++) {
-        const uint32_t ns = (uint32_t)-(int)(code[i] & 1u);  // 0 or all ones
-        acc += ((code[i] >> 1) ^ ns) - ns;
+        const uint32_t ns = (uint32_t)((int)(sw << (31 - (i ^ 7))) >> 31);  // -sign
+        acc += code[i] + (ns & M);
         code[i] = acc;  // first running sum (LZ1 reconstruction / LZ2 first differences)
     }
     // carries from the blocks before in the tile (none when every block
