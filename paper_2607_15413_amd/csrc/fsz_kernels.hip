@@ -1899,7 +1899,7 @@ __device__ __forceinline__ void dec_decode(const DecompressArgs &a, const DecChu
     }
 
     // ---- inverse cross-block prediction + dequantization
-    const uint32_t M = 1u - (1u << (8 * G));  // 1 - 2^(8 G) mod 2^32 (G <= 3: rates <= 24)
+    const uint32_t M = G < 4 ? 1u - (1u << (8 * G)) : 1u;  // 1 - 2^(8 G) mod 2^32
     uint32_t acc = 0;
 #pragma unroll
     for (int i = 0; i < 32; i++) {
@@ -3246,17 +3246,21 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
     const uint8_t *wave_data = a.cmp + a.data0 + base + wave_base;
     int mu = 0;
     if (cent) mu = (int)*reinterpret_cast<const uint32_t *>(wave_data + tile_excl);
+    // the sign map folded into the magnitude planes, as in dec_decode: a
+    // residual is x + sign (1 - 2^(8 G)) (mod 2^32)
     uint32_t code[32];
 #pragma unroll
     for (int i = 0; i < 32; i++) code[i] = 0;
-    const uint32_t nwords = (blk_ok && r) ? r + 1 : 0;
+    const uint32_t rp = blk_ok ? r : 0;  // magnitude planes
     const uint32_t *words = reinterpret_cast<const uint32_t *>(wave_data + tile_excl + blk_rel) + h;
-    for (uint32_t g = 0; __ballot(8 * g < nwords) != 0; g++) {
+    const uint32_t sw = rp ? words[0] : 0u;  // the lane's half of the sign map
+    uint32_t G = 0;
+    for (uint32_t g = 0; __ballot(8 * g < rp) != 0; g++) {
         uint32_t Rg[8];
 #pragma unroll
-        for (int p = 0; p < 8; p++) Rg[p] = 8 * g + p < nwords ? words[HB * (8 * g + p)] : 0u;
+        for (int p = 0; p < 8; p++) Rg[p] = (8 * g + p < rp ? words[HB * (1 + 8 * g + p)] : 0u) ^ sw;
         transpose8(Rg);
-        // Rg[rho] byte k = byte g of code 8k + 7 - rho
+        // Rg[rho] byte k = byte g of x of element 8k + 7 - rho
 #pragma unroll
         for (int rho = 0; rho < 8; rho++) {
 #pragma unroll
@@ -3265,12 +3269,14 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
                 code[8 * k + 7 - rho] = __builtin_amdgcn_perm(Rg[rho], code[8 * k + 7 - rho], sel);
             }
         }
+        G = g + 1;
     }
+    const uint32_t M = G < 4 ? 1u - (1u << (8 * G)) : 1u;  // 1 - 2^(8 G) mod 2^32
     uint32_t acc = 0;
 #pragma unroll
     for (int i = 0; i < 32; i++) {
-        const uint32_t ns = (uint32_t)-(int)(code[i] & 1u);
-        acc += ((code[i] >> 1) ^ ns) - ns;
+        const uint32_t ns = (uint32_t)((int)(sw << (31 - (i ^ 7))) >> 31);  // -sign
+        acc += code[i] + (ns & M);
         code[i] = acc;  // first running sum inside the segment
     }
     // carries from the earlier lanes of the prediction run (the tile, or the

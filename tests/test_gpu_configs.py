@@ -185,6 +185,30 @@ def test_config_fuzz():
         assert np.array_equal(y.view(np.uint32), oracle.decompress(exp, n).view(np.uint32)), case
 
 
+@pytest.mark.parametrize("config", [(32, 4), (64, 8)])
+def test_config_decoder_high_rates(config):
+    """Rates up to 31 in a configuration's stream (tiles centred on means
+    far from their data), next to tiles of low rates."""
+    B, T = config
+    rng = np.random.default_rng(79)
+    for n in (3000, 20_001):
+        announce(f"config {config} python-encoded high rates n={n}")
+        x = workloads.sinusoid_field(n, int(rng.integers(1000)))
+        st, E, inv, _ = oracle.resolve(x, oracle.REL, 1e-3)
+        lim = (1 << 31) - (1 << 23)
+        choices = []
+        for t in range(fmt.ceil_div(n, B * T)):
+            far = t == 0 or rng.random() < 0.5
+            mu = int(rng.integers(-lim, lim)) if far else int(rng.integers(-5000, 5000))
+            choices.append((int(rng.integers(2)), 1 if far else int(rng.integers(2)), mu))
+        s = fmt.encode_stream(x, E, inv, oracle.REL, 1e-3, 0, choices, B=B, T=T)
+        assert max(b & 31 for b in fmt.rate_bytes(s, n, B)) >= 25
+        st, y = gpu_decompress_config(s, n, config)
+        assert st == fsz.FSZ_OK
+        assert np.array_equal(y.view(np.uint32), fmt.closed_form(x, E, inv).view(np.uint32))
+        assert np.array_equal(y.view(np.uint32), oracle.decompress(s, n).view(np.uint32))
+
+
 def test_default_config_is_the_plain_stream():
     x = workloads.grf_field((64, 64, 64), 9)
     for rel in (1e-2, 1e-3):

@@ -400,6 +400,30 @@ def test_decoder_any_variant_and_mean():
         assert np.array_equal(y, fmt.closed_form(x, E, inv))
 
 
+def test_decoder_high_rates():
+    """Rates up to 31 (the format's maximum; the compressor itself stays at
+    or below 24): tiles centred on means far from their data give tile-start
+    residuals near 2^31, so waves assemble all four byte groups of the
+    magnitude planes next to waves of low rates."""
+    rng = np.random.default_rng(78)
+    for n in (256, 3000, 20_001):
+        announce(f"python-encoded high rates n={n}")
+        x = workloads.sinusoid_field(n, int(rng.integers(1000)))
+        st, E, inv, _ = oracle.resolve(x, oracle.REL, 1e-3)
+        lim = (1 << 31) - (1 << 23)
+        choices = []
+        for t in range(fmt.ceil_div(n, 256)):
+            far = t == 0 or rng.random() < 0.5
+            mu = int(rng.integers(-lim, lim)) if far else int(rng.integers(-5000, 5000))
+            choices.append((int(rng.integers(2)), 1 if far else int(rng.integers(2)), mu))
+        s = fmt.encode_stream(x, E, inv, oracle.REL, 1e-3, 0, choices)
+        assert max(b & 31 for b in fmt.rate_bytes(s, n)) >= 25
+        st, y = gpu_decompress(s, n)
+        assert st == fsz.FSZ_OK
+        assert np.array_equal(y.view(np.uint32), fmt.closed_form(x, E, inv).view(np.uint32))
+        assert np.array_equal(y.view(np.uint32), oracle.decompress(s, n).view(np.uint32))
+
+
 def test_corrupt_streams_match_oracle_status():
     from tests.test_oracle import _mutations
     n = 3000
