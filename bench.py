@@ -1188,6 +1188,9 @@ def main():
         "decompress_GBps": round(len(RELS) * 4 * n / dec_time / 1e6, 1),
         "range_pass_ms": round(stats_ms, 4),
         "compress_end_to_end_GBps": round(len(RELS) * 4 * n / (comp_time + len(RELS) * stats_ms) / 1e6, 1),
+        # the range pass reads the field once more: 8 n + stream bytes per call
+        "compress_end_to_end_hbm_frac": round(sum(8 * n + sizes[k] for k in range(len(RELS))) /
+                                              (comp_time + len(RELS) * stats_ms) / 1e6 / HBM_PEAK_GBPS, 4),
         "per_bound": per_bound,
         "copy_ceiling_GBps": round(copy_GBps, 1),
         "roofline": roofline,
