@@ -1624,6 +1624,10 @@ __device__ __forceinline__ void ctrl_run(const CompressArgs &a, const Resolved &
 {
     const uint64_t N = a.nchunks;
     const uint64_t takes = N + gridDim.x;
+    // first pick of its SIMD's issue slots: the wave shares a SIMD with two
+    // data waves in their rate pass, and its short lookback bursts gate the
+    // step's second barrier
+    __builtin_amdgcn_s_setprio(3);
     int tslot = 0;
     uint64_t A = next_ticket(a.ticket, takes, sh, tslot);
     if (A >= N) return;
