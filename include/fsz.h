@@ -241,8 +241,11 @@ fsz_status fsz_compress_five_read_async(const float *d_in, size_t n, fsz_eb_mode
  *     are zero for 32 / 8, so the default configuration gives exactly the
  *     stream of fsz_compress_async.
  * The reconstruction x' = q E does not depend on the configuration.  These
- * calls run the generic kernels (a lane per 32 elements, one chunk of 32768
- * elements per workgroup) for every configuration, 32 / 8 included.
+ * calls run the same kernels for every configuration, 32 / 8 included: a
+ * lane per 32 elements; compression of a 16-byte aligned input by the
+ * pipelined persistent kernel of the default path (chunks of 16384
+ * elements), other inputs and every decompression one chunk of 32768
+ * elements per workgroup.
  *
  * fsz_compressed_bound_config: worst-case stream size (every block at rate
  *   31); 0 for an unsupported configuration.
