@@ -904,6 +904,9 @@ def parse_args():
                     help="compress requests of the served byte comparison against the plain path (0: none)")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served section of the default line (offered loads 0.1 / 0.5 / 0.9)")
+    ap.add_argument("--only-small", action="store_true",
+                    help="time only the small configurations (2^20 sinusoid, 100x500x500 piecewise "
+                         "quadratic) and print their rows; for kernel traces of those calls")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run one plain device copy of the input (n floats) so that "
                          "profiler counters can be calibrated against a kernel of known traffic")
@@ -919,6 +922,13 @@ def main():
         sys.exit(2)
     if args.served:
         served_benchmark(args)
+        return
+    if args.only_small:
+        import torch
+
+        from paper_2607_15413_amd import fsz, workloads
+        torch.cuda.set_device(torch.device("cuda:0"))
+        print(json.dumps({"other_configs": small_configs(torch, fsz, workloads, not args.no_verify)}), flush=True)
         return
 
     import torch
