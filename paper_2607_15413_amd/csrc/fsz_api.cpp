@@ -388,7 +388,17 @@ fsz_status enqueue_decompress_config(Workspace *ws, const void *d_cmp, uint64_t 
     a.flags = ws->d_flags;
     a.ticket = ws->d_ticket;
     a.final = d_final;
-    if (!ok(launch_decompress_cfg(a, block, tile_blocks, aligned(d_out, 16), ws->stream))) return FSZ_ERR_DEVICE;
+    hipError_t e;
+    if (tuning().dec_prescan && n >= tuning().dec_lookback_below) {
+        // chunk offsets from the rate header first, as for the default format
+        if (!grow(&ws->d_offs, &ws->offs_cap, a.nchunks, ws->stream)) return FSZ_ERR_DEVICE;
+        a.offsets = ws->d_offs;
+        a.go = ws->d_go;
+        e = launch_decompress_cfg_prescan(a, block, tile_blocks, aligned(d_out, 16), ws->stream);
+    } else {
+        e = launch_decompress_cfg(a, block, tile_blocks, aligned(d_out, 16), ws->stream);
+    }
+    if (!ok(e)) return FSZ_ERR_DEVICE;
     return FSZ_OK;
 }
 

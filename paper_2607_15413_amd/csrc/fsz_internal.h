@@ -179,6 +179,10 @@ hipError_t launch_decompress_prezero(const DecompressArgs &a, bool out_aligned16
 hipError_t launch_compress_cfg(const CompressArgs &a, int block, int tile_blocks, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
                                  hipStream_t s);
+// The same decode with chunk offsets from a pre-pass over the rate header
+// (a.offsets: one per chunk of kCfgChunkSegs segments; a.go: its outcome).
+hipError_t launch_decompress_cfg_prescan(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
+                                         hipStream_t s);
 constexpr int kCfgWaves = 16;
 constexpr int kCfgChunkSegs = kCfgWaves * 64;
 constexpr int kCfgPipeChunkSegs = 8 * 64;  // the pipelined configuration compressor's chunk

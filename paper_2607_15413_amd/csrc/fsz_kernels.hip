@@ -2005,7 +2005,10 @@ __device__ __forceinline__ int dec_header(const DecompressArgs &a, float &E, uin
     total = 0;
     const uint32_t h1 = h[1];
     indep = false;
-    if (h[0] != 0x315A5346u || (h1 & 0xFFFFu) != 1u || ((h1 >> 16) & 0xFFu) > 1u || ((h1 >> 24) & ~3u) != 0u)
+    // flags: bits 0-1 free, bits 2-4 the tile configuration (a.cfg_flags: 0 for
+    // the default format), the rest zero
+    if (h[0] != 0x315A5346u || (h1 & 0xFFFFu) != 1u || ((h1 >> 16) & 0xFFu) > 1u || ((h1 >> 24) & ~0x1Fu) != 0u ||
+        ((h1 >> 24) & 0x1Cu) != a.cfg_flags)
         return FSZ_ERR_CORRUPT;
     indep = ((h1 >> 25) & 1u) != 0;  // flags bit 1: prediction restarts at every block
     if (((uint64_t)h[3] << 32 | h[2]) != a.n) return FSZ_ERR_SIZE_MISMATCH;
@@ -2080,10 +2083,13 @@ constexpr int kScanThreads = 1024;
 constexpr int kScanTilesPerThread = 4;
 constexpr int kScanTiles = kScanThreads * kScanTilesPerThread;
 
-template <int TPC>
+// TPC tiles per decoder chunk; T blocks per tile of HB 32-element segments
+// each (the default format: 8 and 1; the tile configurations: the stream's).
+template <int TPC, int T = kBlocksPerTile, int HB = 1>
 __global__ __launch_bounds__(kScanThreads) void dec_offsets_single_kernel(DecompressArgs a, unsigned long long *offs,
                                                                           uint32_t *go, uint64_t ngroups)
 {
+    static_assert(T == 4 || T == 8 || T == 16, "a tile's rate bytes are 1, 2 or 4 words");
     static_assert(TPC % kScanTilesPerThread == 0, "a chunk starts at a thread's first tile");
     __shared__ uint32_t wsum[kScanThreads / 64];
     __shared__ unsigned long long gbase;
@@ -2117,16 +2123,18 @@ __global__ __launch_bounds__(kScanThreads) void dec_offsets_single_kernel(Decomp
     for (int i = 0; i < kScanTilesPerThread; i++) {
         const uint64_t tile = tile0 + i;
         if (tile < a.ntiles) {
-            const uint32_t *p = reinterpret_cast<const uint32_t *>(a.cmp + kHeaderBytes + tile * kBlocksPerTile);
-            const uint32_t w0 = p[0], w1 = p[1];
-            const uint64_t nb64 = a.nblocks - tile * kBlocksPerTile;
-            const uint32_t nb = nb64 < kBlocksPerTile ? (uint32_t)nb64 : (uint32_t)kBlocksPerTile;
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(a.cmp + kHeaderBytes + tile * T);
+            uint32_t rw[T / 4];
 #pragma unroll
-            for (uint32_t b = 0; b < kBlocksPerTile; b++) {
-                const uint32_t rb = ((b < 4 ? w0 : w1) >> (8 * (b & 3))) & 0xFFu;
+            for (int q = 0; q < T / 4; q++) rw[q] = p[q];
+            const uint64_t nb64 = a.nblocks - tile * T;
+            const uint32_t nb = nb64 < (uint64_t)T ? (uint32_t)nb64 : (uint32_t)T;
+#pragma unroll
+            for (uint32_t b = 0; b < (uint32_t)T; b++) {
+                const uint32_t rb = (rw[b >> 2] >> (8 * (b & 3))) & 0xFFu;
                 if (b < nb) {
                     bad |= b == 0 ? (rb & 0x20u) : (rb & 0xE0u);
-                    z += block_bytes(rb & 31u) + ((b == 0 && (rb & 0x40u)) ? 4u : 0u);
+                    z += HB * block_bytes(rb & 31u) + ((b == 0 && (rb & 0x40u)) ? 4u : 0u);
                 }
             }
         }
@@ -3163,7 +3171,10 @@ __global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressAr
     wave_store_staged(reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base), st, wave_total >> 2, lane);
 }
 
-template <bool ALIGNED, int HB, int L>
+// PRESCAN: the chunk offsets come from dec_offsets_single_kernel<1024 / L,
+// L / HB, HB> (which also checked the stream and reported its outcome):
+// chunk = workgroup, no lookback.
+template <bool ALIGNED, int HB, int L, bool PRESCAN = false>
 __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(DecompressArgs a)
 {
     __shared__ DecompressShared<kCfgWaves> sh;
@@ -3188,12 +3199,14 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
     const uint64_t total = (uint64_t)hw[7] << 32 | hw[6];
     if (hst == FSZ_OK && (!__builtin_isfinite(E) || !(E > 0.0f) || total > a.cmp_size || total < a.data0))
         hst = FSZ_ERR_CORRUPT;
-    if (hst != FSZ_OK) {
+    if (PRESCAN) {
+        if (*a.go != FSZ_OK) return;
+    } else if (hst != FSZ_OK) {
         if (tid == 0 && blockIdx.x == 0) write_final(a.final, 0, hst, a.epoch);
         return;
     }
     int tslot = 0;
-    const uint64_t chunk = next_ticket(a.ticket, a.nchunks, sh, tslot);
+    const uint64_t chunk = PRESCAN ? (uint64_t)blockIdx.x : next_ticket(a.ticket, a.nchunks, sh, tslot);
     if (chunk >= a.nchunks) return;
 
     // ---- steps 1-2: rate bytes -> block, tile and wave sizes
@@ -3230,20 +3243,25 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
         chunk_total += sh.wave_total[0][k];
         any_bad = any_bad || sh.wave_total[1][k] != 0;
     }
-    if (tid == 0) publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, any_bad);
-    if (w == 0) {
-        const Prefix pre_c = lookback_wait(a.flags, chunk, a.flag_epoch, chunk_total, any_bad);
-        if (lane == 0) {
-            sh.base = pre_c.excl;
-            if (chunk == a.nchunks - 1) {  // the sizes add up to the stream's total, padding is zero
-                bool good = !pre_c.err && a.data0 + pre_c.excl + chunk_total == total;
-                for (uint64_t k = kHeaderBytes + a.nblocks; good && k < a.data0; k++) good = a.cmp[k] == 0;
-                write_final(a.final, total, good ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT, a.epoch);
+    uint64_t base;
+    if (PRESCAN) {
+        base = a.offsets[chunk];
+    } else {
+        if (tid == 0) publish_aggregate(a.flags, chunk, a.flag_epoch, chunk_total, any_bad);
+        if (w == 0) {
+            const Prefix pre_c = lookback_wait(a.flags, chunk, a.flag_epoch, chunk_total, any_bad);
+            if (lane == 0) {
+                sh.base = pre_c.excl;
+                if (chunk == a.nchunks - 1) {  // the sizes add up to the stream's total, padding is zero
+                    bool good = !pre_c.err && a.data0 + pre_c.excl + chunk_total == total;
+                    for (uint64_t k = kHeaderBytes + a.nblocks; good && k < a.data0; k++) good = a.cmp[k] == 0;
+                    write_final(a.final, total, good ? (uint32_t)FSZ_OK : (uint32_t)FSZ_ERR_CORRUPT, a.epoch);
+                }
             }
         }
+        lds_barrier();
+        base = sh.base;
     }
-    lds_barrier();
-    const uint64_t base = sh.base;
     if (any_bad || a.data0 + base + chunk_total > total || seg0 / L >= a.ntiles) return;
 
     // ---- steps 3-5: bit-unshuffle, inverse prediction, x' = (float)q * E
@@ -3624,6 +3642,44 @@ hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_bl
 {
     return out_aligned16 ? launch_decompress_cfg_t<true>(a, block, tile_blocks, s)
                          : launch_decompress_cfg_t<false>(a, block, tile_blocks, s);
+}
+
+// Offsets pre-pass (chunks of kCfgChunkSegs segments = 1024 / L tiles), then
+// one chunk per workgroup without lookback.
+template <bool ALIGNED, int HB, int L>
+static hipError_t launch_decompress_cfg_prescan_t(const DecompressArgs &a, hipStream_t s)
+{
+    const uint64_t ngroups = a.ntiles ? ceil_div(a.ntiles, (uint64_t)kScanTiles) : 1;
+    hipLaunchKernelGGL((dec_offsets_single_kernel<kCfgChunkSegs / L, L / HB, HB>), dim3((unsigned)ngroups),
+                       dim3(kScanThreads), 0, s, a, const_cast<unsigned long long *>(a.offsets),
+                       const_cast<uint32_t *>(a.go), ngroups);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, HB, L, true>), dim3((unsigned)a.nchunks),
+                       dim3(kCfgWaves * 64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <bool ALIGNED>
+static hipError_t launch_decompress_cfg_prescan_a(const DecompressArgs &a, int block, int tile_blocks,
+                                                  hipStream_t s)
+{
+    switch (block * 100 + tile_blocks) {
+    case 3204: return launch_decompress_cfg_prescan_t<ALIGNED, 1, 4>(a, s);
+    case 3208: return launch_decompress_cfg_prescan_t<ALIGNED, 1, 8>(a, s);
+    case 3216: return launch_decompress_cfg_prescan_t<ALIGNED, 1, 16>(a, s);
+    case 6404: return launch_decompress_cfg_prescan_t<ALIGNED, 2, 8>(a, s);
+    case 6408: return launch_decompress_cfg_prescan_t<ALIGNED, 2, 16>(a, s);
+    case 6416: return launch_decompress_cfg_prescan_t<ALIGNED, 2, 32>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_decompress_cfg_prescan(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
+                                         hipStream_t s)
+{
+    return out_aligned16 ? launch_decompress_cfg_prescan_a<true>(a, block, tile_blocks, s)
+                         : launch_decompress_cfg_prescan_a<false>(a, block, tile_blocks, s);
 }
 
 constexpr size_t kLdsPerCu = 160 * 1024;

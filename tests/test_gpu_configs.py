@@ -291,6 +291,52 @@ def test_config_errors_match_oracle():
             assert gpu_decompress_config(bytes(c), n, config)[0] == oracle.ERR_CORRUPT
 
 
+@pytest.mark.parametrize("config", [(32, 4), (64, 8), (64, 16)])
+def test_config_prepass_decoder_and_corrupt_streams(config):
+    """Fields of 2^22 elements and more decode with chunk offsets from a
+    pre-pass over the rate header: bit-exact decoding, and the oracle's
+    status for corrupt streams (header fields, reserved rate bits, a rate
+    that no longer matches the sizes, padding, a stream cut short)."""
+    B, T = config
+    old = oracle.set_threads(8)
+    try:
+        n = (1 << 22) + 77
+        x = workloads.sinusoid_field(n, 21)
+        s = oracle.compress(x, oracle.REL, 1e-4, config=config)
+        announce(f"config {config} pre-pass decode n={n}: clean stream")
+        st, y = gpu_decompress_config(s, n, config)
+        assert st == fsz.FSZ_OK
+        assert np.array_equal(y.view(np.uint32), oracle.decompress(s, n).view(np.uint32))
+        nb = fmt.ceil_div(n, B)
+        d0 = fmt.data_start(n, B)
+        cases = {
+            "magic": lambda c: c.__setitem__(0, ord("G")),
+            "mode": lambda c: c.__setitem__(6, 2),
+            "reserved tile code": lambda c: c.__setitem__(7, c[7] | 0x18),
+            "n": lambda c: c.__setitem__(8, c[8] ^ 1),
+            "E zero": lambda c: c.__setitem__(slice(16, 20), bytes(4)),
+            "total": lambda c: c.__setitem__(24, c[24] ^ 4),
+            "reserved rate bit (block 0)": lambda c: c.__setitem__(32, c[32] | 0x20),
+            "reserved rate bit (block 1)": lambda c: c.__setitem__(33, c[33] | 0x80),
+            "rate + 1": lambda c: c.__setitem__(34, (c[34] & 0xE0) | min(31, (c[34] & 0x1F) + 1)),
+            "last rate + 1": lambda c: c.__setitem__(32 + nb - 1, (c[32 + nb - 1] & 0xE0) |
+                                                     min(31, (c[32 + nb - 1] & 0x1F) + 1)),
+        }
+        if d0 > 32 + nb:
+            cases["padding"] = lambda c: c.__setitem__(32 + nb, 1)
+        for name, f in cases.items():
+            announce(f"config {config} pre-pass decode n={n}: {name}")
+            c = bytearray(s)
+            f(c)
+            want = oracle.decompress_status(bytes(c), n)[0]
+            assert want != oracle.OK, name
+            assert gpu_decompress_config(bytes(c), n, config)[0] == want, name
+        announce(f"config {config} pre-pass decode n={n}: stream cut short")
+        assert gpu_decompress_config(s[:-4], n, config)[0] == oracle.decompress_status(s[:-4], n)[0]
+    finally:
+        oracle.set_threads(old)
+
+
 @pytest.mark.parametrize("config", [(32, 16), (64, 8)])
 def test_config_full_size_grf_512(config):
     """The 512^3 field in the launch configuration the benchmark times: the
