@@ -245,7 +245,7 @@ fsz_status fsz_compress_five_read_async(const float *d_in, size_t n, fsz_eb_mode
  * lane per 32 elements; compression of a 16-byte aligned input by the
  * pipelined persistent kernel of the default path (chunks of 16384
  * elements), other inputs one chunk of 32768 elements per workgroup;
- * decompression one chunk of 32768 elements per workgroup, its offset from a
+ * decompression one chunk of 8192 elements per workgroup, its offset from a
  * pre-pass over the rate header for fields of 2^22 elements or more.
  *
  * fsz_compressed_bound_config: worst-case stream size (every block at rate

@@ -330,7 +330,8 @@ bool auto_prezero(uint64_t n, uint64_t cmp_size)
 }
 
 // Tile configurations (Sec. VI-C, Table V): the generic lane-per-segment
-// kernels, one chunk of kCfgChunkSegs 32-element segments per workgroup.
+// kernels, one chunk of kCfgChunkSegs 32-element segments per workgroup
+// (decoder: kCfgDecChunkSegs).
 fsz_status enqueue_compress_config(Workspace *ws, const float *d_in, uint64_t n, int mode, double value,
                                    const fsz_stats *d_stats, int block, int tile_blocks, void *d_out, uint64_t cap,
                                    fsz_result *d_final)
@@ -375,7 +376,7 @@ fsz_status enqueue_decompress_config(Workspace *ws, const void *d_cmp, uint64_t 
     a.n = n;
     a.ntiles = ceil_div(n, (uint64_t)block * tile_blocks);
     a.nblocks = ceil_div(n, (uint64_t)block);
-    a.nchunks = n ? ceil_div(ceil_div(n, kBlock), kCfgChunkSegs) : 1;
+    a.nchunks = n ? ceil_div(ceil_div(n, kBlock), kCfgDecChunkSegs) : 1;
     a.data0 = kHeaderBytes + pad16(a.nblocks);
     a.tile_begin = 0;
     a.tile_end = a.ntiles;

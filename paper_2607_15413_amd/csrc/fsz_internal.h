@@ -173,19 +173,24 @@ hipError_t launch_decompress_prescan(const DecompressArgs &a, unsigned long long
 // the decoder that skips waves whose tiles are all zero.
 hipError_t launch_decompress_prezero(const DecompressArgs &a, bool out_aligned16, hipStream_t s);
 // Tile configurations (Sec. VI-C): one chunk of kCfgWaves x 64 32-element segments per
-// workgroup (a.nchunks counts those), block in {32, 64}, tile_blocks in {4, 8, 16}.  A
+// workgroup (a.nchunks counts those; for the decoder kCfgDecWaves x 64), block in {32, 64},
+// tile_blocks in {4, 8, 16}.  A
 // 16-byte aligned input runs the pipelined compressor instead, whose chunks of
 // kCfgPipeChunkSegs segments the launch counts itself (the flags must cover them).
 hipError_t launch_compress_cfg(const CompressArgs &a, int block, int tile_blocks, bool in_aligned16, hipStream_t s);
 hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
                                  hipStream_t s);
 // The same decode with chunk offsets from a pre-pass over the rate header
-// (a.offsets: one per chunk of kCfgChunkSegs segments; a.go: its outcome).
+// (a.nchunks and a.offsets: one per chunk of kCfgDecChunkSegs segments; a.go:
+// its outcome).
 hipError_t launch_decompress_cfg_prescan(const DecompressArgs &a, int block, int tile_blocks, bool out_aligned16,
                                          hipStream_t s);
 constexpr int kCfgWaves = 16;
 constexpr int kCfgChunkSegs = kCfgWaves * 64;
 constexpr int kCfgPipeChunkSegs = 8 * 64;  // the pipelined configuration compressor's chunk
+// the configuration decoder: workgroups of 4 waves, one chunk of 4 x 64 segments each
+constexpr int kCfgDecWaves = 4;
+constexpr int kCfgDecChunkSegs = kCfgDecWaves * 64;
 // header flags bits 2-4 of a tile configuration (0 for B 32, T 8)
 inline uint32_t cfg_flag_bits(int block, int tile_blocks)
 {

@@ -2759,7 +2759,8 @@ __global__ __launch_bounds__(W * 64) void batch_pipe_kernel(BatchArgs b)
 // bits with element i at bit 63 - i, written most-significant byte first:
 // the stored words of its two halves side by side, so the lane of half h
 // writes its word k at byte 8k + 4h of the block.  One chunk of kCfgWaves
-// waves per workgroup, chunk ids from the ticket counter (as compress_kernel).
+// waves (decoder: kCfgDecWaves) per workgroup, chunk ids from the ticket
+// counter (as compress_kernel).
 
 // a wave's staging area: the padded input rows (64 x 36 dwords), reused for
 // its output (at most 64 x 128 B + 16 tile means = 2064 dwords)
@@ -3171,14 +3172,16 @@ __global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressAr
     wave_store_staged(reinterpret_cast<uint32_t *>(a.out + a.data0 + base + wave_base), st, wave_total >> 2, lane);
 }
 
-// PRESCAN: the chunk offsets come from dec_offsets_single_kernel<1024 / L,
-// L / HB, HB> (which also checked the stream and reported its outcome):
-// chunk = workgroup, no lookback.
-template <bool ALIGNED, int HB, int L, bool PRESCAN = false>
-__global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(DecompressArgs a)
+// WV waves per workgroup, chunks of 64 WV segments (4 waves: a wider grid,
+// which small fields need, and several workgroups per CU to hide the lookback
+// and the tile loads).  PRESCAN: the chunk offsets come from
+// dec_offsets_single_kernel<64 WV / L, L / HB, HB> (which also checked the
+// stream and reported its outcome): chunk = workgroup, no lookback.
+template <bool ALIGNED, int HB, int L, bool PRESCAN = false, int WV = kCfgDecWaves>
+__global__ __launch_bounds__(WV * 64) void decompress_cfg_kernel(DecompressArgs a)
 {
-    __shared__ DecompressShared<kCfgWaves> sh;
-    __shared__ __attribute__((aligned(16))) uint32_t stage[kCfgWaves * kCfgStageDwords];
+    __shared__ DecompressShared<WV> sh;
+    __shared__ __attribute__((aligned(16))) uint32_t stage[WV * kCfgStageDwords];
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
@@ -3210,7 +3213,7 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
     if (chunk >= a.nchunks) return;
 
     // ---- steps 1-2: rate bytes -> block, tile and wave sizes
-    const uint64_t seg0 = (chunk * kCfgWaves + w) * 64;
+    const uint64_t seg0 = (chunk * WV + w) * 64;
     const uint64_t seg = seg0 + lane;
     const bool tile_ok = seg / L < a.ntiles;
     const uint64_t blk = seg / HB;
@@ -3238,7 +3241,7 @@ __global__ __launch_bounds__(kCfgWaves * 64) void decompress_cfg_kernel(Decompre
     uint32_t chunk_total = 0, wave_base = 0;
     bool any_bad = false;
 #pragma unroll
-    for (int k = 0; k < kCfgWaves; k++) {
+    for (int k = 0; k < WV; k++) {
         if (k < w) wave_base += sh.wave_total[0][k];
         chunk_total += sh.wave_total[0][k];
         any_bad = any_bad || sh.wave_total[1][k] != 0;
@@ -3594,7 +3597,7 @@ static hipError_t launch_compress_cfg_t(const CompressArgs &a, int block, int ti
 template <bool ALIGNED>
 static hipError_t launch_decompress_cfg_t(const DecompressArgs &a, int block, int tile_blocks, hipStream_t s)
 {
-    const dim3 grid((unsigned)a.nchunks), threads(kCfgWaves * 64);
+    const dim3 grid((unsigned)a.nchunks), threads(kCfgDecWaves * 64);
     const int key = block * 100 + tile_blocks;
     switch (key) {
     case 3204: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 4>), grid, threads, 0, s, a); break;
@@ -3644,19 +3647,19 @@ hipError_t launch_decompress_cfg(const DecompressArgs &a, int block, int tile_bl
                          : launch_decompress_cfg_t<false>(a, block, tile_blocks, s);
 }
 
-// Offsets pre-pass (chunks of kCfgChunkSegs segments = 1024 / L tiles), then
-// one chunk per workgroup without lookback.
+// Offsets pre-pass (chunks of kCfgDecChunkSegs segments = kCfgDecChunkSegs / L
+// tiles), then one chunk per workgroup without lookback.
 template <bool ALIGNED, int HB, int L>
 static hipError_t launch_decompress_cfg_prescan_t(const DecompressArgs &a, hipStream_t s)
 {
     const uint64_t ngroups = a.ntiles ? ceil_div(a.ntiles, (uint64_t)kScanTiles) : 1;
-    hipLaunchKernelGGL((dec_offsets_single_kernel<kCfgChunkSegs / L, L / HB, HB>), dim3((unsigned)ngroups),
+    hipLaunchKernelGGL((dec_offsets_single_kernel<kCfgDecChunkSegs / L, L / HB, HB>), dim3((unsigned)ngroups),
                        dim3(kScanThreads), 0, s, a, const_cast<unsigned long long *>(a.offsets),
                        const_cast<uint32_t *>(a.go), ngroups);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, HB, L, true>), dim3((unsigned)a.nchunks),
-                       dim3(kCfgWaves * 64), 0, s, a);
+                       dim3(kCfgDecWaves * 64), 0, s, a);
     return hipGetLastError();
 }
 
