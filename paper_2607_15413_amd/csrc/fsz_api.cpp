@@ -38,7 +38,10 @@ const Tuning &tuning()
         }
         if (const char *e = std::getenv("FSZ_PREZERO_CR")) v.prezero_min_cr = std::atof(e);
         if (const char *e = std::getenv("FSZ_DEC_PRESCAN")) v.dec_prescan = std::atoi(e) != 0;
+        if (const char *e = std::getenv("FSZ_DEC_WIDE_ABOVE")) v.dec_wide_above = std::strtoull(e, nullptr, 10);
         if (const char *e = std::getenv("FSZ_DEC_LOOKBACK_BELOW")) v.dec_lookback_below = std::strtoull(e, nullptr, 10);
+        if (const char *e = std::getenv("FSZ_CFG_DEC_LOOKBACK_BELOW"))
+            v.cfg_dec_lookback_below = std::strtoull(e, nullptr, 10);
         if (const char *e = std::getenv("FSZ_DEC_DIRECT_BELOW")) v.dec_direct_below = std::strtoull(e, nullptr, 10);
         if (const char *e = std::getenv("FSZ_GRID_FACTOR")) {
             const int f = std::atoi(e);
@@ -390,7 +393,7 @@ fsz_status enqueue_decompress_config(Workspace *ws, const void *d_cmp, uint64_t 
     a.ticket = ws->d_ticket;
     a.final = d_final;
     hipError_t e;
-    if (tuning().dec_prescan && n >= tuning().dec_lookback_below) {
+    if (tuning().dec_prescan && n >= tuning().cfg_dec_lookback_below) {
         // chunk offsets from the rate header first, as for the default format
         if (!grow(&ws->d_offs, &ws->offs_cap, a.nchunks, ws->stream)) return FSZ_ERR_DEVICE;
         a.offsets = ws->d_offs;

@@ -234,8 +234,14 @@ bool reserve_batch(hipStream_t stream, uint64_t jobs, uint64_t chunks, uint64_t 
 // FSZ_STAGED (letters c / d / l: stage compress output / decompress output /
 // compress input through LDS), FSZ_PIPE (0: no pipelined persistent
 // compression for 16-byte aligned inputs), FSZ_PIPE_WAVES (its waves per
-// workgroup: 1, 2, 4 or 8), FSZ_DEC_WAVES (waves per decompression
-// workgroup: 4, 8 or 16), FSZ_GRID_FACTOR (persistent workgroups per CU slot,
+// workgroup: 1, 2, 4 or 8), FSZ_DEC_WAVES (waves per workgroup of the
+// lookback decoder: 4, 8 or 16, for every size), FSZ_DEC_WIDE_ABOVE (without
+// FSZ_DEC_WAVES: 16 waves above this many decoded elements, 8 up to it),
+// FSZ_DEC_LOOKBACK_BELOW and FSZ_CFG_DEC_LOOKBACK_BELOW (whole-field decodes of
+// the default format / the tile configurations below this many elements use
+// the lookback decoder, larger ones the offsets pre-pass), FSZ_DEC_DIRECT_BELOW
+// (pre-pass decodes below this size: one chunk per workgroup), FSZ_GRID_FACTOR
+// (persistent workgroups per CU slot,
 // default 1) and FSZ_PREZERO_CR (whole-field decodes of streams above this
 // compression ratio, judged from the buffer size, use the pre-zeroed decoder)
 // and FSZ_DEC_PRESCAN (0: whole-field decodes find chunk offsets by lookback
@@ -247,11 +253,13 @@ struct Tuning {
     bool pipe_compress = true;  // persistent compression with asynchronous LDS prefetch
     int pipe_waves = 9;         // pipelined compression: data waves per workgroup (1, 2, 4, 8), or 9 / 7:
                                 // 8 / 7 data waves and a control wave (compress_ctrl_kernel)
-    int dec_waves = 8;          // waves per workgroup of the decompression (4, 8, 16)
+    int dec_waves = 0;          // waves per workgroup of the lookback decoder (4, 8, 16; 0: by size)
+    uint64_t dec_wide_above = 1ull << 21;  // by size: 16 waves above this many decoded elements, else 8
     int grid_factor = 1;
     double prezero_min_cr = 0.0;  // whole-field decodes pre-zero above this CR (0: never)
     bool dec_prescan = true;      // whole-field decodes take chunk offsets from a pre-pass (no lookback)
-    uint64_t dec_lookback_below = 1ull << 22;  // ... except fields below this many elements (one launch)
+    uint64_t dec_lookback_below = 1ull << 23;      // ... except fields below this many elements (one launch)
+    uint64_t cfg_dec_lookback_below = 1ull << 22;  // the same for the tile configurations
     uint64_t dec_direct_below = 1ull << 26;    // pre-pass decodes below this size: one chunk per workgroup
 };
 const Tuning &tuning();

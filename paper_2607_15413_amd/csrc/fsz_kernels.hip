@@ -3457,10 +3457,15 @@ hipError_t launch_decompress_prezero(const DecompressArgs &a, bool out_aligned16
                          : launch_decompress_w<false, true, 8, false, true>(a, s);
 }
 
+// Waves per workgroup: FSZ_DEC_WAVES if set, else by the elements to decode:
+// 8 (64-tile chunks) for up to dec_wide_above, 16 above it, where the shorter
+// lookback chain of the larger chunks pays for their coarser spread.
 template <bool ALIGNED, bool STAGED>
 static hipError_t launch_decompress_t(const DecompressArgs &a, hipStream_t s)
 {
-    switch (tuning().dec_waves) {
+    const uint64_t elems = (a.tile_end - a.tile_begin) * kTile;
+    const int w = tuning().dec_waves ? tuning().dec_waves : (elems > tuning().dec_wide_above ? 16 : 8);
+    switch (w) {
     case 16: return launch_decompress_w<ALIGNED, STAGED, 16>(a, s);
     case 8: return launch_decompress_w<ALIGNED, STAGED, 8>(a, s);
     default: return launch_decompress_w<ALIGNED, STAGED, 4>(a, s);

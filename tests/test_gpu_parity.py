@@ -544,16 +544,17 @@ def test_bound_step_exact_cases():
 
 @pytest.mark.timeout(600)
 def test_decoder_regimes_and_corrupt_streams():
-    """Whole-field decodes use the lookback decoder for small fields and the
-    offsets pre-pass (one chunk per workgroup, or the persistent grid) for
-    larger ones: each regime decodes bit-exactly and reports corrupt streams
-    (reserved bits, sizes that disagree with the total, padding, header
-    fields, a mismatched n) with the oracle's status."""
+    """Whole-field decodes use the lookback decoder for small fields (8-wave
+    chunks up to 2^21 elements, 16-wave ones above) and the offsets pre-pass
+    (one chunk per workgroup, or the persistent grid) for larger ones: each
+    regime decodes bit-exactly and reports corrupt streams (reserved bits,
+    sizes that disagree with the total, padding, header fields, a mismatched
+    n) with the oracle's status."""
     from tests.test_oracle import _mutations
 
     old = oracle.set_threads(8)
     try:
-        for n in (1000, (1 << 22) + 77, (1 << 26) + 5):
+        for n in (1000, (3 << 20) + 5, (1 << 23) + 77, (1 << 26) + 5):
             x = workloads.sinusoid_field(n, 17)
             s = oracle.compress(x, oracle.REL, 1e-4)
             announce(f"decoder regime n={n}: clean stream")
