@@ -245,8 +245,9 @@ fsz_status fsz_compress_five_read_async(const float *d_in, size_t n, fsz_eb_mode
  * lane per 32 elements; compression of a 16-byte aligned input by the
  * pipelined persistent kernel of the default path (chunks of 16384
  * elements), other inputs one chunk of 32768 elements per workgroup;
- * decompression one chunk of 8192 elements per workgroup, its offset from a
- * pre-pass over the rate header for fields of 2^22 elements or more.
+ * decompression one chunk of 8192 elements per workgroup (32768 in the
+ * lookback form of fields above 2^21 elements), its offset from a pre-pass
+ * over the rate header for fields of 2^23 elements or more.
  *
  * fsz_compressed_bound_config: worst-case stream size (every block at rate
  *   31); 0 for an unsupported configuration.

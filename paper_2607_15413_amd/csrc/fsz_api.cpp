@@ -334,7 +334,8 @@ bool auto_prezero(uint64_t n, uint64_t cmp_size)
 
 // Tile configurations (Sec. VI-C, Table V): the generic lane-per-segment
 // kernels, one chunk of kCfgChunkSegs 32-element segments per workgroup
-// (decoder: kCfgDecChunkSegs).
+// (decoder: 64 x kCfgDecWaves, or 64 x kCfgDecWideWaves in the lookback form
+// of fields above dec_wide_above elements).
 fsz_status enqueue_compress_config(Workspace *ws, const float *d_in, uint64_t n, int mode, double value,
                                    const fsz_stats *d_stats, int block, int tile_blocks, void *d_out, uint64_t cap,
                                    fsz_result *d_final)
@@ -379,7 +380,9 @@ fsz_status enqueue_decompress_config(Workspace *ws, const void *d_cmp, uint64_t 
     a.n = n;
     a.ntiles = ceil_div(n, (uint64_t)block * tile_blocks);
     a.nblocks = ceil_div(n, (uint64_t)block);
-    a.nchunks = n ? ceil_div(ceil_div(n, kBlock), kCfgDecChunkSegs) : 1;
+    const bool prescan = tuning().dec_prescan && n >= tuning().cfg_dec_lookback_below;
+    const uint64_t chunk_segs = 64ull * (uint64_t)(prescan ? kCfgDecWaves : cfg_dec_lookback_waves(n));
+    a.nchunks = n ? ceil_div(ceil_div(n, kBlock), chunk_segs) : 1;
     a.data0 = kHeaderBytes + pad16(a.nblocks);
     a.tile_begin = 0;
     a.tile_end = a.ntiles;
@@ -393,7 +396,7 @@ fsz_status enqueue_decompress_config(Workspace *ws, const void *d_cmp, uint64_t 
     a.ticket = ws->d_ticket;
     a.final = d_final;
     hipError_t e;
-    if (tuning().dec_prescan && n >= tuning().cfg_dec_lookback_below) {
+    if (prescan) {
         // chunk offsets from the rate header first, as for the default format
         if (!grow(&ws->d_offs, &ws->offs_cap, a.nchunks, ws->stream)) return FSZ_ERR_DEVICE;
         a.offsets = ws->d_offs;

@@ -189,8 +189,10 @@ constexpr int kCfgWaves = 16;
 constexpr int kCfgChunkSegs = kCfgWaves * 64;
 constexpr int kCfgPipeChunkSegs = 8 * 64;  // the pipelined configuration compressor's chunk
 // the configuration decoder: workgroups of 4 waves, one chunk of 4 x 64 segments each
+// (the lookback form of fields above dec_wide_above elements: 16 waves)
 constexpr int kCfgDecWaves = 4;
 constexpr int kCfgDecChunkSegs = kCfgDecWaves * 64;
+constexpr int kCfgDecWideWaves = 16;
 // header flags bits 2-4 of a tile configuration (0 for B 32, T 8)
 inline uint32_t cfg_flag_bits(int block, int tile_blocks)
 {
@@ -255,13 +257,18 @@ struct Tuning {
                                 // 8 / 7 data waves and a control wave (compress_ctrl_kernel)
     int dec_waves = 0;          // waves per workgroup of the lookback decoder (4, 8, 16; 0: by size)
     uint64_t dec_wide_above = 1ull << 21;  // by size: 16 waves above this many decoded elements, else 8
+                                           // (tile configurations: 16, else 4)
     int grid_factor = 1;
     double prezero_min_cr = 0.0;  // whole-field decodes pre-zero above this CR (0: never)
     bool dec_prescan = true;      // whole-field decodes take chunk offsets from a pre-pass (no lookback)
     uint64_t dec_lookback_below = 1ull << 23;      // ... except fields below this many elements (one launch)
-    uint64_t cfg_dec_lookback_below = 1ull << 22;  // the same for the tile configurations
+    uint64_t cfg_dec_lookback_below = 1ull << 23;  // the same for the tile configurations
     uint64_t dec_direct_below = 1ull << 26;    // pre-pass decodes below this size: one chunk per workgroup
 };
 const Tuning &tuning();
+
+// Waves per workgroup of the configuration decoder's lookback form for an
+// n-element field (the pre-pass form always takes kCfgDecWaves).
+inline int cfg_dec_lookback_waves(uint64_t n) { return n > tuning().dec_wide_above ? kCfgDecWideWaves : kCfgDecWaves; }
 
 }  // namespace fsz

@@ -3174,7 +3174,8 @@ __global__ __launch_bounds__(kCfgWaves * 64) void compress_cfg_kernel(CompressAr
 
 // WV waves per workgroup, chunks of 64 WV segments (4 waves: a wider grid,
 // which small fields need, and several workgroups per CU to hide the lookback
-// and the tile loads).  PRESCAN: the chunk offsets come from
+// and the tile loads; 16 in the lookback form of fields above 2^21 elements,
+// whose chain the larger chunks halve twice).  PRESCAN: the chunk offsets come from
 // dec_offsets_single_kernel<64 WV / L, L / HB, HB> (which also checked the
 // stream and reported its outcome): chunk = workgroup, no lookback.
 template <bool ALIGNED, int HB, int L, bool PRESCAN = false, int WV = kCfgDecWaves>
@@ -3599,21 +3600,30 @@ static hipError_t launch_compress_cfg_t(const CompressArgs &a, int block, int ti
     return hipGetLastError();
 }
 
-template <bool ALIGNED>
-static hipError_t launch_decompress_cfg_t(const DecompressArgs &a, int block, int tile_blocks, hipStream_t s)
+template <bool ALIGNED, int WV>
+static hipError_t launch_decompress_cfg_w(const DecompressArgs &a, int block, int tile_blocks, hipStream_t s)
 {
-    const dim3 grid((unsigned)a.nchunks), threads(kCfgDecWaves * 64);
+    const dim3 grid((unsigned)a.nchunks), threads(WV * 64);
     const int key = block * 100 + tile_blocks;
     switch (key) {
-    case 3204: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 4>), grid, threads, 0, s, a); break;
-    case 3208: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 8>), grid, threads, 0, s, a); break;
-    case 3216: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 16>), grid, threads, 0, s, a); break;
-    case 6404: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 8>), grid, threads, 0, s, a); break;
-    case 6408: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 16>), grid, threads, 0, s, a); break;
-    case 6416: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 32>), grid, threads, 0, s, a); break;
+    case 3204: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 4, false, WV>), grid, threads, 0, s, a); break;
+    case 3208: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 8, false, WV>), grid, threads, 0, s, a); break;
+    case 3216: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 1, 16, false, WV>), grid, threads, 0, s, a); break;
+    case 6404: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 8, false, WV>), grid, threads, 0, s, a); break;
+    case 6408: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 16, false, WV>), grid, threads, 0, s, a); break;
+    case 6416: hipLaunchKernelGGL((decompress_cfg_kernel<ALIGNED, 2, 32, false, WV>), grid, threads, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Lookback form: a.nchunks counts chunks of 64 cfg_dec_lookback_waves(n) segments.
+template <bool ALIGNED>
+static hipError_t launch_decompress_cfg_t(const DecompressArgs &a, int block, int tile_blocks, hipStream_t s)
+{
+    return cfg_dec_lookback_waves(a.n) == kCfgDecWideWaves
+               ? launch_decompress_cfg_w<ALIGNED, kCfgDecWideWaves>(a, block, tile_blocks, s)
+               : launch_decompress_cfg_w<ALIGNED, kCfgDecWaves>(a, block, tile_blocks, s);
 }
 
 // Pipelined form (16-byte aligned input): persistent workgroups of 8 data

@@ -291,19 +291,20 @@ def test_config_errors_match_oracle():
             assert gpu_decompress_config(bytes(c), n, config)[0] == oracle.ERR_CORRUPT
 
 
+@pytest.mark.parametrize("n", [(3 << 20) + 5, (1 << 23) + 77])
 @pytest.mark.parametrize("config", [(32, 4), (64, 8), (64, 16)])
-def test_config_prepass_decoder_and_corrupt_streams(config):
-    """Fields of 2^22 elements and more decode with chunk offsets from a
-    pre-pass over the rate header: bit-exact decoding, and the oracle's
-    status for corrupt streams (header fields, reserved rate bits, a rate
-    that no longer matches the sizes, padding, a stream cut short)."""
+def test_config_prepass_decoder_and_corrupt_streams(config, n):
+    """Fields above 2^21 elements decode in 16-wave lookback chunks, fields of
+    2^23 elements and more with chunk offsets from a pre-pass over the rate
+    header: bit-exact decoding, and the oracle's status for corrupt streams
+    (header fields, reserved rate bits, a rate that no longer matches the
+    sizes, padding, a stream cut short)."""
     B, T = config
     old = oracle.set_threads(8)
     try:
-        n = (1 << 22) + 77
         x = workloads.sinusoid_field(n, 21)
         s = oracle.compress(x, oracle.REL, 1e-4, config=config)
-        announce(f"config {config} pre-pass decode n={n}: clean stream")
+        announce(f"config {config} large-field decode n={n}: clean stream")
         st, y = gpu_decompress_config(s, n, config)
         assert st == fsz.FSZ_OK
         assert np.array_equal(y.view(np.uint32), oracle.decompress(s, n).view(np.uint32))
@@ -325,13 +326,13 @@ def test_config_prepass_decoder_and_corrupt_streams(config):
         if d0 > 32 + nb:
             cases["padding"] = lambda c: c.__setitem__(32 + nb, 1)
         for name, f in cases.items():
-            announce(f"config {config} pre-pass decode n={n}: {name}")
+            announce(f"config {config} large-field decode n={n}: {name}")
             c = bytearray(s)
             f(c)
             want = oracle.decompress_status(bytes(c), n)[0]
             assert want != oracle.OK, name
             assert gpu_decompress_config(bytes(c), n, config)[0] == want, name
-        announce(f"config {config} pre-pass decode n={n}: stream cut short")
+        announce(f"config {config} large-field decode n={n}: stream cut short")
         assert gpu_decompress_config(s[:-4], n, config)[0] == oracle.decompress_status(s[:-4], n)[0]
     finally:
         oracle.set_threads(old)
