@@ -3574,9 +3574,13 @@ hipError_t launch_range_base(const DecompressArgs &a, unsigned long long *range_
 
 hipError_t launch_decompress(const DecompressArgs &a, bool out_aligned16, bool staged, hipStream_t s)
 {
-    if (a.range_base)  // random access: the staged 8-wave decoder with range bookkeeping
+    if (a.range_base) {  // random access: the staged decoder with range bookkeeping, 16 waves for long ranges
+        if ((a.tile_end - a.tile_begin) * kTile > tuning().dec_wide_above)
+            return out_aligned16 ? launch_decompress_w<true, true, 16, true>(a, s)
+                                 : launch_decompress_w<false, true, 16, true>(a, s);
         return out_aligned16 ? launch_decompress_w<true, true, 8, true>(a, s)
                              : launch_decompress_w<false, true, 8, true>(a, s);
+    }
     if (out_aligned16)
         return staged ? launch_decompress_t<true, true>(a, s) : launch_decompress_t<true, false>(a, s);
     return staged ? launch_decompress_t<false, true>(a, s) : launch_decompress_t<false, false>(a, s);

@@ -63,6 +63,22 @@ def test_range_decode_matches_whole_field(features):
                 assert np.array_equal(y.view(np.uint32), full[begin:end].view(np.uint32)), (begin, end)
 
 
+def test_long_range_decode_matches_whole_field():
+    """Ranges of more than 2^21 elements decode in 16-wave chunks: bit-exact
+    against the oracle's whole-field decode, ragged ends and an odd output
+    offset included."""
+    n = (1 << 22) + 333
+    x = workloads.sinusoid_field(n, 8)
+    s = oracle.compress(x, oracle.REL, 1e-4)
+    full = oracle.decompress(s, n)
+    for begin, end in ((0, n), (1000, (3 << 20) + 17), (n - (5 << 19) - 9, n)):
+        for off in (0, 1):
+            announce(f"long range n={n} [{begin}, {end}) output offset {off}")
+            st, y = gpu_decompress_range(s, n, begin, end, out_offset=off)
+            assert st == fsz.FSZ_OK
+            assert np.array_equal(y.view(np.uint32), full[begin:end].view(np.uint32)), (begin, end)
+
+
 def test_range_decode_errors():
     x = workloads.sinusoid_field(100000, 5)
     n = x.size
