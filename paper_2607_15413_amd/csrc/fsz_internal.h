@@ -237,8 +237,10 @@ bool reserve_batch(hipStream_t stream, uint64_t jobs, uint64_t chunks, uint64_t 
 // compress input through LDS), FSZ_PIPE (0: no pipelined persistent
 // compression for 16-byte aligned inputs), FSZ_PIPE_WAVES (its waves per
 // workgroup: 1, 2, 4 or 8), FSZ_DEC_WAVES (waves per workgroup of the
-// lookback decoder: 4, 8 or 16, for every size), FSZ_DEC_WIDE_ABOVE (without
-// FSZ_DEC_WAVES: 16 waves above this many decoded elements, 8 up to it),
+// default format's whole-field lookback decoder: 4, 8 or 16, for every size),
+// FSZ_DEC_WIDE_ABOVE (16-wave chunks above this many decoded elements, else 8,
+// for that decoder without FSZ_DEC_WAVES and for random access; for the tile
+// configurations' lookback form 16, else 4),
 // FSZ_DEC_LOOKBACK_BELOW and FSZ_CFG_DEC_LOOKBACK_BELOW (whole-field decodes of
 // the default format / the tile configurations below this many elements use
 // the lookback decoder, larger ones the offsets pre-pass), FSZ_DEC_DIRECT_BELOW
